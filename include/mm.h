@@ -1,0 +1,199 @@
+/*
+ * mm.h -- C ABI of the MI355X (gfx950) micro-macro KFVS solver for the
+ * Boltzmann-BGK (1D1V) and Boltzmann-ES-BGK (2D2V) equations of
+ * J.A. Rossmanith and P. Sar, "Micro-macro kinetic flux-vector splitting
+ * schemes for the multidimensional Boltzmann-ES-BGK equation",
+ * arXiv:2509.21832.
+ *
+ * One time step is the paper's micro step followed by its macro step:
+ *   2D (Sec. 5.3-5.4): G^n -x-transport-> G* -y-transport-> G**
+ *       -backward-Euler relaxation to G-hat (eqn5-97, eqn5-98)-> G^{n+1};
+ *       H^{n+1} = eps dv sum w^3 G^{n+1} (eqn5-99);
+ *       Q^n -TR-BDF2 half step-> Q* -KFVS x + dH/dx-> Q** -KFVS y + dH/dy->
+ *       Q*** -TR-BDF2 half step-> Q^{n+1} (macro2d-split1..4, eqn5-103).
+ *   1D (Sec. 3.3-3.4): eqn5-19 .. eqn5-25 (micro), eqn5-26, eqn5-27 (macro).
+ * Every step runs on the GPU; the host only enqueues kernels.
+ *
+ * Conventions shared by all entry points
+ *   - Status codes: every function returns an mm_status; nothing throws or
+ *     aborts across this ABI.  mm_strerror() names a code.
+ *   - Host buffers are owned by the caller and are not retained after the
+ *     call returns.  Device memory and the context are owned by the library
+ *     and released by mm_free().
+ *   - Layouts (C order, FP64 on the host side):
+ *       Q  [ny][nx][ncomp]      ncomp = 6 in 2D: (rho, rho u1, rho u2, E11, E12, E22),
+ *                                E = rho u (x) u + P (Sec. 5.2); ncomp = 3 in 1D:
+ *                                (rho, rho u, E), E = rho T/2 + rho u^2/2 (eq5-11).
+ *       G  [ny][nx][nv2][nv1]   micro part g at the phase-space nodes, v1 fastest
+ *                                (1D: [nx][nv1]).
+ *       H  [ny][nx][4]          heat-flux tensor (H111, H112, H122, H222) (eqn5-99);
+ *                                1D: [nx][1], H = (eps/2) dv sum v^3 G (eqn5-26).
+ *   - One context is used by one host thread at a time; contexts are
+ *     independent.  The library holds no global state.
+ */
+#ifndef MM_H
+#define MM_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mm_ctx mm_ctx;
+
+enum mm_status {
+    MM_OK = 0,
+    MM_EINVAL = 1,     /* invalid configuration or argument                    */
+    MM_ENOMEM = 2,     /* device or host allocation failed                     */
+    MM_EDEVICE = 3,    /* a HIP runtime call failed                            */
+    MM_ENONPHYS = 4,   /* rho <= 0, T <= 0, det(calT) <= 0 or a non-finite value */
+    MM_ESTATE = 5      /* the context is unusable (an earlier device error)     */
+};
+
+/* boundary kinds of one side of the spatial box */
+enum {
+    MM_BC_EXTRAP = 0,    /* constant extrapolation ("outflow"), Sec. 5.3.1 / 5.4.1   */
+    MM_BC_PERIODIC = 1,  /* periodic, Sec. 5.3.2 / 5.4.2 (both sides of an axis)    */
+    MM_BC_WALL = 2,      /* diffusely reflecting wall at T_wall, moving tangentially
+                            with u_wall (the lid), Sec. 6.3                          */
+    MM_BC_INFLOW = 3     /* fixed ghost Maxwellian (rho, u1, u2, T) entering the box;
+                            wall machinery otherwise (g = 0 ghosts, H ghost = 0)     */
+};
+
+/* collision parameter tau(rho, p, T) */
+enum {
+    MM_TAU_RHO = 0,      /* tau = coef * rho   (coef = 3 C25 pi/(2 sqrt 2), eqn:tau-for-2d-es-bgk) */
+    MM_TAU_P = 1,        /* tau = coef * p     (eqn:collision_parameter_1d_p)                    */
+    MM_TAU_HS1D = 2,     /* tau = coef * sqrt(T/(2 pi)) (coef = 16/5, eqn:collision_parameter_1d) */
+    MM_TAU_CONST = 3     /* tau = coef                                                          */
+};
+
+/* projector onto the null space of the collision operator */
+enum {
+    MM_PROJ_DISCRETE = 0,  /* orthogonal projector of the midpoint quadrature (discrete
+                              Gram matrix); also applied to G-hat.  Default.          */
+    MM_PROJ_PAPER = 1      /* the continuous normalisation 1/rho of (coeffs-2D-xdir)
+                              with midpoint sums, verbatim                           */
+};
+
+/* time-step rule: dt = cfl * min(dx/V1, dy/V2) (CFL-2D-part1) or
+ * dt = cfl / (V1/dx + V2/dy) (the rule the printed cylindrical run follows) */
+enum { MM_CFL_MIN = 0, MM_CFL_SUM = 1 };
+
+/* arithmetic of the phase-space pass */
+enum {
+    MM_FP64 = 0,    /* everything FP64                                               */
+    MM_MIXED = 1,   /* g stored and transported in FP32; velocity reductions, cell
+                       coefficients, Gaussian / pressure-tensor algebra and the macro
+                       update in FP64                                                 */
+    MM_CLOSURE = 2  /* MM_MIXED plus the learned closure in near-continuum cells     */
+};
+
+/* one side of the box: 0 = x_lo, 1 = x_hi, 2 = y_lo, 3 = y_hi */
+typedef struct {
+    int kind;
+    double T_wall;          /* MM_BC_WALL: wall temperature (> 0)                 */
+    double u_wall;          /* MM_BC_WALL: wall speed tangential to the side      */
+    double rho, u1, u2, T;  /* MM_BC_INFLOW: ghost state                          */
+} mm_bc;
+
+typedef struct {
+    int dim;                          /* 1 (1D1V) or 2 (2D2V)                       */
+    int nx, ny, nv1, nv2;             /* cells / velocity nodes; ny = nv2 = 1 in 1D  */
+    double x_lo, x_hi, y_lo, y_hi;    /* spatial box (cell-centred uniform grid)    */
+    double v1_lo, v1_hi, v2_lo, v2_hi;/* velocity box (midpoint nodes)              */
+    double eps;                       /* Knudsen number, > 0                        */
+    double cfl;                       /* > 0                                        */
+    int cfl_rule;                     /* MM_CFL_MIN | MM_CFL_SUM                    */
+    double nu;                        /* ES-BGK parameter, -1 <= nu < 1 (2D); unused in 1D */
+    int tau_model;                    /* MM_TAU_*                                   */
+    double tau_coef;
+    mm_bc bc[4];
+    int proj_mode;                    /* MM_PROJ_*                                  */
+    int wall_es_term;                 /* keep (G - M)/eps in wall-cell G-hat (1 = yes) */
+    double dt;                        /* > 0: use this dt instead of the CFL rule   */
+    int precision;                    /* MM_FP64 | MM_MIXED | MM_CLOSURE            */
+    int device;                       /* HIP device ordinal                         */
+    void *stream;                     /* hipStream_t to enqueue on; NULL: the library
+                                         creates its own (default-priority) stream  */
+} mm_config;
+
+/*
+ * mm_init -- validate cfg, allocate device state, upload the initial data.
+ *   q0: host Q^0 (layout above), required.
+ *   g0: host G^0 (layout above) or NULL for g = 0, the paper's initial
+ *       condition in every example.
+ *   *out receives the context, or NULL on failure (nothing leaks).
+ * Errors: MM_EINVAL (bad sizes, eps <= 0, cfl <= 0, nu outside [-1, 1) in 2D,
+ * unpaired periodic sides, walls in 1D, T_wall <= 0), MM_ENONPHYS (Q^0 not
+ * physical), MM_ENOMEM, MM_EDEVICE.
+ */
+int mm_init(const mm_config *cfg, const double *q0, const double *g0, mm_ctx **out);
+
+/*
+ * mm_step -- advance nsteps fixed-dt steps, then wait for the GPU once.
+ * Returns MM_ENONPHYS if some step produced a non-physical macro state
+ * (mm_failed_step() gives the first such step, counted from the start of the
+ * run); the state then holds the result of the last step enqueued.
+ */
+int mm_step(mm_ctx *ctx, int nsteps);
+
+/* mm_step_async -- enqueue nsteps steps on the context's stream and return
+ * without waiting; the non-physical check happens at the next mm_sync(). */
+int mm_step_async(mm_ctx *ctx, int nsteps);
+
+/* mm_sync -- wait for the stream; returns MM_ENONPHYS as mm_step would. */
+int mm_sync(mm_ctx *ctx);
+
+/*
+ * mm_moments -- wait for the stream and copy the macro state out.
+ *   q_out  host Q (required)            [ny][nx][ncomp]
+ *   h_out  host H of the last step or NULL  [ny][nx][4] (1D: [nx])
+ *   gmom_out host g-moments or NULL     [ny][nx][7] (2D only):
+ *          dv sum (1, v1, v2, |v|^2/2) G (zero up to round-off with the discrete
+ *          projector), then eps dv sum (w1^2 - w2^2, 2 w1 w2, |w|^2) G / 2
+ *          (stress deviation and trace of the micro part)
+ */
+int mm_moments(mm_ctx *ctx, double *q_out, double *h_out, double *gmom_out);
+
+/* mm_get_g -- copy G out as FP64 (host [ny][nx][nv2][nv1]). */
+int mm_get_g(mm_ctx *ctx, double *g_out);
+
+/* mm_set_state -- replace Q (required) and G (NULL: zero) with host data;
+ * together with mm_moments/mm_get_g this is checkpoint / restart. */
+int mm_set_state(mm_ctx *ctx, const double *q, const double *g);
+
+/* mm_free -- release the context; mm_free(NULL) does nothing. */
+void mm_free(mm_ctx *ctx);
+
+/* mm_dt -- the time step cfg implies (cfg->dt if > 0, else the CFL rule).
+ * With t_final > 0 the reset rule of Sec. 3.2 / (CFL-2D-part1) is applied:
+ * N = ceil(t_final / dt), dt = t_final / N, and *nsteps (if not NULL) gets N.
+ * Returns a negative value for an invalid configuration. */
+double mm_dt(const mm_config *cfg, double t_final, int *nsteps);
+
+/* mm_failed_step -- first step whose macro state was non-physical, or -1. */
+int mm_failed_step(const mm_ctx *ctx);
+
+/* mm_strerror -- static text for a status code. */
+const char *mm_strerror(int status);
+
+/*
+ * Kernel timing (HIP events on the context's stream around every launch of
+ * the phase-space pass).  mm_timing(ctx, 1) enables and resets the counters;
+ * mm_timing_get() returns the number of timed launches and their summed
+ * duration in milliseconds for kernel class `which`:
+ *   0 = phase-space (micro) pass, 1 = per-cell preparation, 2 = macro sweeps.
+ */
+int mm_timing(mm_ctx *ctx, int enable);
+int mm_timing_get(mm_ctx *ctx, int which, int *count, double *total_ms);
+
+/* mm_device_ptrs -- device addresses of the current Q, G and H buffers (for
+ * zero-copy interop, e.g. wrapping them as torch tensors).  G is FP64 or FP32
+ * according to cfg->precision; *g_bytes receives its element size. */
+int mm_device_ptrs(mm_ctx *ctx, void **q, void **g, void **h, int *g_bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MM_H */

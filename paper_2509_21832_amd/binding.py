@@ -1,0 +1,228 @@
+"""ctypes binding of libmm.so (the C ABI in include/mm.h).
+
+Argument marshalling only: every step of the scheme runs in the library's HIP
+kernels.  There is no fallback: if libmm.so is missing or fails to load, the
+import of this module raises.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmm.so")
+
+MM_OK, MM_EINVAL, MM_ENOMEM, MM_EDEVICE, MM_ENONPHYS, MM_ESTATE = range(6)
+BC = {"extrap": 0, "periodic": 1, "wall": 2, "inflow": 3}
+TAU = {"rho": 0, "p": 1, "hs1d": 2, "const": 3}
+PROJ = {"discrete": 0, "paper": 1}
+CFL = {"min": 0, "sum": 1}
+PRECISION = {"fp64": 0, "mixed": 1, "closure": 2}
+
+# every entry point declared in include/mm.h
+EXPORTS = ("mm_init", "mm_step", "mm_step_async", "mm_sync", "mm_moments", "mm_get_g", "mm_set_state",
+           "mm_free", "mm_dt", "mm_failed_step", "mm_strerror", "mm_timing", "mm_timing_get", "mm_device_ptrs")
+
+
+class MMError(RuntimeError):
+    def __init__(self, code, what):
+        super().__init__(f"{what}: {_lib.mm_strerror(code).decode()} (status {code})")
+        self.code = code
+
+
+class NonPhysical(MMError):
+    pass
+
+
+class mm_bc(C.Structure):
+    _fields_ = [("kind", C.c_int), ("T_wall", C.c_double), ("u_wall", C.c_double),
+                ("rho", C.c_double), ("u1", C.c_double), ("u2", C.c_double), ("T", C.c_double)]
+
+
+class mm_config(C.Structure):
+    _fields_ = [("dim", C.c_int), ("nx", C.c_int), ("ny", C.c_int), ("nv1", C.c_int), ("nv2", C.c_int),
+                ("x_lo", C.c_double), ("x_hi", C.c_double), ("y_lo", C.c_double), ("y_hi", C.c_double),
+                ("v1_lo", C.c_double), ("v1_hi", C.c_double), ("v2_lo", C.c_double), ("v2_hi", C.c_double),
+                ("eps", C.c_double), ("cfl", C.c_double), ("cfl_rule", C.c_int), ("nu", C.c_double),
+                ("tau_model", C.c_int), ("tau_coef", C.c_double), ("bc", mm_bc * 4),
+                ("proj_mode", C.c_int), ("wall_es_term", C.c_int), ("dt", C.c_double),
+                ("precision", C.c_int), ("device", C.c_int), ("stream", C.c_void_p)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                          "(hipcc --offload-arch=gfx950); there is no CPU fallback")
+    L = C.CDLL(LIB_PATH)
+    dp = C.POINTER(C.c_double)
+    vp = C.c_void_p
+    cp = C.POINTER(mm_config)
+    L.mm_init.argtypes = [cp, dp, dp, C.POINTER(vp)]
+    L.mm_step.argtypes = [vp, C.c_int]
+    L.mm_step_async.argtypes = [vp, C.c_int]
+    L.mm_sync.argtypes = [vp]
+    L.mm_moments.argtypes = [vp, dp, dp, dp]
+    L.mm_get_g.argtypes = [vp, dp]
+    L.mm_set_state.argtypes = [vp, dp, dp]
+    L.mm_free.argtypes = [vp]
+    L.mm_free.restype = None
+    L.mm_dt.argtypes = [cp, C.c_double, C.POINTER(C.c_int)]
+    L.mm_dt.restype = C.c_double
+    L.mm_failed_step.argtypes = [vp]
+    L.mm_strerror.argtypes = [C.c_int]
+    L.mm_strerror.restype = C.c_char_p
+    L.mm_timing.argtypes = [vp, C.c_int]
+    L.mm_timing_get.argtypes = [vp, C.c_int, C.POINTER(C.c_int), dp]
+    L.mm_device_ptrs.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), C.POINTER(C.c_int)]
+    for name in EXPORTS:
+        getattr(L, name)
+    return L
+
+
+_lib = _load()
+
+
+def lib():
+    return _lib
+
+
+def config(p, stream=None, device=0):
+    """mm_config from a problem dictionary (see mm_workloads)."""
+    c = mm_config()
+    c.dim = p["dim"]
+    c.nx, c.ny = p["nx"], p.get("ny", 1)
+    c.nv1, c.nv2 = p["nv1"], p.get("nv2", 1)
+    c.x_lo, c.x_hi = p["x"]
+    c.y_lo, c.y_hi = p.get("y", (0.0, 1.0))
+    c.v1_lo, c.v1_hi = p["v1"]
+    c.v2_lo, c.v2_hi = p.get("v2", (0.0, 1.0))
+    c.eps, c.cfl = p["eps"], p["cfl"]
+    c.cfl_rule = CFL[p.get("cfl_rule", "min")]
+    c.nu = p.get("nu", 0.0)
+    c.tau_model = TAU[p["tau_model"]]
+    c.tau_coef = p["tau_coef"]
+    for s, b in enumerate(p["bc"]):
+        c.bc[s].kind = BC[b["kind"]]
+        c.bc[s].T_wall = b.get("T_wall", 1.0)
+        c.bc[s].u_wall = b.get("u_wall", 0.0)
+        c.bc[s].rho = b.get("rho", 1.0)
+        c.bc[s].u1 = b.get("u1", 0.0)
+        c.bc[s].u2 = b.get("u2", 0.0)
+        c.bc[s].T = b.get("T", 1.0)
+    c.proj_mode = PROJ[p.get("proj_mode", "discrete")]
+    c.wall_es_term = 1 if p.get("wall_es_term", True) else 0
+    c.dt = p.get("dt", 0.0)
+    c.precision = PRECISION[p.get("precision", "fp64")]
+    c.device = device
+    c.stream = stream
+    return c
+
+
+def _dp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double)) if a is not None else None
+
+
+def _check(rc, what):
+    if rc == MM_ENONPHYS:
+        raise NonPhysical(rc, what)
+    if rc != MM_OK:
+        raise MMError(rc, what)
+
+
+def dt(p, t_final=0.0):
+    n = C.c_int(0)
+    d = _lib.mm_dt(C.byref(config(p)), float(t_final), C.byref(n))
+    if d < 0:
+        raise MMError(MM_EINVAL, "mm_dt")
+    return d, n.value
+
+
+class Solver:
+    """One mm_ctx: Q, G and H live in device memory owned by the library."""
+
+    def __init__(self, p, Q0, G0=None, stream=None, device=0):
+        self.p = dict(p)
+        self.ncell = p["nx"] * p.get("ny", 1)
+        self.nv = p["nv1"] * p.get("nv2", 1)
+        self.ncomp = 6 if p["dim"] == 2 else 3
+        q = np.ascontiguousarray(Q0, dtype=np.float64).reshape(-1)
+        if q.size != self.ncell * self.ncomp:
+            raise ValueError("Q0 has the wrong size")
+        g = None
+        if G0 is not None:
+            g = np.ascontiguousarray(G0, dtype=np.float64).reshape(-1)
+            if g.size != self.ncell * self.nv:
+                raise ValueError("G0 has the wrong size")
+        self._cfg = config(p, stream, device)
+        self._ctx = C.c_void_p()
+        _check(_lib.mm_init(C.byref(self._cfg), _dp(q), _dp(g), C.byref(self._ctx)), "mm_init")
+
+    def close(self):
+        if self._ctx:
+            _lib.mm_free(self._ctx)
+            self._ctx = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    @property
+    def dt(self):
+        return _lib.mm_dt(C.byref(self._cfg), 0.0, None)
+
+    def step(self, n=1):
+        _check(_lib.mm_step(self._ctx, int(n)), "mm_step")
+
+    def step_async(self, n=1):
+        _check(_lib.mm_step_async(self._ctx, int(n)), "mm_step_async")
+
+    def sync(self):
+        _check(_lib.mm_sync(self._ctx), "mm_sync")
+
+    def failed_step(self):
+        return _lib.mm_failed_step(self._ctx)
+
+    def moments(self, with_h=False, with_gmom=False):
+        Q = np.empty(self.ncell * self.ncomp)
+        H = np.empty(self.ncell * (4 if self.ncomp == 6 else 1)) if with_h else None
+        M = np.empty(self.ncell * 7) if with_gmom else None
+        _check(_lib.mm_moments(self._ctx, _dp(Q), _dp(H), _dp(M)), "mm_moments")
+        out = [Q]
+        if with_h:
+            out.append(H)
+        if with_gmom:
+            out.append(M)
+        return out[0] if len(out) == 1 else tuple(out)
+
+    def get_g(self):
+        G = np.empty(self.ncell * self.nv)
+        _check(_lib.mm_get_g(self._ctx, _dp(G)), "mm_get_g")
+        return G
+
+    def set_state(self, Q, G=None):
+        q = np.ascontiguousarray(Q, dtype=np.float64).reshape(-1)
+        g = None if G is None else np.ascontiguousarray(G, dtype=np.float64).reshape(-1)
+        _check(_lib.mm_set_state(self._ctx, _dp(q), _dp(g)), "mm_set_state")
+
+    def timing(self, enable=True):
+        _check(_lib.mm_timing(self._ctx, 1 if enable else 0), "mm_timing")
+
+    def timing_get(self, which=0):
+        n = C.c_int(0)
+        ms = C.c_double(0.0)
+        _check(_lib.mm_timing_get(self._ctx, int(which), C.byref(n), C.byref(ms)), "mm_timing_get")
+        return n.value, ms.value
+
+    def device_ptrs(self):
+        q, g, h = C.c_void_p(), C.c_void_p(), C.c_void_p()
+        gb = C.c_int(0)
+        _check(_lib.mm_device_ptrs(self._ctx, C.byref(q), C.byref(g), C.byref(h), C.byref(gb)), "mm_device_ptrs")
+        return q.value, g.value, h.value, gb.value

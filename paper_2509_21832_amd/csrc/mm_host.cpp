@@ -1,0 +1,494 @@
+// mm_host.cpp -- implementation of the C ABI declared in include/mm.h:
+// configuration checks, device buffers, the per-step launch sequence and
+// kernel timing.  No arithmetic of the scheme runs here.
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/mm.h"
+#include "mm_launch.h"
+
+namespace {
+
+struct TimedLaunch {
+    int which;
+    hipEvent_t a, b;
+};
+
+} // namespace
+
+struct mm_ctx {
+    mm_config cfg;
+    mm::Params P;
+    int ncell = 0, nv = 0, ncomp = 0;
+    hipStream_t st = nullptr;
+    bool own_stream = false;
+    double *Q = nullptr, *Qs = nullptr, *H = nullptr, *rec = nullptr, *wrec = nullptr, *gmom = nullptr;
+    double *Gs = nullptr;          // G* scratch of the reference (unfused) 2D pass
+    void *G[2] = {nullptr, nullptr};
+    int gbytes = 8, cur = 0;
+    int *flag = nullptr;
+    int steps_done = 0, failed = -1;
+    bool fused = false, broken = false;
+    // timing
+    bool timing = false;
+    std::vector<TimedLaunch> pending;
+    std::vector<hipEvent_t> pool;
+    int tcount[3] = {0, 0, 0};
+    double tms[3] = {0.0, 0.0, 0.0};
+};
+
+namespace {
+
+#define HIP_TRY(x)                                     \
+    do {                                               \
+        if ((x) != hipSuccess) return MM_EDEVICE;      \
+    } while (0)
+
+int check_cfg(const mm_config *c)
+{
+    if (!c) return MM_EINVAL;
+    if (c->dim != 1 && c->dim != 2) return MM_EINVAL;
+    if (c->nx < 2 || c->nv1 < 2) return MM_EINVAL;
+    if (c->dim == 2 && (c->ny < 2 || c->nv2 < 2)) return MM_EINVAL;
+    if (!(c->x_hi > c->x_lo) || !(c->v1_hi > c->v1_lo)) return MM_EINVAL;
+    if (c->dim == 2 && (!(c->y_hi > c->y_lo) || !(c->v2_hi > c->v2_lo))) return MM_EINVAL;
+    if (!(c->eps > 0.0) || !std::isfinite(c->eps)) return MM_EINVAL;
+    if (!(c->dt > 0.0) && !(c->cfl > 0.0)) return MM_EINVAL;
+    if (c->dim == 2 && (!(c->nu >= -1.0) || !(c->nu < 1.0))) return MM_EINVAL;
+    if (c->tau_model < 0 || c->tau_model > 3 || !(c->tau_coef > 0.0)) return MM_EINVAL;
+    if (c->proj_mode != MM_PROJ_DISCRETE && c->proj_mode != MM_PROJ_PAPER) return MM_EINVAL;
+    if (c->precision < MM_FP64 || c->precision > MM_CLOSURE) return MM_EINVAL;
+    if (c->dim == 1 && c->precision != MM_FP64) return MM_EINVAL;
+    const int nside = c->dim == 2 ? 4 : 2;
+    for (int s = 0; s < nside; ++s) {
+        const mm_bc &b = c->bc[s];
+        if (b.kind < MM_BC_EXTRAP || b.kind > MM_BC_INFLOW) return MM_EINVAL;
+        if (c->dim == 1 && (b.kind == MM_BC_WALL || b.kind == MM_BC_INFLOW)) return MM_EINVAL;
+        if (b.kind == MM_BC_WALL && !(b.T_wall > 0.0)) return MM_EINVAL;
+        if (b.kind == MM_BC_INFLOW && (!(b.rho > 0.0) || !(b.T > 0.0))) return MM_EINVAL;
+    }
+    if ((c->bc[0].kind == MM_BC_PERIODIC) != (c->bc[1].kind == MM_BC_PERIODIC)) return MM_EINVAL;
+    if (c->dim == 2 && (c->bc[2].kind == MM_BC_PERIODIC) != (c->bc[3].kind == MM_BC_PERIODIC)) return MM_EINVAL;
+    const double pts = (double)c->nx * (c->dim == 2 ? c->ny : 1) * c->nv1 * (c->dim == 2 ? c->nv2 : 1);
+    if (pts > 4.0e10) return MM_EINVAL;
+    return MM_OK;
+}
+
+double dt_rule(const mm_config *c)
+{
+    const double V1 = std::fmax(std::fabs(c->v1_lo), std::fabs(c->v1_hi));
+    const double dx = (c->x_hi - c->x_lo) / c->nx;
+    if (c->dim == 1) return c->cfl * dx / V1;
+    const double V2 = std::fmax(std::fabs(c->v2_lo), std::fabs(c->v2_hi));
+    const double dy = (c->y_hi - c->y_lo) / c->ny;
+    if (c->cfl_rule == MM_CFL_SUM) return c->cfl / (V1 / dx + V2 / dy);
+    return c->cfl * std::fmin(dx / V1, dy / V2);
+}
+
+// host-side validation of a macro state given to the library
+bool state_ok(const mm_config *c, const double *q, int ncell)
+{
+    for (int i = 0; i < ncell; ++i) {
+        if (c->dim == 1) {
+            const double *s = q + 3 * (size_t)i;
+            const double rho = s[0], u = s[1] / rho, T = 2.0 * s[2] / rho - u * u;
+            if (!(rho > 0.0) || !(T > 0.0) || !std::isfinite(u)) return false;
+        } else {
+            const double *s = q + 6 * (size_t)i;
+            const double rho = s[0], u1 = s[1] / rho, u2 = s[2] / rho;
+            const double P11 = s[3] - s[1] * u1, P12 = s[4] - s[1] * u2, P22 = s[5] - s[2] * u2;
+            const double T = 0.5 * (P11 + P22) / rho;
+            const double S11 = (1.0 - c->nu) * T + c->nu * P11 / rho, S22 = (1.0 - c->nu) * T + c->nu * P22 / rho;
+            const double S12 = c->nu * P12 / rho;
+            if (!(rho > 0.0) || !(T > 0.0) || !(P11 > 0.0) || !(P22 > 0.0) || !(S11 * S22 - S12 * S12 > 0.0) ||
+                !std::isfinite(u1) || !std::isfinite(u2) || !std::isfinite(P12))
+                return false;
+        }
+    }
+    return true;
+}
+
+void release(mm_ctx *c)
+{
+    if (!c) return;
+    if (c->st) hipStreamSynchronize(c->st);
+    for (auto &t : c->pending) {
+        c->pool.push_back(t.a);
+        c->pool.push_back(t.b);
+    }
+    for (hipEvent_t e : c->pool) hipEventDestroy(e);
+    double *bufs[] = {c->Q, c->Qs, c->H, c->rec, c->wrec, c->gmom, c->Gs};
+    for (double *b : bufs)
+        if (b) hipFree(b);
+    for (void *g : c->G)
+        if (g) hipFree(g);
+    if (c->flag) hipFree(c->flag);
+    if (c->own_stream && c->st) hipStreamDestroy(c->st);
+    delete c;
+}
+
+int upload_state(mm_ctx *c, const double *q, const double *g)
+{
+    HIP_TRY(hipMemcpyAsync(c->Q, q, sizeof(double) * c->ncomp * c->ncell, hipMemcpyHostToDevice, c->st));
+    const size_t n = (size_t)c->ncell * c->nv;
+    if (!g) {
+        HIP_TRY(hipMemsetAsync(c->G[c->cur], 0, n * c->gbytes, c->st));
+    } else if (c->gbytes == 8) {
+        HIP_TRY(hipMemcpyAsync(c->G[c->cur], g, n * 8, hipMemcpyHostToDevice, c->st));
+    } else {
+        std::vector<float> tmp(n);
+        for (size_t i = 0; i < n; ++i) tmp[i] = (float)g[i];
+        HIP_TRY(hipMemcpyAsync(c->G[c->cur], tmp.data(), n * 4, hipMemcpyHostToDevice, c->st));
+        HIP_TRY(hipStreamSynchronize(c->st));
+    }
+    const int none = INT_MAX;
+    HIP_TRY(hipMemcpyAsync(c->flag, &none, sizeof(int), hipMemcpyHostToDevice, c->st));
+    HIP_TRY(hipMemsetAsync(c->H, 0, sizeof(double) * 4 * c->ncell, c->st));
+    HIP_TRY(hipStreamSynchronize(c->st));
+    c->failed = -1;
+    return MM_OK;
+}
+
+hipEvent_t get_event(mm_ctx *c)
+{
+    if (!c->pool.empty()) {
+        hipEvent_t e = c->pool.back();
+        c->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+struct Timer {
+    mm_ctx *c;
+    int which;
+    hipEvent_t a = nullptr, b = nullptr;
+    Timer(mm_ctx *c_, int w) : c(c_), which(w)
+    {
+        if (!c->timing) return;
+        a = get_event(c);
+        b = get_event(c);
+        if (a) hipEventRecord(a, c->st);
+    }
+    ~Timer()
+    {
+        if (!c->timing || !a || !b) return;
+        hipEventRecord(b, c->st);
+        c->pending.push_back({which, a, b});
+    }
+};
+
+void collect_timing(mm_ctx *c)
+{
+    for (auto &t : c->pending) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, t.a, t.b) == hipSuccess) {
+            c->tcount[t.which] += 1;
+            c->tms[t.which] += ms;
+        }
+        c->pool.push_back(t.a);
+        c->pool.push_back(t.b);
+    }
+    c->pending.clear();
+}
+
+int enqueue_steps(mm_ctx *c, int nsteps)
+{
+    const mm::Params &P = c->P;
+    for (int s = 0; s < nsteps; ++s) {
+        const int step = c->steps_done;
+        if (c->cfg.dim == 1) {
+            void *Gn = c->G[1 - c->cur];
+            {
+                Timer t(c, 0);
+                mm::launch_step1d(c->Q, c->Qs, (const double *)c->G[c->cur], (double *)Gn, c->H, c->flag, step, P, c->st);
+            }
+            std::swap(c->Q, c->Qs);
+        } else {
+            {
+                Timer t(c, 1);
+                mm::launch_prep2d(c->Q, c->rec, c->wrec, c->flag, step, P, c->st);
+            }
+            {
+                Timer t(c, 0);
+                if (c->fused)
+                    mm::launch_micro_fused2d(c->G[c->cur], c->G[1 - c->cur], c->H, c->rec, c->wrec, P,
+                                             c->cfg.precision, c->st);
+                else
+                    mm::launch_micro_ref2d((const double *)c->G[c->cur], c->Gs, (double *)c->G[1 - c->cur], c->H,
+                                           c->rec, c->wrec, P, c->st);
+            }
+            {
+                Timer t(c, 2);
+                mm::launch_macro2d(c->Q, c->Qs, c->H, c->flag, step, P, c->st);
+            }
+        }
+        if (hipGetLastError() != hipSuccess) {
+            c->broken = true;
+            return MM_EDEVICE;
+        }
+        c->cur = 1 - c->cur;
+        c->steps_done += 1;
+    }
+    return MM_OK;
+}
+
+int finish(mm_ctx *c)
+{
+    if (hipStreamSynchronize(c->st) != hipSuccess) {
+        c->broken = true;
+        return MM_EDEVICE;
+    }
+    collect_timing(c);
+    int f = INT_MAX;
+    if (hipMemcpy(&f, c->flag, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) {
+        c->broken = true;
+        return MM_EDEVICE;
+    }
+    if (f != INT_MAX) {
+        c->failed = f;
+        return MM_ENONPHYS;
+    }
+    return MM_OK;
+}
+
+} // namespace
+
+extern "C" {
+
+double mm_dt(const mm_config *cfg, double t_final, int *nsteps)
+{
+    if (check_cfg(cfg) != MM_OK) return -1.0;
+    double dt = cfg->dt > 0.0 ? cfg->dt : dt_rule(cfg);
+    if (t_final > 0.0) {
+        const int n = (int)std::ceil(t_final / dt);
+        dt = t_final / n;
+        if (nsteps) *nsteps = n;
+    } else if (nsteps) {
+        *nsteps = 0;
+    }
+    return dt;
+}
+
+int mm_init(const mm_config *cfg, const double *q0, const double *g0, mm_ctx **out)
+{
+    if (!out) return MM_EINVAL;
+    *out = nullptr;
+    int rc = check_cfg(cfg);
+    if (rc) return rc;
+    if (!q0) return MM_EINVAL;
+    mm_ctx *c = new (std::nothrow) mm_ctx();
+    if (!c) return MM_ENOMEM;
+    c->cfg = *cfg;
+    c->ncell = cfg->nx * (cfg->dim == 2 ? cfg->ny : 1);
+    c->nv = cfg->nv1 * (cfg->dim == 2 ? cfg->nv2 : 1);
+    c->ncomp = cfg->dim == 2 ? 6 : 3;
+    if (!state_ok(cfg, q0, c->ncell)) {
+        delete c;
+        return MM_ENONPHYS;
+    }
+    mm::Params &P = c->P;
+    P.nx = cfg->nx;
+    P.ny = cfg->dim == 2 ? cfg->ny : 1;
+    P.nv1 = cfg->nv1;
+    P.nv2 = cfg->dim == 2 ? cfg->nv2 : 1;
+    P.nv = c->nv;
+    P.x_lo = cfg->x_lo;
+    P.y_lo = cfg->y_lo;
+    P.v1_lo = cfg->v1_lo;
+    P.v2_lo = cfg->v2_lo;
+    P.dx = (cfg->x_hi - cfg->x_lo) / cfg->nx;
+    P.dy = cfg->dim == 2 ? (cfg->y_hi - cfg->y_lo) / cfg->ny : 1.0;
+    P.dv1 = (cfg->v1_hi - cfg->v1_lo) / cfg->nv1;
+    P.dv2 = cfg->dim == 2 ? (cfg->v2_hi - cfg->v2_lo) / cfg->nv2 : 1.0;
+    P.eps = cfg->eps;
+    P.dt = mm_dt(cfg, 0.0, nullptr);
+    P.nu = cfg->nu;
+    P.tau_model = cfg->tau_model;
+    P.tau_coef = cfg->tau_coef;
+    P.proj_mode = cfg->proj_mode;
+    P.wall_es_term = cfg->wall_es_term ? 1 : 0;
+    for (int s = 0; s < 4; ++s) {
+        const mm_bc &b = cfg->bc[s];
+        P.bc[s].kind = (cfg->dim == 1 && s >= 2) ? mm::BC_EXTRAP : b.kind;
+        P.bc[s].T_wall = b.T_wall;
+        P.bc[s].u_wall = b.u_wall;
+        P.bc[s].rho = b.rho;
+        P.bc[s].u1 = b.u1;
+        P.bc[s].u2 = b.u2;
+        P.bc[s].T = b.T;
+    }
+    c->gbytes = cfg->precision == MM_FP64 ? 8 : 4;
+    c->fused = cfg->dim == 2 && mm::fused_supported(P, cfg->precision) && !std::getenv("MM_REFERENCE_PASS");
+    if (cfg->dim == 2 && !c->fused && cfg->precision != MM_FP64) {
+        delete c;
+        return MM_EINVAL;          // the FP32-storage forms exist only as the fused pass
+    }
+    if (hipSetDevice(cfg->device) != hipSuccess) {
+        delete c;
+        return MM_EDEVICE;
+    }
+    if (cfg->stream) {
+        c->st = (hipStream_t)cfg->stream;
+    } else {
+        if (hipStreamCreateWithFlags(&c->st, hipStreamNonBlocking) != hipSuccess) {
+            delete c;
+            return MM_EDEVICE;
+        }
+        c->own_stream = true;
+    }
+    const size_t ncell = c->ncell, npts = ncell * c->nv;
+    bool ok = hipMalloc(&c->Q, sizeof(double) * c->ncomp * ncell) == hipSuccess &&
+              hipMalloc(&c->Qs, sizeof(double) * c->ncomp * ncell) == hipSuccess &&
+              hipMalloc(&c->H, sizeof(double) * 4 * ncell) == hipSuccess &&
+              hipMalloc(&c->flag, sizeof(int)) == hipSuccess &&
+              hipMalloc(&c->G[0], npts * c->gbytes) == hipSuccess &&
+              hipMalloc(&c->G[1], npts * c->gbytes) == hipSuccess;
+    if (ok && cfg->dim == 2)
+        ok = hipMalloc(&c->rec, sizeof(double) * mm::REC * ncell) == hipSuccess &&
+             hipMalloc(&c->wrec, sizeof(double) * mm::WREC * ncell) == hipSuccess;
+    if (ok && cfg->dim == 2 && !c->fused) ok = hipMalloc(&c->Gs, sizeof(double) * npts) == hipSuccess;
+    if (!ok) {
+        hipGetLastError();
+        release(c);
+        return MM_ENOMEM;
+    }
+    rc = upload_state(c, q0, g0);
+    if (rc) {
+        release(c);
+        return rc;
+    }
+    *out = c;
+    return MM_OK;
+}
+
+int mm_step_async(mm_ctx *ctx, int nsteps)
+{
+    if (!ctx || nsteps < 0) return MM_EINVAL;
+    if (ctx->broken) return MM_ESTATE;
+    if (hipSetDevice(ctx->cfg.device) != hipSuccess) return MM_EDEVICE;
+    return enqueue_steps(ctx, nsteps);
+}
+
+int mm_sync(mm_ctx *ctx)
+{
+    if (!ctx) return MM_EINVAL;
+    if (ctx->broken) return MM_ESTATE;
+    return finish(ctx);
+}
+
+int mm_step(mm_ctx *ctx, int nsteps)
+{
+    int rc = mm_step_async(ctx, nsteps);
+    if (rc) return rc;
+    return finish(ctx);
+}
+
+int mm_moments(mm_ctx *ctx, double *q_out, double *h_out, double *gmom_out)
+{
+    if (!ctx || !q_out) return MM_EINVAL;
+    if (ctx->broken) return MM_ESTATE;
+    if (gmom_out && ctx->cfg.dim != 2) return MM_EINVAL;
+    if (gmom_out) {
+        if (!ctx->gmom && hipMalloc(&ctx->gmom, sizeof(double) * 7 * ctx->ncell) != hipSuccess) return MM_ENOMEM;
+        // cell velocities of the current state for the centred moments
+        mm::launch_prep2d(ctx->Q, ctx->rec, ctx->wrec, ctx->flag, ctx->steps_done, ctx->P, ctx->st);
+        mm::launch_gmom2d(ctx->G[ctx->cur], ctx->gbytes, ctx->rec, ctx->gmom, ctx->P, ctx->st);
+    }
+    if (hipStreamSynchronize(ctx->st) != hipSuccess) return MM_EDEVICE;
+    HIP_TRY(hipMemcpy(q_out, ctx->Q, sizeof(double) * ctx->ncomp * ctx->ncell, hipMemcpyDeviceToHost));
+    if (h_out) {
+        if (ctx->cfg.dim == 2) {
+            HIP_TRY(hipMemcpy(h_out, ctx->H, sizeof(double) * 4 * ctx->ncell, hipMemcpyDeviceToHost));
+        } else {
+            HIP_TRY(hipMemcpy(h_out, ctx->H, sizeof(double) * ctx->ncell, hipMemcpyDeviceToHost));
+        }
+    }
+    if (gmom_out) HIP_TRY(hipMemcpy(gmom_out, ctx->gmom, sizeof(double) * 7 * ctx->ncell, hipMemcpyDeviceToHost));
+    return MM_OK;
+}
+
+int mm_get_g(mm_ctx *ctx, double *g_out)
+{
+    if (!ctx || !g_out) return MM_EINVAL;
+    if (ctx->broken) return MM_ESTATE;
+    if (hipStreamSynchronize(ctx->st) != hipSuccess) return MM_EDEVICE;
+    const size_t n = (size_t)ctx->ncell * ctx->nv;
+    if (ctx->gbytes == 8) {
+        HIP_TRY(hipMemcpy(g_out, ctx->G[ctx->cur], n * 8, hipMemcpyDeviceToHost));
+    } else {
+        std::vector<float> tmp(n);
+        HIP_TRY(hipMemcpy(tmp.data(), ctx->G[ctx->cur], n * 4, hipMemcpyDeviceToHost));
+        for (size_t i = 0; i < n; ++i) g_out[i] = tmp[i];
+    }
+    return MM_OK;
+}
+
+int mm_set_state(mm_ctx *ctx, const double *q, const double *g)
+{
+    if (!ctx || !q) return MM_EINVAL;
+    if (ctx->broken) return MM_ESTATE;
+    if (!state_ok(&ctx->cfg, q, ctx->ncell)) return MM_ENONPHYS;
+    if (hipStreamSynchronize(ctx->st) != hipSuccess) return MM_EDEVICE;
+    return upload_state(ctx, q, g);
+}
+
+void mm_free(mm_ctx *ctx) { release(ctx); }
+
+int mm_failed_step(const mm_ctx *ctx) { return ctx ? ctx->failed : -1; }
+
+const char *mm_strerror(int status)
+{
+    switch (status) {
+    case MM_OK: return "ok";
+    case MM_EINVAL: return "invalid configuration or argument";
+    case MM_ENOMEM: return "out of memory";
+    case MM_EDEVICE: return "HIP runtime error";
+    case MM_ENONPHYS: return "non-physical macro state (rho, T or det of the ES temperature tensor not positive, or not finite)";
+    case MM_ESTATE: return "context unusable after an earlier device error";
+    default: return "unknown status";
+    }
+}
+
+int mm_timing(mm_ctx *ctx, int enable)
+{
+    if (!ctx) return MM_EINVAL;
+    if (hipStreamSynchronize(ctx->st) != hipSuccess) return MM_EDEVICE;
+    collect_timing(ctx);
+    ctx->timing = enable != 0;
+    for (int w = 0; w < 3; ++w) {
+        ctx->tcount[w] = 0;
+        ctx->tms[w] = 0.0;
+    }
+    return MM_OK;
+}
+
+int mm_timing_get(mm_ctx *ctx, int which, int *count, double *total_ms)
+{
+    if (!ctx || which < 0 || which > 2) return MM_EINVAL;
+    if (hipStreamSynchronize(ctx->st) != hipSuccess) return MM_EDEVICE;
+    collect_timing(ctx);
+    if (count) *count = ctx->tcount[which];
+    if (total_ms) *total_ms = ctx->tms[which];
+    return MM_OK;
+}
+
+int mm_device_ptrs(mm_ctx *ctx, void **q, void **g, void **h, int *g_bytes)
+{
+    if (!ctx) return MM_EINVAL;
+    if (q) *q = ctx->Q;
+    if (g) *g = ctx->G[ctx->cur];
+    if (h) *h = ctx->H;
+    if (g_bytes) *g_bytes = ctx->gbytes;
+    return MM_OK;
+}
+
+} // extern "C"

@@ -1,0 +1,69 @@
+// mm_internal.h -- device-side parameters and cell-record layout shared by the
+// library's HIP translation units (not part of the ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define MM_PI 3.14159265358979323846
+
+namespace mm {
+
+// boundary kinds (same values as the ABI)
+enum { BC_EXTRAP = 0, BC_PERIODIC = 1, BC_WALL = 2, BC_INFLOW = 3 };
+enum { TAU_RHO = 0, TAU_P = 1, TAU_HS1D = 2, TAU_CONST = 3 };
+enum { PROJ_DISCRETE = 0, PROJ_PAPER = 1 };
+
+struct Side {
+    int kind;
+    double T_wall, u_wall;
+    double rho, u1, u2, T;
+};
+
+// Everything a kernel needs to know about the problem; passed by value.
+struct Params {
+    int nx, ny, nv1, nv2, nv;
+    double x_lo, y_lo, v1_lo, v2_lo;
+    double dx, dy, dv1, dv2;
+    double eps, dt, nu;
+    int tau_model;
+    double tau_coef;
+    int proj_mode;
+    int wall_es_term;
+    Side bc[4];   // 0 = x_lo, 1 = x_hi, 2 = y_lo, 3 = y_hi
+};
+
+__host__ __device__ inline bool is_open(int kind) { return kind == BC_WALL || kind == BC_INFLOW; }
+
+// ---------------------------------------------------------------------------
+// Per-cell record written by the preparation kernel from Q^n and read by the
+// phase-space pass (2D).  FP64, REC doubles per cell.
+enum {
+    R_RHO = 0, R_U1, R_U2, R_T,
+    R_RST,        // 1/sqrt(T)
+    R_MPRE,       // rho / (2 pi T): Maxwellian prefactor
+    R_I2T,        // 1 / (2T)
+    R_TAU,
+    R_A,          // eps / (eps + dt tau): weight of G** in the relaxation
+    R_B,          // dt tau / (eps + dt tau): weight of G-hat
+    R_P0,         // 10 entries: symmetric 4x4 matrix mapping sum_p phi_a F_p to the
+                  // projection coefficients (dv1 dv2 Gram^{-1}, or dv1 dv2 / rho * I)
+    R_GPRE = R_P0 + 10,   // rho / (2 pi sqrt(det calT))
+    R_QA, R_QB, R_QC,     // exponent of the ES Gaussian: -(QA w1^2 + 2 QB w1 w2 + QC w2^2)
+    R_S11, R_S12,         // sigma_11 (= -sigma_22), sigma_12 of (eqn5-97more)
+    R_DTX, R_DTY,         // grad T of (eqn5-97)
+    R_WALL,               // 1 for cells that use the wall form of G-hat
+    R_ITAU,               // 1 / tau
+    R_IEPS,               // 1 / eps
+    REC = 32
+};
+// wall cells: (rho, u1, u2, T) of the four neighbour Maxwellians (x-, x+, y-, y+)
+enum { WREC = 16 };
+
+// index of the symmetric 4x4 entry (a, b) in the packed R_P0 block
+__host__ __device__ constexpr int sym4(int a, int b)
+{
+    return a <= b ? (a == 0 ? b : a == 1 ? 3 + b : a == 2 ? 5 + b : 9)
+                  : (b == 0 ? a : b == 1 ? 3 + a : b == 2 ? 5 + a : 9);
+}
+
+} // namespace mm

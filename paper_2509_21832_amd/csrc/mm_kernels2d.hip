@@ -1,0 +1,521 @@
+// mm_kernels2d.hip -- 2D2V ES-BGK micro-macro step on gfx950 (FP64 reference
+// kernels: one workgroup per spatial cell for the phase-space pass, one thread
+// per cell for the per-cell work).
+//
+// Paper: Rossmanith & Sar, arXiv:2509.21832, Sec. 5.3 (micro step) and
+// Sec. 5.4 (macro step); walls of Sec. 6.3.
+#include "mm_device.h"
+#include "mm_launch.h"
+
+namespace mm {
+
+// ---------------------------------------------------------------------------
+// per-cell preparation from Q^n
+
+struct CellPrim {
+    double rho, u1, u2, P11, P12, P22, p, T;
+};
+
+__device__ __forceinline__ CellPrim prim_of(const double *q)
+{
+    CellPrim c;
+    c.rho = q[0];
+    c.u1 = q[1] / q[0];
+    c.u2 = q[2] / q[0];
+    c.P11 = q[3] - q[1] * c.u1;
+    c.P12 = q[4] - q[1] * c.u2;
+    c.P22 = q[5] - q[2] * c.u2;
+    c.p = 0.5 * (c.P11 + c.P22);
+    c.T = c.p / c.rho;
+    return c;
+}
+
+// neighbour cell along x (dir 0) or y (dir 1), `up` = +1 side; returns the cell
+// index to read (the cell itself for extrapolation and open sides)
+__device__ __forceinline__ int nbr_cell(const Params &P, int i, int j, int dir, int up)
+{
+    if (dir == 0) {
+        if (up) return i < P.nx - 1 ? j * P.nx + i + 1 : (P.bc[1].kind == BC_PERIODIC ? j * P.nx : j * P.nx + i);
+        return i > 0 ? j * P.nx + i - 1 : (P.bc[0].kind == BC_PERIODIC ? j * P.nx + P.nx - 1 : j * P.nx + i);
+    }
+    if (up) return j < P.ny - 1 ? (j + 1) * P.nx + i : (P.bc[3].kind == BC_PERIODIC ? i : j * P.nx + i);
+    return j > 0 ? (j - 1) * P.nx + i : (P.bc[2].kind == BC_PERIODIC ? (P.ny - 1) * P.nx + i : j * P.nx + i);
+}
+
+__device__ __forceinline__ bool wall_cell(const Params &P, int i, int j)
+{
+    return (i == 0 && is_open(P.bc[0].kind)) || (i == P.nx - 1 && is_open(P.bc[1].kind)) ||
+           (j == 0 && is_open(P.bc[2].kind)) || (j == P.ny - 1 && is_open(P.bc[3].kind));
+}
+
+// inverse of a symmetric positive definite 4x4 matrix (Cholesky); out packed by sym4
+__device__ __forceinline__ void spd_inverse4(const double A[4][4], double scale, double *out)
+{
+    double L[4][4] = {};
+    for (int r = 0; r < 4; ++r) {
+        for (int s = 0; s <= r; ++s) {
+            double v = A[r][s];
+            for (int t = 0; t < s; ++t) v -= L[r][t] * L[s][t];
+            L[r][s] = (r == s) ? sqrt(v) : v / L[s][s];
+        }
+    }
+    // inverse columns: solve L L^T x = e_c
+    double X[4][4];
+    for (int col = 0; col < 4; ++col) {
+        double y[4];
+        for (int r = 0; r < 4; ++r) {
+            double v = (r == col) ? 1.0 : 0.0;
+            for (int t = 0; t < r; ++t) v -= L[r][t] * y[t];
+            y[r] = v / L[r][r];
+        }
+        for (int r = 3; r >= 0; --r) {
+            double v = y[r];
+            for (int t = r + 1; t < 4; ++t) v -= L[t][r] * X[t][col];
+            X[r][col] = v / L[r][r];
+        }
+    }
+    for (int a = 0; a < 4; ++a)
+        for (int b = a; b < 4; ++b) out[sym4(a, b)] = scale * 0.5 * (X[a][b] + X[b][a]);
+}
+
+__global__ void k_prep2d(const double *__restrict__ Q, double *__restrict__ rec, double *__restrict__ wrec,
+                         int *__restrict__ flag, int step, Params P)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= P.nx * P.ny) return;
+    const int i = c % P.nx, j = c / P.nx;
+    const CellPrim s = prim_of(Q + 6 * (size_t)c);
+    double *R = rec + (size_t)c * REC;
+
+    const double tau = tau_of(P, s.rho, s.p, s.T);
+    const double S11 = (1.0 - P.nu) * s.T + P.nu * s.P11 / s.rho;
+    const double S12 = P.nu * s.P12 / s.rho;
+    const double S22 = (1.0 - P.nu) * s.T + P.nu * s.P22 / s.rho;
+    const double det = S11 * S22 - S12 * S12;
+    if (!(s.rho > 0.0) || !(s.T > 0.0) || !(det > 0.0) || !(s.P11 > 0.0) || !(s.P22 > 0.0) ||
+        !isfinite(s.u1) || !isfinite(s.u2) || !isfinite(s.P12))
+        atomicMin(flag, step);
+
+    R[R_RHO] = s.rho;
+    R[R_U1] = s.u1;
+    R[R_U2] = s.u2;
+    R[R_T] = s.T;
+    R[R_RST] = 1.0 / sqrt(s.T);
+    R[R_MPRE] = s.rho / (2.0 * MM_PI * s.T);
+    R[R_I2T] = 1.0 / (2.0 * s.T);
+    R[R_TAU] = tau;
+    R[R_ITAU] = 1.0 / tau;
+    R[R_IEPS] = 1.0 / P.eps;
+    R[R_A] = P.eps / (P.eps + P.dt * tau);
+    R[R_B] = P.dt * tau / (P.eps + P.dt * tau);
+    R[R_GPRE] = s.rho / (2.0 * MM_PI * sqrt(det));
+    R[R_QA] = S22 / (2.0 * det);
+    R[R_QB] = -S12 / (2.0 * det);
+    R[R_QC] = S11 / (2.0 * det);
+
+    // projection coefficients
+    const double dA = P.dv1 * P.dv2;
+    if (P.proj_mode == PROJ_PAPER) {
+        for (int a = 0; a < 4; ++a)
+            for (int b = a; b < 4; ++b) R[R_P0 + sym4(a, b)] = a == b ? dA / s.rho : 0.0;
+    } else {
+        // Gram_ab = dA sum phi_a phi_b M from separable 1D sums: M = c0 e1(k) e2(l)
+        double S1[5] = {0, 0, 0, 0, 0}, S2[5] = {0, 0, 0, 0, 0};
+        for (int k = 0; k < P.nv1; ++k) {
+            const double w = P.v1_lo + (k + 0.5) * P.dv1 - s.u1;
+            const double e = exp(-w * w / (2.0 * s.T));
+            double m = e;
+            for (int q = 0; q < 5; ++q) { S1[q] += m; m *= w; }
+        }
+        for (int l = 0; l < P.nv2; ++l) {
+            const double w = P.v2_lo + (l + 0.5) * P.dv2 - s.u2;
+            const double e = exp(-w * w / (2.0 * s.T));
+            double m = e;
+            for (int q = 0; q < 5; ++q) { S2[q] += m; m *= w; }
+        }
+        auto mm = [&](int p, int q) { return S1[p] * S2[q]; };
+        const double c0 = dA * s.rho / (2.0 * MM_PI * s.T);
+        const double T = s.T, rT = sqrt(T);
+        double A[4][4];
+        A[0][0] = c0 * mm(0, 0);
+        A[0][1] = c0 * mm(1, 0) / rT;
+        A[0][2] = c0 * mm(0, 1) / rT;
+        A[0][3] = c0 * ((mm(2, 0) + mm(0, 2)) / (2.0 * T) - mm(0, 0));
+        A[1][1] = c0 * mm(2, 0) / T;
+        A[1][2] = c0 * mm(1, 1) / T;
+        A[1][3] = c0 * ((mm(3, 0) + mm(1, 2)) / (2.0 * T) - mm(1, 0)) / rT;
+        A[2][2] = c0 * mm(0, 2) / T;
+        A[2][3] = c0 * ((mm(2, 1) + mm(0, 3)) / (2.0 * T) - mm(0, 1)) / rT;
+        A[3][3] = c0 * ((mm(4, 0) + 2.0 * mm(2, 2) + mm(0, 4)) / (4.0 * T * T) - (mm(2, 0) + mm(0, 2)) / T + mm(0, 0));
+        for (int a = 0; a < 4; ++a)
+            for (int b = 0; b < a; ++b) A[a][b] = A[b][a];
+        spd_inverse4(A, dA, R + R_P0);
+    }
+
+    // central differences of u and T (eqn5-97, eqn5-97more) with boundary ghosts
+    const CellPrim xm = prim_of(Q + 6 * (size_t)nbr_cell(P, i, j, 0, 0));
+    const CellPrim xp = prim_of(Q + 6 * (size_t)nbr_cell(P, i, j, 0, 1));
+    const CellPrim ym = prim_of(Q + 6 * (size_t)nbr_cell(P, i, j, 1, 0));
+    const CellPrim yp = prim_of(Q + 6 * (size_t)nbr_cell(P, i, j, 1, 1));
+    const double Tip = 0.5 * (xp.T + s.T), Tim = 0.5 * (xm.T + s.T);
+    const double Tjp = 0.5 * (yp.T + s.T), Tjm = 0.5 * (ym.T + s.T);
+    R[R_DTX] = (Tip - Tim) / P.dx;
+    R[R_DTY] = (Tjp - Tjm) / P.dy;
+    const double Dxu1 = 0.5 * (xp.u1 - xm.u1), Dxu2 = 0.5 * (xp.u2 - xm.u2);
+    const double Dyu1 = 0.5 * (yp.u1 - ym.u1), Dyu2 = 0.5 * (yp.u2 - ym.u2);
+    R[R_S11] = Dxu1 / P.dx - Dyu2 / P.dy;
+    R[R_S12] = Dyu1 / P.dy + Dxu2 / P.dx;
+
+    const bool wall = wall_cell(P, i, j);
+    R[R_WALL] = wall ? 1.0 : 0.0;
+    if (wall) {
+        double *Wr = wrec + (size_t)c * WREC;
+        const CellPrim *nb[4] = {&xm, &xp, &ym, &yp};
+        for (int d = 0; d < 4; ++d) {
+            const int dir = d / 2, up = d % 2;
+            const bool inside = dir == 0 ? (up ? i < P.nx - 1 : i > 0) : (up ? j < P.ny - 1 : j > 0);
+            const int side = dir == 0 ? (up ? 1 : 0) : (up ? 3 : 2);
+            double g[4];
+            if (!inside && is_open(P.bc[side].kind)) {
+                side_ghost(P.bc[side], side, s.rho, s.u1, s.u2, side < 2 ? s.P11 / s.rho : s.P22 / s.rho, g);
+            } else {
+                g[0] = nb[d]->rho; g[1] = nb[d]->u1; g[2] = nb[d]->u2; g[3] = nb[d]->T;
+            }
+            for (int t = 0; t < 4; ++t) Wr[4 * d + t] = g[t];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// phase-space pass, reference form: one workgroup per cell
+
+__device__ __forceinline__ void proj_coef(const double *R, const double s[4], double A[4])
+{
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        double v = 0.0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) v += R[R_P0 + sym4(a, b)] * s[b];
+        A[a] = v;
+    }
+}
+
+// x-transport sub-step (micro-2D-split-1): G -> G*
+template <int NW>
+__global__ __launch_bounds__(64 * NW) void k_micro_x2d(const double *__restrict__ G, double *__restrict__ Gs,
+                                                      const double *__restrict__ rec, Params P)
+{
+    __shared__ double lds[NW * 4];
+    const int c = blockIdx.x, i = c % P.nx;
+    const double *R = rec + (size_t)c * REC;
+    const double u1 = R[R_U1], u2 = R[R_U2], rsT = R[R_RST], i2T = R[R_I2T], mpre = R[R_MPRE];
+    const size_t nv = P.nv;
+    const double *Gc = G + (size_t)c * nv;
+    const double *Gm, *Gp;
+    if (i > 0) Gm = Gc - nv;
+    else if (P.bc[0].kind == BC_PERIODIC) Gm = Gc + (size_t)(P.nx - 1) * nv;
+    else Gm = is_open(P.bc[0].kind) ? nullptr : Gc;
+    if (i < P.nx - 1) Gp = Gc + nv;
+    else if (P.bc[1].kind == BC_PERIODIC) Gp = Gc - (size_t)(P.nx - 1) * nv;
+    else Gp = is_open(P.bc[1].kind) ? nullptr : Gc;
+
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int p = threadIdx.x; p < P.nv; p += 64 * NW) {
+        const int k = p % P.nv1, l = p / P.nv1;
+        const double v1 = P.v1_lo + (k + 0.5) * P.dv1, v2 = P.v2_lo + (l + 0.5) * P.dv2;
+        const double gc = Gc[p], gm = Gm ? Gm[p] : 0.0, gp = Gp ? Gp[p] : 0.0;
+        const double Z = fmin(0.0, v1) * ((gp - gc) / P.dx) + fmax(0.0, v1) * ((gc - gm) / P.dx);
+        const double w1 = v1 - u1, w2 = v2 - u2;
+        s[0] += Z;
+        s[1] += w1 * rsT * Z;
+        s[2] += w2 * rsT * Z;
+        s[3] += ((w1 * w1 + w2 * w2) * i2T - 1.0) * Z;
+    }
+    block_sum<4, NW>(s, lds);
+    double A[4];
+    proj_coef(R, s, A);
+    for (int p = threadIdx.x; p < P.nv; p += 64 * NW) {
+        const int k = p % P.nv1, l = p / P.nv1;
+        const double v1 = P.v1_lo + (k + 0.5) * P.dv1, v2 = P.v2_lo + (l + 0.5) * P.dv2;
+        const double gc = Gc[p], gm = Gm ? Gm[p] : 0.0, gp = Gp ? Gp[p] : 0.0;
+        const double Z = fmin(0.0, v1) * ((gp - gc) / P.dx) + fmax(0.0, v1) * ((gc - gm) / P.dx);
+        const double w1 = v1 - u1, w2 = v2 - u2, r2 = w1 * w1 + w2 * w2;
+        const double M = mpre * exp(-r2 * i2T);
+        const double Zh = (A[0] + A[1] * (w1 * rsT) + A[2] * (w2 * rsT) + A[3] * (r2 * i2T - 1.0)) * M;
+        Gs[(size_t)c * nv + p] = gc + P.dt * (Zh - Z);
+    }
+}
+
+__device__ __forceinline__ double maxw(double rho, double u1, double u2, double T, double v1, double v2)
+{
+    const double w1 = v1 - u1, w2 = v2 - u2;
+    return rho / (2.0 * MM_PI * T) * exp(-(w1 * w1 + w2 * w2) / (2.0 * T));
+}
+
+// y-transport (micro-2D-split-2), G-hat (eqn5-97 / wall form), relaxation
+// (eqn5-98) and the heat-flux tensor (eqn5-99): G* -> G^{n+1}, H^{n+1}
+template <int NW>
+__global__ __launch_bounds__(64 * NW) void k_micro_y2d(const double *__restrict__ Gs, double *__restrict__ Gn,
+                                                      double *__restrict__ H, const double *__restrict__ rec,
+                                                      const double *__restrict__ wrec, Params P)
+{
+    __shared__ double lds[NW * 12];
+    const int c = blockIdx.x, j = c / P.nx;
+    const double *R = rec + (size_t)c * REC;
+    const double u1 = R[R_U1], u2 = R[R_U2], rsT = R[R_RST], i2T = R[R_I2T], mpre = R[R_MPRE];
+    const double gpre = R[R_GPRE], qa = R[R_QA], qb = R[R_QB], qc = R[R_QC], ieps = R[R_IEPS];
+    const double itau = R[R_ITAU], s11 = R[R_S11], s12 = R[R_S12], dTx = R[R_DTX], dTy = R[R_DTY];
+    const double T = R[R_T];
+    const bool wall = R[R_WALL] != 0.0;
+    const bool discrete = P.proj_mode == PROJ_DISCRETE;
+    const bool es_on = !wall || P.wall_es_term;
+    double nbm[16];
+    if (wall)
+        for (int t = 0; t < 16; ++t) nbm[t] = wrec[(size_t)c * WREC + t];
+    const size_t nv = P.nv, row = (size_t)P.nx * nv;
+    const double *Gc = Gs + (size_t)c * nv;
+    const double *Gm, *Gp;
+    if (j > 0) Gm = Gc - row;
+    else if (P.bc[2].kind == BC_PERIODIC) Gm = Gc + (size_t)(P.ny - 1) * row;
+    else Gm = is_open(P.bc[2].kind) ? nullptr : Gc;
+    if (j < P.ny - 1) Gp = Gc + row;
+    else if (P.bc[3].kind == BC_PERIODIC) Gp = Gc - (size_t)(P.ny - 1) * row;
+    else Gp = is_open(P.bc[3].kind) ? nullptr : Gc;
+
+    auto point = [&](int p, double &Z, double &M, double &mup, double &base, double &w1, double &w2, double &gc) {
+        const int k = p % P.nv1, l = p / P.nv1;
+        const double v1 = P.v1_lo + (k + 0.5) * P.dv1, v2 = P.v2_lo + (l + 0.5) * P.dv2;
+        gc = Gc[p];
+        const double gm = Gm ? Gm[p] : 0.0, gp = Gp ? Gp[p] : 0.0;
+        Z = fmin(0.0, v2) * ((gp - gc) / P.dy) + fmax(0.0, v2) * ((gc - gm) / P.dy);
+        w1 = v1 - u1;
+        w2 = v2 - u2;
+        const double r2 = w1 * w1 + w2 * w2;
+        M = mpre * exp(-r2 * i2T);
+        const double es = es_on ? (gpre * exp(-(qa * w1 * w1 + 2.0 * qb * w1 * w2 + qc * w2 * w2)) - M) * ieps : 0.0;
+        if (wall) {
+            const double Mxm = maxw(nbm[0], nbm[1], nbm[2], nbm[3], v1, v2);
+            const double Mxp = maxw(nbm[4], nbm[5], nbm[6], nbm[7], v1, v2);
+            const double Mym = maxw(nbm[8], nbm[9], nbm[10], nbm[11], v1, v2);
+            const double Myp = maxw(nbm[12], nbm[13], nbm[14], nbm[15], v1, v2);
+            mup = fmin(0.0, v1) * ((Mxp - M) / P.dx) + fmax(0.0, v1) * ((M - Mxm) / P.dx) +
+                  fmin(0.0, v2) * ((Myp - M) / P.dy) + fmax(0.0, v2) * ((M - Mym) / P.dy);
+            base = es;
+        } else {
+            mup = 0.0;
+            const double Bs = (s11 * (w1 * w1 - w2 * w2) + 2.0 * s12 * w1 * w2) / (2.0 * T);
+            const double CgT = ((r2 / (2.0 * T) - 2.0) / T) * (w1 * dTx + w2 * dTy);
+            base = -itau * (Bs + CgT) * M + es;
+        }
+    };
+
+    double s[12];
+#pragma unroll
+    for (int n = 0; n < 12; ++n) s[n] = 0.0;
+    for (int p = threadIdx.x; p < P.nv; p += 64 * NW) {
+        double Z, M, mup, base, w1, w2, gc;
+        point(p, Z, M, mup, base, w1, w2, gc);
+        const double f[4] = {1.0, w1 * rsT, w2 * rsT, (w1 * w1 + w2 * w2) * i2T - 1.0};
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            s[a] += f[a] * Z;
+            s[4 + a] += f[a] * mup;
+            s[8 + a] += f[a] * base;
+        }
+    }
+    block_sum<12, NW>(s, lds);
+    double AZ[4], AM[4], AB[4];
+    proj_coef(R, s, AZ);
+    proj_coef(R, s + 4, AM);
+    proj_coef(R, s + 8, AB);
+    if (!discrete)
+        for (int a = 0; a < 4; ++a) AB[a] = 0.0;
+    const double ra = R[R_A], rb = R[R_B];
+    double h[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int p = threadIdx.x; p < P.nv; p += 64 * NW) {
+        double Z, M, mup, base, w1, w2, gc;
+        point(p, Z, M, mup, base, w1, w2, gc);
+        const double f1 = w1 * rsT, f2 = w2 * rsT, f3 = (w1 * w1 + w2 * w2) * i2T - 1.0;
+        const double Zh = (AZ[0] + AZ[1] * f1 + AZ[2] * f2 + AZ[3] * f3) * M;
+        const double gss = gc + P.dt * (Zh - Z);
+        const double PM = (AM[0] + AM[1] * f1 + AM[2] * f2 + AM[3] * f3) * M;
+        const double PB = (AB[0] + AB[1] * f1 + AB[2] * f2 + AB[3] * f3) * M;
+        const double gh = -itau * (mup - PM) + (base - PB);
+        const double gn = ra * gss + rb * gh;
+        Gn[(size_t)c * nv + p] = gn;
+        h[0] += w1 * w1 * w1 * gn;
+        h[1] += w1 * w1 * w2 * gn;
+        h[2] += w1 * w2 * w2 * gn;
+        h[3] += w2 * w2 * w2 * gn;
+    }
+    block_sum<4, NW>(h, lds);
+    if (threadIdx.x == 0) {
+        const double f = P.eps * P.dv1 * P.dv2;
+        for (int a = 0; a < 4; ++a) H[(size_t)c * 4 + a] = f * h[a];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// macro sweeps (eqn5-103) with the collision half steps fused in
+
+// face flux and heat-flux face value between the cells at positions m-1 and m
+// along a line; qlo / qhi are the collided states of those cells.
+__device__ __forceinline__ void interior_face(const double qlo[6], const double qhi[6], int d, double F[6])
+{
+    double fp[6], fm[6];
+    kfvs_half(qlo, d, 1.0, fp);
+    kfvs_half(qhi, d, -1.0, fm);
+#pragma unroll
+    for (int m = 0; m < 6; ++m) F[m] = fp[m] + fm[m];
+}
+
+// boundary face of side `side` next to the edge cell with collided state qe
+__device__ __forceinline__ void boundary_face(const Params &P, int side, const double qe[6], const double qwrap[6],
+                                              int d, double F[6])
+{
+    const int kind = P.bc[side].kind;
+    const bool low = (side == 0 || side == 2);
+    if (kind == BC_EXTRAP) {
+        flux_full(qe, d, F);
+    } else if (kind == BC_PERIODIC) {
+        if (low) interior_face(qwrap, qe, d, F);
+        else interior_face(qe, qwrap, d, F);
+    } else {
+        const double rho = qe[0], u1 = qe[1] / rho, u2 = qe[2] / rho;
+        const double Pnn = d == 0 ? qe[3] - qe[1] * u1 : qe[5] - qe[2] * u2;
+        double g[4], qg[6];
+        side_ghost(P.bc[side], side, rho, u1, u2, Pnn / rho, g);
+        ghost_q(g, qg);
+        if (low) interior_face(qg, qe, d, F);
+        else interior_face(qe, qg, d, F);
+    }
+}
+
+__device__ __forceinline__ void load_q(const double *Q, int c, double q[6])
+{
+#pragma unroll
+    for (int m = 0; m < 6; ++m) q[m] = Q[6 * (size_t)c + m];
+}
+
+// dir 0: Q^n -> (collision half) Q* -> KFVS x -> Q**;  dir 1: Q** -> KFVS y -> Q*** -> (collision half) Q^{n+1}
+template <int DIR>
+__global__ void k_macro2d(const double *__restrict__ Qin, const double *__restrict__ H, double *__restrict__ Qout,
+                          int *__restrict__ flag, int step, Params P)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= P.nx * P.ny) return;
+    const int i = c % P.nx, j = c / P.nx;
+    const int n = DIR == 0 ? P.nx : P.ny, pos = DIR == 0 ? i : j;
+    const int stride = DIR == 0 ? 1 : P.nx;
+    const int slo = DIR == 0 ? 0 : 2, shi = DIR == 0 ? 1 : 3;
+    const double h = DIR == 0 ? P.dx : P.dy;
+    const int hoff = DIR == 0 ? 0 : 1;
+    double qc[6], ql[6], qr[6];
+    load_q(Qin, c, qc);
+    if (DIR == 0) collide(P, qc);
+    const int cl = pos > 0 ? c - stride : c + (n - 1) * stride;      // periodic wrap when at the low edge
+    const int cr = pos < n - 1 ? c + stride : c - (n - 1) * stride;
+    load_q(Qin, cl, ql);
+    load_q(Qin, cr, qr);
+    if (DIR == 0) {
+        collide(P, ql);
+        collide(P, qr);
+    }
+    double FL[6], FR[6], HL[3], HR[3];
+    if (pos > 0) {
+        interior_face(ql, qc, DIR, FL);
+        for (int a = 0; a < 3; ++a) HL[a] = 0.5 * (H[4 * (size_t)c + hoff + a] + H[4 * (size_t)cl + hoff + a]);
+    } else {
+        boundary_face(P, slo, qc, ql, DIR, FL);
+        const int kind = P.bc[slo].kind;
+        for (int a = 0; a < 3; ++a) {
+            const double hc = H[4 * (size_t)c + hoff + a];
+            HL[a] = kind == BC_EXTRAP ? hc : kind == BC_PERIODIC ? 0.5 * (hc + H[4 * (size_t)cl + hoff + a]) : 0.5 * hc;
+        }
+    }
+    if (pos < n - 1) {
+        interior_face(qc, qr, DIR, FR);
+        for (int a = 0; a < 3; ++a) HR[a] = 0.5 * (H[4 * (size_t)cr + hoff + a] + H[4 * (size_t)c + hoff + a]);
+    } else {
+        boundary_face(P, shi, qc, qr, DIR, FR);
+        const int kind = P.bc[shi].kind;
+        for (int a = 0; a < 3; ++a) {
+            const double hc = H[4 * (size_t)c + hoff + a];
+            HR[a] = kind == BC_EXTRAP ? hc : kind == BC_PERIODIC ? 0.5 * (H[4 * (size_t)cr + hoff + a] + hc) : 0.5 * hc;
+        }
+    }
+    double qo[6];
+    for (int m = 0; m < 6; ++m) qo[m] = qc[m] - P.dt / h * (FR[m] - FL[m]);
+    for (int a = 0; a < 3; ++a) qo[3 + a] -= P.dt * (HR[a] - HL[a]) / h;
+    if (DIR == 1) {
+        collide(P, qo);
+        if (q_bad(qo)) atomicMin(flag, step + 1);
+    }
+    for (int m = 0; m < 6; ++m) Qout[6 * (size_t)c + m] = qo[m];
+}
+
+// g-moments for diagnostics: dv sum (1, v1, v2, |v|^2/2) G and
+// eps dv sum ((w1^2 - w2^2)/2, w1 w2, |w|^2/2) G per cell
+template <typename TG>
+__global__ __launch_bounds__(256) void k_gmom2d(const TG *__restrict__ G, const double *__restrict__ rec,
+                                                double *__restrict__ out, Params P)
+{
+    __shared__ double lds[4 * 7];
+    const int c = blockIdx.x;
+    const double u1 = rec[(size_t)c * REC + R_U1], u2 = rec[(size_t)c * REC + R_U2];
+    double s[7] = {0, 0, 0, 0, 0, 0, 0};
+    for (int p = threadIdx.x; p < P.nv; p += 256) {
+        const int k = p % P.nv1, l = p / P.nv1;
+        const double v1 = P.v1_lo + (k + 0.5) * P.dv1, v2 = P.v2_lo + (l + 0.5) * P.dv2;
+        const double g = (double)G[(size_t)c * P.nv + p];
+        const double w1 = v1 - u1, w2 = v2 - u2;
+        s[0] += g;
+        s[1] += v1 * g;
+        s[2] += v2 * g;
+        s[3] += 0.5 * (v1 * v1 + v2 * v2) * g;
+        s[4] += 0.5 * (w1 * w1 - w2 * w2) * g;
+        s[5] += w1 * w2 * g;
+        s[6] += 0.5 * (w1 * w1 + w2 * w2) * g;
+    }
+    block_sum<7, 4>(s, lds);
+    if (threadIdx.x == 0) {
+        const double dA = P.dv1 * P.dv2;
+        for (int a = 0; a < 4; ++a) out[7 * (size_t)c + a] = dA * s[a];
+        for (int a = 4; a < 7; ++a) out[7 * (size_t)c + a] = P.eps * dA * s[a];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+
+void launch_prep2d(const double *Q, double *rec, double *wrec, int *flag, int step, const Params &P, hipStream_t st)
+{
+    const int n = P.nx * P.ny;
+    hipLaunchKernelGGL(k_prep2d, dim3((n + 127) / 128), dim3(128), 0, st, Q, rec, wrec, flag, step, P);
+}
+
+void launch_micro_ref2d(const double *G, double *Gs, double *Gn, double *H, const double *rec, const double *wrec,
+                        const Params &P, hipStream_t st)
+{
+    const int n = P.nx * P.ny;
+    hipLaunchKernelGGL(k_micro_x2d<4>, dim3(n), dim3(256), 0, st, G, Gs, rec, P);
+    hipLaunchKernelGGL(k_micro_y2d<4>, dim3(n), dim3(256), 0, st, Gs, Gn, H, rec, wrec, P);
+}
+
+void launch_macro2d(double *Q, double *Qs, const double *H, int *flag, int step, const Params &P, hipStream_t st)
+{
+    const int n = P.nx * P.ny;
+    hipLaunchKernelGGL(k_macro2d<0>, dim3((n + 127) / 128), dim3(128), 0, st, Q, H, Qs, flag, step, P);
+    hipLaunchKernelGGL(k_macro2d<1>, dim3((n + 127) / 128), dim3(128), 0, st, Qs, H, Q, flag, step, P);
+}
+
+void launch_gmom2d(const void *G, int g_bytes, const double *rec, double *out, const Params &P, hipStream_t st)
+{
+    const int n = P.nx * P.ny;
+    if (g_bytes == 8)
+        hipLaunchKernelGGL(k_gmom2d<double>, dim3(n), dim3(256), 0, st, (const double *)G, rec, out, P);
+    else
+        hipLaunchKernelGGL(k_gmom2d<float>, dim3(n), dim3(256), 0, st, (const float *)G, rec, out, P);
+}
+
+} // namespace mm

@@ -1,0 +1,23 @@
+// mm_launch.h -- host-side launchers of the library's kernels (internal).
+#pragma once
+#include "mm_internal.h"
+
+namespace mm {
+
+// 2D
+void launch_prep2d(const double *Q, double *rec, double *wrec, int *flag, int step, const Params &P, hipStream_t st);
+void launch_micro_ref2d(const double *G, double *Gs, double *Gn, double *H, const double *rec, const double *wrec,
+                        const Params &P, hipStream_t st);
+void launch_macro2d(double *Q, double *Qs, const double *H, int *flag, int step, const Params &P, hipStream_t st);
+void launch_gmom2d(const void *G, int g_bytes, const double *rec, double *out, const Params &P, hipStream_t st);
+
+// fused phase-space pass; returns false when the shape is not supported
+bool fused_supported(const Params &P, int precision);
+void launch_micro_fused2d(const void *G, void *Gn, double *H, const double *rec, const double *wrec,
+                          const Params &P, int precision, hipStream_t st);
+
+// 1D
+void launch_step1d(const double *Q, double *Qn, const double *G, double *Gn, double *H, int *flag, int step,
+                   const Params &P, hipStream_t st);
+
+} // namespace mm

@@ -1,0 +1,107 @@
+"""GPU FP64 path vs the oracle, element by element, through the C ABI."""
+import numpy as np
+import pytest
+
+import mm_workloads as W
+import oracle
+from gpu_common import log, parity, rel_l1, run_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _inflow_box(seed=0):
+    b = [{"kind": "inflow", "rho": 1.2, "u1": 0.3, "u2": 0.05, "T": 1.1}, {"kind": "extrap"},
+         {"kind": "wall", "T_wall": 0.9}, {"kind": "wall", "T_wall": 1.2, "u_wall": -0.15}]
+    return W.smooth2d(seed=seed, nx=14, ny=9, nv=12, eps=0.07, bc=b)
+
+
+def _nonsquare_v():
+    """nv1 != nv2 and different velocity boxes: catches a swapped k/l index."""
+    p, Q, G = W.quadrant2d(seed=2, nx=9, ny=12, nv=12, eps=0.03)
+    p["nv2"], p["v2"] = 9, (-6.0, 6.0)
+    return p, Q, W.zero_g(p)
+
+
+SMALL = {
+    # ragged sizes, every boundary kind, both projector modes, several nu
+    "walls_quadrant": lambda: W.quadrant2d(seed=1, nx=13, ny=11, nv=10, eps=0.1),
+    "walls_nonsquare_v": lambda: _nonsquare_v(),
+    "lid_cavity": lambda: W.cavity2d(seed=3, nx=17, ny=10, nv=14, eps=0.02, amp=0.2),
+    "periodic_smooth": lambda: W.smooth2d(seed=4, nx=12, ny=10, nv=16, eps=0.05),
+    "periodic_paper_proj": lambda: W.smooth2d(seed=5, nx=10, ny=12, nv=13, eps=0.2, proj_mode="paper"),
+    "extrap_nu_minus1": lambda: W.smooth2d(seed=6, nx=11, ny=8, nv=12, eps=0.01, bc=W.extrap2d(), nu=-1.0),
+    "extrap_bgk_nu0": lambda: W.smooth2d(seed=7, nx=8, ny=11, nv=11, eps=1.0, bc=W.extrap2d(), nu=0.0),
+    "inflow_mixed_sides": lambda: _inflow_box(8),
+    "walls_no_es_term": lambda: W.quadrant2d(seed=9, nx=10, ny=10, nv=10, eps=0.1, wall_es_term=False),
+    "walls_paper_proj": lambda: W.cavity2d(seed=10, nx=12, ny=12, nv=12, eps=0.05, amp=0.2, proj_mode="paper"),
+    "tiny_2x2": lambda: W.smooth2d(seed=11, nx=2, ny=2, nv=4, eps=0.3),
+    "small_eps": lambda: W.cavity2d(seed=12, nx=10, ny=9, nv=16, eps=1e-3, amp=0.1),
+    "tau_p_model": lambda: W.quadrant2d(seed=13, nx=8, ny=8, nv=12, eps=0.05, tau_model="p", tau_coef=1.0),
+}
+
+
+@pytest.mark.parametrize("name", sorted(SMALL))
+def test_small_2d(name):
+    p, Q, G = SMALL[name]()
+    parity(p, Q, G, 30, label=name)
+
+
+def test_small_2d_nonzero_g0():
+    """Start from a micro part with nonzero (projected) values."""
+    p, Q, G = W.smooth2d(seed=14, nx=9, ny=9, nv=12, eps=0.1)
+    Qo, Go, Ho = oracle.run(p, Q.reshape(-1), G.reshape(-1), 5)     # a valid g from 5 oracle steps
+    parity(p, Qo, Go, 20, label="nonzero_g0")
+
+
+@pytest.mark.parametrize("bc,mode", [("extrap", "discrete"), ("periodic", "discrete"), ("periodic", "paper")])
+def test_small_1d(bc, mode):
+    p, Q, G = W.sod1d(nx=37, nv=20, eps=0.05, bc=bc, proj_mode=mode)
+    parity(p, Q, G, 60, label=f"1d_{bc}_{mode}")
+
+
+def test_c1_sod1d_full():
+    """Config 1: Nx = 200, Nv = 64, eps = 1e-2, outflow, 100 steps."""
+    p, Q, G = W.sod1d()
+    parity(p, Q, G, 100, label="c1_full")
+
+
+def test_c2_quadrant_full():
+    """Config 2: 64^2 x 24^2 quadrant Riemann problem with walls, eps = 0.1, 200 steps (seed 0)."""
+    p, Q, G = W.quadrant2d(seed=0)
+    parity(p, Q, G, 200, label="c2_full", chunks=4)
+
+
+@pytest.mark.parametrize("eps", [1e-3, 1.0])
+def test_c3_full_one_step_all_outputs(eps):
+    """Config 3 at full size (256^2 x 32^2): one step, every output element."""
+    p, Q, G = W.cavity2d(seed=0, eps=eps)
+    parity(p, Q, G, 1, label=f"c3_one_step_eps{eps:g}")
+
+
+def test_c3_full_two_steps_from_nonzero_g():
+    """Config 3 at full size from a developed state (g != 0, u != 0): the state after
+    2 oracle steps is advanced 1 step by both sides."""
+    p, Q, G = W.cavity2d(seed=1, eps=1e-2)
+    Qo, Go, Ho = oracle.run(p, Q.reshape(-1), G.reshape(-1), 2)
+    parity(p, Qo, Go, 1, label="c3_developed")
+
+
+def test_c3_full_100_steps_vs_golden():
+    """Config 3, 100 steps, all four eps: macro rel-L1 <= 1e-12 against the oracle's
+    stored result (tests/golden/make_c3_reference.py)."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "c3_cavity_100steps.npz")
+    ref = np.load(path)
+    st = int(ref["stride"])
+    for eps in (1e-3, 1e-2, 1e-1, 1.0):
+        key = f"eps{eps:g}"
+        p, Q, G = W.cavity2d(seed=0, eps=eps)
+        log(f"[c3_100 {key}] start")
+        Qg, Gg, Hg = run_gpu(p, Q, G, int(ref["steps"]), chunks=4)
+        Qg = Qg.reshape(p["ny"], p["nx"], 6)
+        e = rel_l1(Qg[::st, ::st, :], ref[key + "_sample"])
+        sums = Qg.reshape(-1, 6).sum(0)
+        es = np.abs(sums - ref[key + "_sum"]) / ref[key + "_abssum"]
+        log(f"[c3_100 {key}] sampled Q rel-L1 {e:.3e}; domain sums rel {es.max():.3e}")
+        assert e <= 1e-12
+        assert es.max() <= 1e-12
