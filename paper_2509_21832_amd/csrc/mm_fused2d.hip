@@ -1,15 +1,502 @@
-// mm_fused2d.hip -- fused phase-space pass (x-transport, y-transport, G-hat,
-// relaxation and heat-flux tensor in one read of G^n and one write of G^{n+1}).
+// mm_fused2d.hip -- the fused 2D phase-space pass: x-transport (G^n -> G*),
+// y-transport (G* -> G**), G-hat, backward-Euler relaxation and the heat-flux
+// tensor in one read of G^n and one write of G^{n+1}.
+//
+// Paper: Rossmanith & Sar, arXiv:2509.21832, Sec. 5.3 (eqs. zmicrox ..
+// update-micro-2D-ydir, eqn5-97, eqn5-97more, eqn5-98), eqn5-99, and the wall
+// form of G-hat of Sec. 6.3.
+//
+// Mapping on gfx950:
+//   - one 64-wide wavefront owns one spatial column i and marches up a segment
+//     of rows j; a lane owns NPT velocity nodes p = lane + 64 m of every cell;
+//   - the y-sweep of row j needs G* of rows j-1, j, j+1, so the wavefront keeps
+//     a three-row window of G* in registers and computes G* of row j+1 (the
+//     x-sweep, which needs the x-neighbour cells of the same row) just before
+//     it finishes row j;
+//   - every velocity moment is a wavefront reduction (transposed butterfly of
+//     cross-lane shuffles, totals read back as scalars), so the waves of a
+//     workgroup never wait for each other;
+//   - the Maxwellian of a cell is separable, M = [rho/(2 pi T) e1(k)] e2(l): each
+//     wavefront keeps per-cell tables of e1, e2 in its own LDS slice;
+//   - the ES term (G - M)/eps is evaluated as M expm1(delta)/eps, with delta
+//     the (small) difference of the two exponents, so no cancellation occurs.
+// G may be stored in FP64 (TS = double, arithmetic in FP64) or FP32
+// (TS = float, per-node arithmetic in FP32); velocity sums are always FP64.
 #include "mm_device.h"
 #include "mm_launch.h"
 
 namespace mm {
 
-bool fused_supported(const Params &, int) { return false; }
+namespace {
 
-void launch_micro_fused2d(const void *, void *, double *, const double *, const double *, const Params &, int,
-                          hipStream_t)
+constexpr int WPG = 4;        // wavefronts per workgroup (one column each)
+constexpr int MAXV = 64;      // largest nv1, nv2 of the fused pass
+
+__device__ __forceinline__ double bcast(double v, int lane)
 {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+    return __hiloint2double(hi, lo);
+}
+
+// One halving step of the wavefront sum below: lanes with bit `o` set keep
+// the upper H partial sums, the others the lower H, and each adds its
+// partner's copy of the half it keeps.
+template <int H>
+__device__ __forceinline__ void fold(double *a, int o, int lane)
+{
+    const bool up = (lane & o) != 0;
+#pragma unroll
+    for (int k = 0; k < H; ++k) {
+        const double keep = up ? a[k + H] : a[k];
+        const double send = up ? a[k] : a[k + H];
+        a[k] = keep + __shfl_xor(send, o, 64);
+    }
+}
+
+// Sum N doubles (N a power of two, <= 16) over the wavefront.  A halving step
+// exchanges n/2 values instead of n; after log2(N) of them lane L holds partial
+// sum number L >> (6 - log2 N), the remaining xor steps finish the sums, and
+// the totals are read back as wave-uniform values.
+template <int N>
+__device__ __forceinline__ void wave_sum(double (&v)[N], int lane)
+{
+    static_assert(N == 1 || N == 2 || N == 4 || N == 8 || N == 16, "power of two <= 16");
+    double a[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) a[k] = v[k];
+    if constexpr (N >= 2) fold<N / 2>(a, 32, lane);
+    if constexpr (N >= 4) fold<N / 4>(a, 16, lane);
+    if constexpr (N >= 8) fold<N / 8>(a, 8, lane);
+    if constexpr (N >= 16) fold<N / 16>(a, 4, lane);
+#pragma unroll
+    for (int o = 32 / N; o >= 1; o >>= 1) a[0] += __shfl_xor(a[0], o, 64);
+#pragma unroll
+    for (int q = 0; q < N; ++q) v[q] = bcast(a[0], q * (64 / N));
+}
+
+__device__ __forceinline__ float t_exp(float x) { return expf(x); }
+__device__ __forceinline__ double t_exp(double x) { return exp(x); }
+__device__ __forceinline__ float t_expm1(float x) { return expm1f(x); }
+__device__ __forceinline__ double t_expm1(double x) { return expm1(x); }
+
+// Per-cell coefficients (wave-uniform), converted to the compute type
+template <typename TC>
+struct Cell {
+    TC u1, u2, i2T, iT, itau, ieps, s11, s12, dTx, dTy;
+    TC dA, dB, dC, lg;         // ES exponent difference: delta = lg - (dA w1^2 + 2 dB w1 w2 + dC w2^2)
+    double P0[10];
+    double u1d, u2d, rsTd, i2Td, ra, rb;
+};
+
+template <typename TC>
+__device__ __forceinline__ void load_cell(const double *R, Cell<TC> &c)
+{
+    c.u1d = R[R_U1];
+    c.u2d = R[R_U2];
+    c.rsTd = R[R_RST];
+    c.i2Td = R[R_I2T];
+    c.u1 = (TC)c.u1d;
+    c.u2 = (TC)c.u2d;
+    c.i2T = (TC)c.i2Td;
+    c.iT = (TC)R[R_IT];
+    c.itau = (TC)R[R_ITAU];
+    c.ieps = (TC)R[R_IEPS];
+    c.s11 = (TC)R[R_S11];
+    c.s12 = (TC)R[R_S12];
+    c.dTx = (TC)R[R_DTX];
+    c.dTy = (TC)R[R_DTY];
+    c.dA = (TC)R[R_DA];
+    c.dB = (TC)R[R_QB];
+    c.dC = (TC)R[R_DC];
+    c.lg = (TC)R[R_LG];
+#pragma unroll
+    for (int q = 0; q < 10; ++q) c.P0[q] = R[R_P0 + q];
+    c.ra = R[R_A];
+    c.rb = R[R_B];
+}
+
+// Projection coefficients from raw moments s = sum (1, v1, v2, |v|^2) F:
+// returns (c0, c1, c2, c3) with Pi F = (c0 + c1 v1 + c2 v2 + c3 |v|^2) M.
+template <typename TC>
+__device__ __forceinline__ void proj_poly(const Cell<TC> &c, const double *s, TC out[4])
+{
+    const double u1 = c.u1d, u2 = c.u2d, rsT = c.rsTd, i2T = c.i2Td;
+    // moments against the basis phi = (1, w1/sqrt T, w2/sqrt T, |w|^2/(2T) - 1)
+    const double sw1 = s[1] - u1 * s[0], sw2 = s[2] - u2 * s[0];
+    const double sww = s[3] - 2.0 * u1 * s[1] - 2.0 * u2 * s[2] + (u1 * u1 + u2 * u2) * s[0];
+    const double b[4] = {s[0], rsT * sw1, rsT * sw2, i2T * sww - s[0]};
+    double A[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        double v = 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v += c.P0[sym4(a, q)] * b[q];
+        A[a] = v;
+    }
+    // sum_a A_a phi_a as a polynomial in v
+    const double c3 = A[3] * i2T;
+    out[3] = (TC)c3;
+    out[1] = (TC)(A[1] * rsT - 2.0 * c3 * u1);
+    out[2] = (TC)(A[2] * rsT - 2.0 * c3 * u2);
+    out[0] = (TC)(A[0] - A[1] * rsT * u1 - A[2] * rsT * u2 + c3 * (u1 * u1 + u2 * u2) - A[3]);
+}
+
+template <typename TS, typename TC, int NPT>
+struct Pass {
+    const TS *__restrict__ G;
+    TS *__restrict__ Gn;
+    double *__restrict__ H;
+    const double *__restrict__ rec;
+    const double *__restrict__ wrec;
+    const Params *P;
+    const double2 *sv;    // per-node (v1, v2) in LDS
+    const int2 *skl;      // per-node (k, l) in LDS
+    double *tab;          // this wavefront's Maxwellian tables: 3 slots x 2 x MAXV
+    int lane, i;
+
+    __device__ __forceinline__ TC maxw_tab(int slot, int m) const
+    {
+        const int2 kl = skl[lane + 64 * m];
+        const double *t = tab + slot * 2 * MAXV;
+        return (TC)(t[kl.x] * t[MAXV + kl.y]);
+    }
+
+    __device__ __forceinline__ void build_tables(int slot, const double *R) const
+    {
+        const double u1 = R[R_U1], u2 = R[R_U2], i2T = R[R_I2T], mpre = R[R_MPRE];
+        double *t = tab + slot * 2 * MAXV;
+        if (lane < P->nv1) {
+            const double w = P->v1_lo + (lane + 0.5) * P->dv1 - u1;
+            t[lane] = mpre * exp(-w * w * i2T);
+        }
+        if (lane < P->nv2) {
+            const double w = P->v2_lo + (lane + 0.5) * P->dv2 - u2;
+            t[MAXV + lane] = exp(-w * w * i2T);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+
+    __device__ __forceinline__ void load(size_t cell, TC (&out)[NPT]) const
+    {
+        const TS *g = G + cell * (size_t)P->nv;
+#pragma unroll
+        for (int m = 0; m < NPT; ++m) {
+            const int p = lane + 64 * m;
+            out[m] = p < P->nv ? (TC)g[p] : (TC)0;
+        }
+    }
+
+    // x-sweep of row r: G*(i, r) into out; tables of cell (i, r) go to `slot`
+    __device__ __forceinline__ void xsweep(int r, int slot, TC (&out)[NPT]) const
+    {
+        const size_t c = (size_t)r * P->nx + i;
+        const double *R = rec + c * REC;
+        build_tables(slot, R);
+        TC gc[NPT], Z[NPT];
+        {
+            TC gm[NPT], gp[NPT];
+            load(c, gc);
+            // x neighbours with the boundary ghosts of Sec. 5.3.1 / 5.3.2 / 6.3
+            if (i > 0) load(c - 1, gm);
+            else if (P->bc[0].kind == BC_PERIODIC) load(c + P->nx - 1, gm);
+            else {
+                const bool open = is_open(P->bc[0].kind);
+#pragma unroll
+                for (int m = 0; m < NPT; ++m) gm[m] = open ? (TC)0 : gc[m];
+            }
+            if (i < P->nx - 1) load(c + 1, gp);
+            else if (P->bc[1].kind == BC_PERIODIC) load(c - (P->nx - 1), gp);
+            else {
+                const bool open = is_open(P->bc[1].kind);
+#pragma unroll
+                for (int m = 0; m < NPT; ++m) gp[m] = open ? (TC)0 : gc[m];
+            }
+            const TC idx = (TC)(1.0 / P->dx);
+#pragma unroll
+            for (int m = 0; m < NPT; ++m) {
+                const TC v1 = (TC)sv[lane + 64 * m].x;
+                Z[m] = (fmin(v1, (TC)0) * (gp[m] - gc[m]) + fmax(v1, (TC)0) * (gc[m] - gm[m])) * idx;
+            }
+        }
+        double s[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int m = 0; m < NPT; ++m) {
+            const double2 v = sv[lane + 64 * m];
+            const double z = (double)Z[m];
+            s[0] += z;
+            s[1] += v.x * z;
+            s[2] += v.y * z;
+            s[3] += (v.x * v.x + v.y * v.y) * z;
+        }
+        wave_sum<4>(s, lane);
+        Cell<TC> cl;
+        load_cell(R, cl);
+        TC cp[4];
+        proj_poly(cl, s, cp);
+        const TC dt = (TC)P->dt;
+#pragma unroll
+        for (int m = 0; m < NPT; ++m) {
+            const double2 v = sv[lane + 64 * m];
+            const TC v1 = (TC)v.x, v2 = (TC)v.y;
+            const TC poly = cp[0] + cp[1] * v1 + cp[2] * v2 + cp[3] * (v1 * v1 + v2 * v2);
+            const TC M = maxw_tab(slot, m);
+            out[m] = gc[m] + dt * (poly * M - Z[m]);
+        }
+    }
+
+    __device__ __forceinline__ TC zy(int m, const TC (&lo)[NPT], const TC (&ce)[NPT], const TC (&hi)[NPT],
+                                     TC idy) const
+    {
+        const TC v2 = (TC)sv[lane + 64 * m].y;
+        return (fmin(v2, (TC)0) * (hi[m] - ce[m]) + fmax(v2, (TC)0) * (ce[m] - lo[m])) * idy;
+    }
+
+    // y-sweep, G-hat, relaxation and H for row j with window (lo, ce, hi)
+    template <bool WALL>
+    __device__ __forceinline__ void finish_row(size_t c, int slot, const TC (&lo)[NPT], const TC (&ce)[NPT],
+                                               const TC (&hi)[NPT]) const
+    {
+        const double *R = rec + c * REC;
+        Cell<TC> cl;
+        load_cell(R, cl);
+        const bool discrete = P->proj_mode == PROJ_DISCRETE;
+        const bool es_on = !WALL || P->wall_es_term;
+        const TC idy = (TC)(1.0 / P->dy);
+        constexpr int NS = WALL ? 16 : 8;
+        TC base[NPT];
+        TC mup[WALL ? NPT : 1];
+        double s[NS];
+#pragma unroll
+        for (int q = 0; q < NS; ++q) s[q] = 0.0;
+        TC nb[16];
+        if (WALL) {
+#pragma unroll
+            for (int t = 0; t < 16; ++t) nb[t] = (TC)wrec[c * WREC + t];
+        }
+#pragma unroll
+        for (int m = 0; m < NPT; ++m) {
+            const double2 v = sv[lane + 64 * m];
+            const TC v1 = (TC)v.x, v2 = (TC)v.y;
+            const TC M = maxw_tab(slot, m);
+            const TC w1 = v1 - cl.u1, w2 = v2 - cl.u2;
+            const TC w11 = w1 * w1, w22 = w2 * w2, w12 = w1 * w2;
+            TC es = (TC)0;
+            if (es_on) {
+                const TC delta = cl.lg - (cl.dA * w11 + (TC)2 * cl.dB * w12 + cl.dC * w22);
+                es = M * t_expm1(delta) * cl.ieps;
+            }
+            if (!WALL) {
+                // interior G-hat (eqn5-97): -(1/tau)(B:sigma + C.gradT) M + (G - M)/eps
+                const TC Bs = (cl.s11 * (w11 - w22) + (TC)2 * cl.s12 * w12) * cl.i2T;
+                const TC CgT = ((w11 + w22) * cl.i2T - (TC)2) * cl.iT * (w1 * cl.dTx + w2 * cl.dTy);
+                base[m] = -cl.itau * (Bs + CgT) * M + es;
+            } else {
+                // wall cells: upwind v.grad M with ghost Maxwellians (Sec. 6.3)
+                base[m] = es;
+                TC Mn[4];
+#pragma unroll
+                for (int d = 0; d < 4; ++d) {
+                    const TC a1 = v1 - nb[4 * d + 1], a2 = v2 - nb[4 * d + 2];
+                    Mn[d] = nb[4 * d] * t_exp(-(a1 * a1 + a2 * a2) * nb[4 * d + 3]);
+                }
+                mup[WALL ? m : 0] = (fmin(v1, (TC)0) * (Mn[1] - M) + fmax(v1, (TC)0) * (M - Mn[0])) *
+                                        (TC)(1.0 / P->dx) +
+                                    (fmin(v2, (TC)0) * (Mn[3] - M) + fmax(v2, (TC)0) * (M - Mn[2])) * idy;
+            }
+            const double vsq = v.x * v.x + v.y * v.y;
+            const double z = (double)zy(m, lo, ce, hi, idy), b = (double)base[m];
+            s[0] += z; s[1] += v.x * z; s[2] += v.y * z; s[3] += vsq * z;
+            s[4] += b; s[5] += v.x * b; s[6] += v.y * b; s[7] += vsq * b;
+            if (WALL) {
+                const double u = (double)mup[WALL ? m : 0];
+                s[8] += u; s[9] += v.x * u; s[10] += v.y * u; s[11] += vsq * u;
+            }
+        }
+        wave_sum<NS>(s, lane);
+        TC cz[4], cb[4], cm[4] = {(TC)0, (TC)0, (TC)0, (TC)0};
+        proj_poly(cl, s, cz);
+        if (discrete) proj_poly(cl, s + 4, cb);
+        else cb[0] = cb[1] = cb[2] = cb[3] = (TC)0;
+        if (WALL) proj_poly(cl, s + 8, cm);
+        const TC dt = (TC)P->dt, ra = (TC)cl.ra, rb = (TC)cl.rb;
+        TS *gout = Gn + c * (size_t)P->nv;
+        double h[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int m = 0; m < NPT; ++m) {
+            const int p = lane + 64 * m;
+            const double2 v = sv[p];
+            const TC v1 = (TC)v.x, v2 = (TC)v.y, vsq = v1 * v1 + v2 * v2;
+            const TC M = maxw_tab(slot, m);
+            const TC pz = cz[0] + cz[1] * v1 + cz[2] * v2 + cz[3] * vsq;
+            const TC pb = cb[0] + cb[1] * v1 + cb[2] * v2 + cb[3] * vsq;
+            const TC gss = ce[m] + dt * (pz * M - zy(m, lo, ce, hi, idy));
+            TC gh = base[m] - pb * M;
+            if (WALL) {
+                const TC pm = cm[0] + cm[1] * v1 + cm[2] * v2 + cm[3] * vsq;
+                gh -= cl.itau * (mup[WALL ? m : 0] - pm * M);
+            }
+            const TS gn = (TS)(ra * gss + rb * gh);
+            if (p < P->nv) gout[p] = gn;
+            const double g = (double)gn, w1 = v.x - cl.u1d, w2 = v.y - cl.u2d;
+            const double g11 = g * w1 * w1, g22 = g * w2 * w2;
+            h[0] += g11 * w1;
+            h[1] += g11 * w2;
+            h[2] += g22 * w1;
+            h[3] += g22 * w2;
+        }
+        wave_sum<4>(h, lane);
+        if (lane == 0) {
+            const double f = P->eps * P->dv1 * P->dv2;
+            for (int a = 0; a < 4; ++a) H[c * 4 + a] = f * h[a];
+        }
+    }
+
+    // ghost row of the window beyond a y side that is not periodic
+    __device__ __forceinline__ void ghost(int kind, const TC (&own)[NPT], TC (&dst)[NPT]) const
+    {
+        const bool open = is_open(kind);
+#pragma unroll
+        for (int m = 0; m < NPT; ++m) dst[m] = open ? (TC)0 : own[m];
+    }
+
+    // one row: G* of row j+1 into win[HI], then finish row j
+    template <int LO, int CE, int HI>
+    __device__ __forceinline__ void step(int j, TC (&win)[3][NPT]) const
+    {
+        if (j + 1 < P->ny) xsweep(j + 1, (j + 1) & 1, win[HI]);
+        else if (P->bc[3].kind == BC_PERIODIC) xsweep(0, 2, win[HI]);
+        else ghost(P->bc[3].kind, win[CE], win[HI]);
+        const size_t c = (size_t)j * P->nx + i;
+        if (rec[c * REC + R_WALL] != 0.0) finish_row<true>(c, j & 1, win[LO], win[CE], win[HI]);
+        else finish_row<false>(c, j & 1, win[LO], win[CE], win[HI]);
+    }
+};
+
+// Geometry of the launch: columns are grouped WPG to a workgroup; rows are cut
+// into segments of `seg` rows.  Workgroup b works on tile t(b), where tiles
+// that share halo columns get consecutive ids on the same XCD (dispatch puts
+// workgroup b on XCD b mod 8).
+struct Geom {
+    int ncg, nseg, seg, ntiles;
+};
+
+__device__ __forceinline__ int tile_of(int b, int ntiles)
+{
+    const int per = (ntiles + 7) / 8;
+    return (b % 8) * per + b / 8;   // >= ntiles for padding workgroups
+}
+
+template <typename TS, typename TC, int NPT>
+__global__ __launch_bounds__(64 * WPG, (sizeof(TC) * NPT <= 32 ? 2 : 1)) void k_fused2d(const TS *__restrict__ G, TS *__restrict__ Gn,
+                                                         double *__restrict__ H, const double *__restrict__ rec,
+                                                         const double *__restrict__ wrec,
+                                                         const Params *__restrict__ Pd, Geom geo)
+{
+    const Params &P = *Pd;
+    __shared__ double2 s_v[64 * NPT];
+    __shared__ int2 s_kl[64 * NPT];
+    __shared__ double s_tab[WPG][3 * 2 * MAXV];
+    for (int p = threadIdx.x; p < 64 * NPT; p += 64 * WPG) {
+        const int k = p < P.nv ? p % P.nv1 : 0, l = p < P.nv ? p / P.nv1 : 0;
+        s_v[p] = p < P.nv ? make_double2(P.v1_lo + (k + 0.5) * P.dv1, P.v2_lo + (l + 0.5) * P.dv2)
+                          : make_double2(0.0, 0.0);
+        s_kl[p] = make_int2(k, l);
+    }
+    __syncthreads();
+    const int t = tile_of(blockIdx.x, geo.ntiles);
+    if (t >= geo.ntiles) return;
+    const int cg = t % geo.ncg, sg = t / geo.ncg;
+    const int wv = threadIdx.x >> 6;
+    Pass<TS, TC, NPT> ps;
+    ps.G = G; ps.Gn = Gn; ps.H = H; ps.rec = rec; ps.wrec = wrec; ps.P = Pd;
+    ps.sv = s_v; ps.skl = s_kl; ps.tab = s_tab[wv];
+    ps.lane = threadIdx.x & 63;
+    ps.i = cg * WPG + wv;
+    if (ps.i >= P.nx) return;
+    const int j0 = sg * geo.seg, j1 = min(P.ny, j0 + geo.seg);
+
+    TC win[3][NPT];
+    // prologue: window rows (j0 - 1, j0) in win[0], win[1]
+    ps.xsweep(j0, j0 & 1, win[1]);
+    if (j0 > 0) ps.xsweep(j0 - 1, 2, win[0]);
+    else if (P.bc[2].kind == BC_PERIODIC) ps.xsweep(P.ny - 1, 2, win[0]);
+    else ps.ghost(P.bc[2].kind, win[1], win[0]);
+    for (int j = j0; j < j1; j += 3) {
+        ps.template step<0, 1, 2>(j, win);
+        if (j + 1 < j1) ps.template step<1, 2, 0>(j + 1, win);
+        if (j + 2 < j1) ps.template step<2, 0, 1>(j + 2, win);
+    }
+}
+
+template <typename TS, typename TC>
+bool launch_npt(int npt, const void *G, void *Gn, double *H, const double *rec, const double *wrec,
+                const Params *Pd, const Geom &geo, hipStream_t st)
+{
+    const dim3 grid(((geo.ntiles + 7) / 8) * 8), block(64 * WPG);
+#define MM_CASE(N)                                                                                           \
+    case N:                                                                                                  \
+        hipLaunchKernelGGL((k_fused2d<TS, TC, N>), grid, block, 0, st, (const TS *)G, (TS *)Gn, H, rec, wrec, \
+                           Pd, geo);                                                                          \
+        return true;
+    switch (npt) {
+        MM_CASE(1)
+        MM_CASE(2)
+        MM_CASE(3)
+        MM_CASE(4)
+        MM_CASE(6)
+        MM_CASE(8)
+        MM_CASE(9)
+        MM_CASE(12)
+        MM_CASE(16)
+    default:
+        return false;
+    }
+#undef MM_CASE
+}
+
+int npt_for(int nv)
+{
+    static const int opts[] = {1, 2, 3, 4, 6, 8, 9, 12, 16};
+    const int need = (nv + 63) / 64;
+    for (int o : opts)
+        if (o >= need) return o;
+    return 0;
+}
+
+Geom geometry(const Params &P)
+{
+    Geom g;
+    g.ncg = (P.nx + WPG - 1) / WPG;
+    // aim for >= 4 workgroups per CU on 256 CUs, segments of at least 16 rows
+    const int nseg = (4 * 256 + g.ncg - 1) / g.ncg;
+    int seg = (P.ny + nseg - 1) / nseg;
+    if (seg < 16) seg = 16;
+    if (seg > P.ny) seg = P.ny;
+    g.seg = seg;
+    g.nseg = (P.ny + seg - 1) / seg;
+    g.ntiles = g.ncg * g.nseg;
+    return g;
+}
+
+} // namespace
+
+bool fused_supported(const Params &P, int precision)
+{
+    (void)precision;
+    if (P.nv1 > MAXV || P.nv2 > MAXV) return false;
+    return npt_for(P.nv) != 0;
+}
+
+void launch_micro_fused2d(const void *G, void *Gn, double *H, const double *rec, const double *wrec,
+                          const Params &P, const Params *Pd, int precision, hipStream_t st)
+{
+    const int npt = npt_for(P.nv);
+    const Geom geo = geometry(P);
+    if (precision == 0) launch_npt<double, double>(npt, G, Gn, H, rec, wrec, Pd, geo, st);
+    else launch_npt<float, float>(npt, G, Gn, H, rec, wrec, Pd, geo, st);
 }
 
 } // namespace mm

@@ -30,6 +30,7 @@ struct mm_ctx {
     bool own_stream = false;
     double *Q = nullptr, *Qs = nullptr, *H = nullptr, *rec = nullptr, *wrec = nullptr, *gmom = nullptr;
     double *Gs = nullptr;          // G* scratch of the reference (unfused) 2D pass
+    mm::Params *Pd = nullptr;      // device copy of P (read by the fused pass)
     void *G[2] = {nullptr, nullptr};
     int gbytes = 8, cur = 0;
     int *flag = nullptr;
@@ -129,6 +130,7 @@ void release(mm_ctx *c)
     for (void *g : c->G)
         if (g) hipFree(g);
     if (c->flag) hipFree(c->flag);
+    if (c->Pd) hipFree(c->Pd);
     if (c->own_stream && c->st) hipStreamDestroy(c->st);
     delete c;
 }
@@ -220,7 +222,7 @@ int enqueue_steps(mm_ctx *c, int nsteps)
             {
                 Timer t(c, 0);
                 if (c->fused)
-                    mm::launch_micro_fused2d(c->G[c->cur], c->G[1 - c->cur], c->H, c->rec, c->wrec, P,
+                    mm::launch_micro_fused2d(c->G[c->cur], c->G[1 - c->cur], c->H, c->rec, c->wrec, P, c->Pd,
                                              c->cfg.precision, c->st);
                 else
                     mm::launch_micro_ref2d((const double *)c->G[c->cur], c->Gs, (double *)c->G[1 - c->cur], c->H,
@@ -356,10 +358,15 @@ int mm_init(const mm_config *cfg, const double *q0, const double *g0, mm_ctx **o
         ok = hipMalloc(&c->rec, sizeof(double) * mm::REC * ncell) == hipSuccess &&
              hipMalloc(&c->wrec, sizeof(double) * mm::WREC * ncell) == hipSuccess;
     if (ok && cfg->dim == 2 && !c->fused) ok = hipMalloc(&c->Gs, sizeof(double) * npts) == hipSuccess;
+    if (ok && c->fused) ok = hipMalloc(&c->Pd, sizeof(mm::Params)) == hipSuccess;
     if (!ok) {
         hipGetLastError();
         release(c);
         return MM_ENOMEM;
+    }
+    if (c->Pd && hipMemcpy(c->Pd, &c->P, sizeof(mm::Params), hipMemcpyHostToDevice) != hipSuccess) {
+        release(c);
+        return MM_EDEVICE;
     }
     rc = upload_state(c, q0, g0);
     if (rc) {

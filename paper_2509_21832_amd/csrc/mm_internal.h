@@ -54,9 +54,13 @@ enum {
     R_WALL,               // 1 for cells that use the wall form of G-hat
     R_ITAU,               // 1 / tau
     R_IEPS,               // 1 / eps
-    REC = 32
+    R_IT,                 // 1 / T
+    R_LG,                 // log(GPRE / MPRE) = log(T / sqrt(det calT))
+    R_DA, R_DC,           // QA - 1/(2T), QC - 1/(2T): ES exponent minus Maxwellian exponent
+    REC = 40
 };
-// wall cells: (rho, u1, u2, T) of the four neighbour Maxwellians (x-, x+, y-, y+)
+// wall cells: the four neighbour Maxwellians (x-, x+, y-, y+), each as
+// (rho / (2 pi T), u1, u2, 1 / (2T))
 enum { WREC = 16 };
 
 // index of the symmetric 4x4 entry (a, b) in the packed R_P0 block

@@ -112,6 +112,10 @@ __global__ void k_prep2d(const double *__restrict__ Q, double *__restrict__ rec,
     R[R_QA] = S22 / (2.0 * det);
     R[R_QB] = -S12 / (2.0 * det);
     R[R_QC] = S11 / (2.0 * det);
+    R[R_IT] = 1.0 / s.T;
+    R[R_LG] = log(s.T / sqrt(det));
+    R[R_DA] = R[R_QA] - R[R_I2T];
+    R[R_DC] = R[R_QC] - R[R_I2T];
 
     // projection coefficients
     const double dA = P.dv1 * P.dv2;
@@ -181,7 +185,10 @@ __global__ void k_prep2d(const double *__restrict__ Q, double *__restrict__ rec,
             } else {
                 g[0] = nb[d]->rho; g[1] = nb[d]->u1; g[2] = nb[d]->u2; g[3] = nb[d]->T;
             }
-            for (int t = 0; t < 4; ++t) Wr[4 * d + t] = g[t];
+            Wr[4 * d + 0] = g[0] / (2.0 * MM_PI * g[3]);
+            Wr[4 * d + 1] = g[1];
+            Wr[4 * d + 2] = g[2];
+            Wr[4 * d + 3] = 1.0 / (2.0 * g[3]);
         }
     }
 }
@@ -246,10 +253,11 @@ __global__ __launch_bounds__(64 * NW) void k_micro_x2d(const double *__restrict_
     }
 }
 
-__device__ __forceinline__ double maxw(double rho, double u1, double u2, double T, double v1, double v2)
+// Maxwellian from (rho / (2 pi T), u1, u2, 1 / (2T))
+__device__ __forceinline__ double maxw(double pre, double u1, double u2, double i2T, double v1, double v2)
 {
     const double w1 = v1 - u1, w2 = v2 - u2;
-    return rho / (2.0 * MM_PI * T) * exp(-(w1 * w1 + w2 * w2) / (2.0 * T));
+    return pre * exp(-(w1 * w1 + w2 * w2) * i2T);
 }
 
 // y-transport (micro-2D-split-2), G-hat (eqn5-97 / wall form), relaxation

@@ -13,8 +13,9 @@ void launch_gmom2d(const void *G, int g_bytes, const double *rec, double *out, c
 
 // fused phase-space pass; returns false when the shape is not supported
 bool fused_supported(const Params &P, int precision);
+// P: host copy of the parameters; Pd: the same parameters in device memory
 void launch_micro_fused2d(const void *G, void *Gn, double *H, const double *rec, const double *wrec,
-                          const Params &P, int precision, hipStream_t st);
+                          const Params &P, const Params *Pd, int precision, hipStream_t st);
 
 // 1D
 void launch_step1d(const double *Q, double *Qn, const double *G, double *Gn, double *H, int *flag, int step,

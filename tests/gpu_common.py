@@ -1,6 +1,7 @@
 """Helpers of the GPU parity tests: run the HIP path (through the C ABI) and
 the oracle on the same seeded inputs and compare element by element."""
 import math
+import os
 import sys
 
 import numpy as np
@@ -13,9 +14,20 @@ def log(msg):
     sys.stdout.flush()
 
 
-def run_gpu(p, Q, G, nsteps, chunks=1):
+def run_gpu(p, Q, G, nsteps, chunks=1, reference=False):
+    """Run the HIP path.  reference=True selects the unfused phase-space pass
+    (the library reads MM_REFERENCE_PASS when a context is created)."""
     from paper_2509_21832_amd import binding as B
-    with B.Solver(p, Q, G) as s:
+    old = os.environ.pop("MM_REFERENCE_PASS", None)
+    if reference:
+        os.environ["MM_REFERENCE_PASS"] = "1"
+    try:
+        s = B.Solver(p, Q, G)
+    finally:
+        os.environ.pop("MM_REFERENCE_PASS", None)
+        if old is not None:
+            os.environ["MM_REFERENCE_PASS"] = old
+    with s:
         per = nsteps // chunks
         done = 0
         while done < nsteps:
@@ -57,7 +69,7 @@ def compare(p, Q0, Qg, Gg, Hg, Qo, Go, Ho, q_l1=1e-12, q_el=1e-11, g_rel=1e-10, 
     el = np.abs(Qg - Qo) / (np.abs(Qo) + scale)
     gtol = g_rel * np.abs(Go).max() + 1e-13 * maxwell_scale(p, Q0) / p["eps"]
     gerr = np.abs(Gg - Go).max()
-    htol = 1e-9 * np.abs(Ho).max() + 1e-12 * gtol * p["eps"]
+    htol = max(1e-9, 10 * g_rel) * np.abs(Ho).max() + 1e-12 * gtol * p["eps"]
     herr = np.abs(Hg - Ho).max()
     log(f"[{label}] Q rel-L1 {e1:.3e}  Q max el {el.max():.3e}  G max abs {gerr:.3e} (tol {gtol:.2e})"
         f"  H max abs {herr:.3e} (tol {htol:.2e})")
@@ -69,9 +81,15 @@ def compare(p, Q0, Qg, Gg, Hg, Qo, Go, Ho, q_l1=1e-12, q_el=1e-11, g_rel=1e-10, 
     return e1
 
 
-def parity(p, Q, G, nsteps, label="", chunks=1, **tol):
+MIXED_TOL = dict(q_l1=1e-5, q_el=1e-4, g_rel=1e-4)
+
+
+def parity(p, Q, G, nsteps, label="", chunks=1, reference=False, **tol):
     log(f"[{label}] start: nx={p['nx']} ny={p.get('ny', 1)} nv={p['nv1']}x{p.get('nv2', 1)} "
-        f"steps={nsteps} eps={p['eps']} precision={p.get('precision', 'fp64')}")
-    Qg, Gg, Hg = run_gpu(p, Q, G, nsteps, chunks)
+        f"steps={nsteps} eps={p['eps']} precision={p.get('precision', 'fp64')} reference={reference}")
+    if p.get("precision", "fp64") != "fp64":
+        for k, v in MIXED_TOL.items():
+            tol.setdefault(k, v)
+    Qg, Gg, Hg = run_gpu(p, Q, G, nsteps, chunks, reference)
     Qo, Go, Ho = oracle.run(p, Q.reshape(-1), G.reshape(-1), nsteps)
     return compare(p, Q, Qg, Gg, Hg, Qo, Go, Ho, label=label, **tol)

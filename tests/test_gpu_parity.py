@@ -42,8 +42,34 @@ SMALL = {
 
 @pytest.mark.parametrize("name", sorted(SMALL))
 def test_small_2d(name):
+    """The launch configuration of the benchmark: fused phase-space pass."""
     p, Q, G = SMALL[name]()
     parity(p, Q, G, 30, label=name)
+
+
+@pytest.mark.parametrize("name", ["walls_quadrant", "lid_cavity", "periodic_paper_proj", "inflow_mixed_sides",
+                                  "extrap_nu_minus1", "walls_nonsquare_v"])
+def test_small_2d_reference_pass(name):
+    """The unfused phase-space pass (one workgroup per cell), used for shapes the fused pass
+    does not cover."""
+    p, Q, G = SMALL[name]()
+    parity(p, Q, G, 30, label=name + "_ref", reference=True)
+
+
+def test_large_velocity_grid_uses_reference_pass():
+    """nv1 > 64 is outside the fused pass; the library falls back to the unfused pass."""
+    p, Q, G = W.quadrant2d(seed=15, nx=6, ny=5, nv=12, eps=0.1)
+    p["nv1"], p["v1"] = 72, (-9.0, 9.0)
+    parity(p, Q, W.zero_g(p), 10, label="nv1_72")
+
+
+@pytest.mark.parametrize("name", ["walls_quadrant", "lid_cavity", "periodic_smooth", "inflow_mixed_sides",
+                                  "small_eps", "walls_paper_proj"])
+def test_small_2d_mixed(name):
+    """g stored in FP32: macro rel-L1 <= 1e-5 against the FP64 oracle."""
+    p, Q, G = SMALL[name]()
+    p["precision"] = "mixed"
+    parity(p, Q, G, 30, label=name + "_mixed")
 
 
 def test_small_2d_nonzero_g0():
@@ -86,9 +112,10 @@ def test_c3_full_two_steps_from_nonzero_g():
     parity(p, Qo, Go, 1, label="c3_developed")
 
 
-def test_c3_full_100_steps_vs_golden():
-    """Config 3, 100 steps, all four eps: macro rel-L1 <= 1e-12 against the oracle's
-    stored result (tests/golden/make_c3_reference.py)."""
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("mixed", 1e-5)])
+def test_c3_full_100_steps_vs_golden(precision, tol):
+    """Config 3, 100 steps, all four eps: macro rel-L1 against the oracle's stored
+    result (tests/golden/make_c3_reference.py): <= 1e-12 in FP64, <= 1e-5 with g in FP32."""
     import os
     path = os.path.join(os.path.dirname(__file__), "golden", "c3_cavity_100steps.npz")
     ref = np.load(path)
@@ -96,12 +123,13 @@ def test_c3_full_100_steps_vs_golden():
     for eps in (1e-3, 1e-2, 1e-1, 1.0):
         key = f"eps{eps:g}"
         p, Q, G = W.cavity2d(seed=0, eps=eps)
-        log(f"[c3_100 {key}] start")
+        p["precision"] = precision
+        log(f"[c3_100 {key} {precision}] start")
         Qg, Gg, Hg = run_gpu(p, Q, G, int(ref["steps"]), chunks=4)
         Qg = Qg.reshape(p["ny"], p["nx"], 6)
         e = rel_l1(Qg[::st, ::st, :], ref[key + "_sample"])
         sums = Qg.reshape(-1, 6).sum(0)
         es = np.abs(sums - ref[key + "_sum"]) / ref[key + "_abssum"]
-        log(f"[c3_100 {key}] sampled Q rel-L1 {e:.3e}; domain sums rel {es.max():.3e}")
-        assert e <= 1e-12
-        assert es.max() <= 1e-12
+        log(f"[c3_100 {key} {precision}] sampled Q rel-L1 {e:.3e}; domain sums rel {es.max():.3e}")
+        assert e <= tol
+        assert es.max() <= tol
