@@ -19,128 +19,21 @@
 //   - the Maxwellian of a cell is separable, M = [rho/(2 pi T) e1(k)] e2(l): each
 //     wavefront keeps per-cell tables of e1, e2 in its own LDS slice;
 //   - the ES term (G - M)/eps is evaluated as M expm1(delta)/eps, with delta
-//     the (small) difference of the two exponents, so no cancellation occurs.
+//     the (small) difference of the two exponents, so no cancellation occurs;
+//   - wall-adjacent cells get G** only; k_wall_relax2d finishes them with the
+//     wall form of G-hat (Sec. 6.3), the relaxation and H.
 // G may be stored in FP64 (TS = double, arithmetic in FP64) or FP32
 // (TS = float, per-node arithmetic in FP32); velocity sums are always FP64.
-#include "mm_device.h"
+#include <cstdlib>
+
+#include "mm_fused_common.h"
 #include "mm_launch.h"
 
 namespace mm {
 
 namespace {
 
-constexpr int WPG = 4;        // wavefronts per workgroup (one column each)
-constexpr int MAXV = 64;      // largest nv1, nv2 of the fused pass
-
-__device__ __forceinline__ double bcast(double v, int lane)
-{
-    const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
-    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
-    return __hiloint2double(hi, lo);
-}
-
-// One halving step of the wavefront sum below: lanes with bit `o` set keep
-// the upper H partial sums, the others the lower H, and each adds its
-// partner's copy of the half it keeps.
-template <int H>
-__device__ __forceinline__ void fold(double *a, int o, int lane)
-{
-    const bool up = (lane & o) != 0;
-#pragma unroll
-    for (int k = 0; k < H; ++k) {
-        const double keep = up ? a[k + H] : a[k];
-        const double send = up ? a[k] : a[k + H];
-        a[k] = keep + __shfl_xor(send, o, 64);
-    }
-}
-
-// Sum N doubles (N a power of two, <= 16) over the wavefront.  A halving step
-// exchanges n/2 values instead of n; after log2(N) of them lane L holds partial
-// sum number L >> (6 - log2 N), the remaining xor steps finish the sums, and
-// the totals are read back as wave-uniform values.
-template <int N>
-__device__ __forceinline__ void wave_sum(double (&v)[N], int lane)
-{
-    static_assert(N == 1 || N == 2 || N == 4 || N == 8 || N == 16, "power of two <= 16");
-    double a[N];
-#pragma unroll
-    for (int k = 0; k < N; ++k) a[k] = v[k];
-    if constexpr (N >= 2) fold<N / 2>(a, 32, lane);
-    if constexpr (N >= 4) fold<N / 4>(a, 16, lane);
-    if constexpr (N >= 8) fold<N / 8>(a, 8, lane);
-    if constexpr (N >= 16) fold<N / 16>(a, 4, lane);
-#pragma unroll
-    for (int o = 32 / N; o >= 1; o >>= 1) a[0] += __shfl_xor(a[0], o, 64);
-#pragma unroll
-    for (int q = 0; q < N; ++q) v[q] = bcast(a[0], q * (64 / N));
-}
-
-__device__ __forceinline__ float t_exp(float x) { return expf(x); }
-__device__ __forceinline__ double t_exp(double x) { return exp(x); }
-__device__ __forceinline__ float t_expm1(float x) { return expm1f(x); }
-__device__ __forceinline__ double t_expm1(double x) { return expm1(x); }
-
-// Per-cell coefficients (wave-uniform), converted to the compute type
-template <typename TC>
-struct Cell {
-    TC u1, u2, i2T, iT, itau, ieps, s11, s12, dTx, dTy;
-    TC dA, dB, dC, lg;         // ES exponent difference: delta = lg - (dA w1^2 + 2 dB w1 w2 + dC w2^2)
-    double P0[10];
-    double u1d, u2d, rsTd, i2Td, ra, rb;
-};
-
-template <typename TC>
-__device__ __forceinline__ void load_cell(const double *R, Cell<TC> &c)
-{
-    c.u1d = R[R_U1];
-    c.u2d = R[R_U2];
-    c.rsTd = R[R_RST];
-    c.i2Td = R[R_I2T];
-    c.u1 = (TC)c.u1d;
-    c.u2 = (TC)c.u2d;
-    c.i2T = (TC)c.i2Td;
-    c.iT = (TC)R[R_IT];
-    c.itau = (TC)R[R_ITAU];
-    c.ieps = (TC)R[R_IEPS];
-    c.s11 = (TC)R[R_S11];
-    c.s12 = (TC)R[R_S12];
-    c.dTx = (TC)R[R_DTX];
-    c.dTy = (TC)R[R_DTY];
-    c.dA = (TC)R[R_DA];
-    c.dB = (TC)R[R_QB];
-    c.dC = (TC)R[R_DC];
-    c.lg = (TC)R[R_LG];
-#pragma unroll
-    for (int q = 0; q < 10; ++q) c.P0[q] = R[R_P0 + q];
-    c.ra = R[R_A];
-    c.rb = R[R_B];
-}
-
-// Projection coefficients from raw moments s = sum (1, v1, v2, |v|^2) F:
-// returns (c0, c1, c2, c3) with Pi F = (c0 + c1 v1 + c2 v2 + c3 |v|^2) M.
-template <typename TC>
-__device__ __forceinline__ void proj_poly(const Cell<TC> &c, const double *s, TC out[4])
-{
-    const double u1 = c.u1d, u2 = c.u2d, rsT = c.rsTd, i2T = c.i2Td;
-    // moments against the basis phi = (1, w1/sqrt T, w2/sqrt T, |w|^2/(2T) - 1)
-    const double sw1 = s[1] - u1 * s[0], sw2 = s[2] - u2 * s[0];
-    const double sww = s[3] - 2.0 * u1 * s[1] - 2.0 * u2 * s[2] + (u1 * u1 + u2 * u2) * s[0];
-    const double b[4] = {s[0], rsT * sw1, rsT * sw2, i2T * sww - s[0]};
-    double A[4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-        double v = 0.0;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) v += c.P0[sym4(a, q)] * b[q];
-        A[a] = v;
-    }
-    // sum_a A_a phi_a as a polynomial in v
-    const double c3 = A[3] * i2T;
-    out[3] = (TC)c3;
-    out[1] = (TC)(A[1] * rsT - 2.0 * c3 * u1);
-    out[2] = (TC)(A[2] * rsT - 2.0 * c3 * u2);
-    out[0] = (TC)(A[0] - A[1] * rsT * u1 - A[2] * rsT * u2 + c3 * (u1 * u1 + u2 * u2) - A[3]);
-}
+using namespace fused;
 
 template <typename TS, typename TC, int NPT>
 struct Pass {
@@ -254,8 +147,39 @@ struct Pass {
         return (fmin(v2, (TC)0) * (hi[m] - ce[m]) + fmax(v2, (TC)0) * (ce[m] - lo[m])) * idy;
     }
 
-    // y-sweep, G-hat, relaxation and H for row j with window (lo, ce, hi)
-    template <bool WALL>
+    // y-sweep of a wall-adjacent cell: G** only (the wall G-hat, relaxation and
+    // H of these cells are done by k_wall_relax2d afterwards)
+    __device__ __forceinline__ void wall_row(size_t c, int slot, const TC (&lo)[NPT], const TC (&ce)[NPT],
+                                             const TC (&hi)[NPT]) const
+    {
+        const double *R = rec + c * REC;
+        Cell<TC> cl;
+        load_cell(R, cl);
+        const TC idy = (TC)(1.0 / P->dy);
+        double s[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int m = 0; m < NPT; ++m) {
+            const double2 v = sv[lane + 64 * m];
+            const double z = (double)zy(m, lo, ce, hi, idy);
+            s[0] += z; s[1] += v.x * z; s[2] += v.y * z; s[3] += (v.x * v.x + v.y * v.y) * z;
+        }
+        wave_sum<4>(s, lane);
+        TC cz[4];
+        proj_poly(cl, s, cz);
+        const TC dt = (TC)P->dt;
+        TS *gout = Gn + c * (size_t)P->nv;
+#pragma unroll
+        for (int m = 0; m < NPT; ++m) {
+            const int p = lane + 64 * m;
+            const double2 v = sv[p];
+            const TC v1 = (TC)v.x, v2 = (TC)v.y;
+            const TC pz = cz[0] + cz[1] * v1 + cz[2] * v2 + cz[3] * (v1 * v1 + v2 * v2);
+            const TC gss = ce[m] + dt * (pz * maxw_tab(slot, m) - zy(m, lo, ce, hi, idy));
+            if (p < P->nv) gout[p] = (TS)gss;
+        }
+    }
+
+    // y-sweep, G-hat (eqn5-97), relaxation and H for interior row j with window (lo, ce, hi)
     __device__ __forceinline__ void finish_row(size_t c, int slot, const TC (&lo)[NPT], const TC (&ce)[NPT],
                                                const TC (&hi)[NPT]) const
     {
@@ -263,19 +187,11 @@ struct Pass {
         Cell<TC> cl;
         load_cell(R, cl);
         const bool discrete = P->proj_mode == PROJ_DISCRETE;
-        const bool es_on = !WALL || P->wall_es_term;
         const TC idy = (TC)(1.0 / P->dy);
-        constexpr int NS = WALL ? 16 : 8;
         TC base[NPT];
-        TC mup[WALL ? NPT : 1];
-        double s[NS];
+        double s[8];
 #pragma unroll
-        for (int q = 0; q < NS; ++q) s[q] = 0.0;
-        TC nb[16];
-        if (WALL) {
-#pragma unroll
-            for (int t = 0; t < 16; ++t) nb[t] = (TC)wrec[c * WREC + t];
-        }
+        for (int q = 0; q < 8; ++q) s[q] = 0.0;
 #pragma unroll
         for (int m = 0; m < NPT; ++m) {
             const double2 v = sv[lane + 64 * m];
@@ -283,44 +199,20 @@ struct Pass {
             const TC M = maxw_tab(slot, m);
             const TC w1 = v1 - cl.u1, w2 = v2 - cl.u2;
             const TC w11 = w1 * w1, w22 = w2 * w2, w12 = w1 * w2;
-            TC es = (TC)0;
-            if (es_on) {
-                const TC delta = cl.lg - (cl.dA * w11 + (TC)2 * cl.dB * w12 + cl.dC * w22);
-                es = M * t_expm1(delta) * cl.ieps;
-            }
-            if (!WALL) {
-                // interior G-hat (eqn5-97): -(1/tau)(B:sigma + C.gradT) M + (G - M)/eps
-                const TC Bs = (cl.s11 * (w11 - w22) + (TC)2 * cl.s12 * w12) * cl.i2T;
-                const TC CgT = ((w11 + w22) * cl.i2T - (TC)2) * cl.iT * (w1 * cl.dTx + w2 * cl.dTy);
-                base[m] = -cl.itau * (Bs + CgT) * M + es;
-            } else {
-                // wall cells: upwind v.grad M with ghost Maxwellians (Sec. 6.3)
-                base[m] = es;
-                TC Mn[4];
-#pragma unroll
-                for (int d = 0; d < 4; ++d) {
-                    const TC a1 = v1 - nb[4 * d + 1], a2 = v2 - nb[4 * d + 2];
-                    Mn[d] = nb[4 * d] * t_exp(-(a1 * a1 + a2 * a2) * nb[4 * d + 3]);
-                }
-                mup[WALL ? m : 0] = (fmin(v1, (TC)0) * (Mn[1] - M) + fmax(v1, (TC)0) * (M - Mn[0])) *
-                                        (TC)(1.0 / P->dx) +
-                                    (fmin(v2, (TC)0) * (Mn[3] - M) + fmax(v2, (TC)0) * (M - Mn[2])) * idy;
-            }
+            const TC delta = cl.lg - (cl.dA * w11 + (TC)2 * cl.dB * w12 + cl.dC * w22);
+            const TC es = M * t_expm1(delta) * cl.ieps;
+            const TC Bs = (cl.s11 * (w11 - w22) + (TC)2 * cl.s12 * w12) * cl.i2T;
+            const TC CgT = ((w11 + w22) * cl.i2T - (TC)2) * cl.iT * (w1 * cl.dTx + w2 * cl.dTy);
+            base[m] = -cl.itau * (Bs + CgT) * M + es;
             const double vsq = v.x * v.x + v.y * v.y;
             const double z = (double)zy(m, lo, ce, hi, idy), b = (double)base[m];
             s[0] += z; s[1] += v.x * z; s[2] += v.y * z; s[3] += vsq * z;
             s[4] += b; s[5] += v.x * b; s[6] += v.y * b; s[7] += vsq * b;
-            if (WALL) {
-                const double u = (double)mup[WALL ? m : 0];
-                s[8] += u; s[9] += v.x * u; s[10] += v.y * u; s[11] += vsq * u;
-            }
         }
-        wave_sum<NS>(s, lane);
-        TC cz[4], cb[4], cm[4] = {(TC)0, (TC)0, (TC)0, (TC)0};
+        wave_sum<8>(s, lane);
+        TC cz[4], cb[4] = {(TC)0, (TC)0, (TC)0, (TC)0};
         proj_poly(cl, s, cz);
         if (discrete) proj_poly(cl, s + 4, cb);
-        else cb[0] = cb[1] = cb[2] = cb[3] = (TC)0;
-        if (WALL) proj_poly(cl, s + 8, cm);
         const TC dt = (TC)P->dt, ra = (TC)cl.ra, rb = (TC)cl.rb;
         TS *gout = Gn + c * (size_t)P->nv;
         double h[4] = {0.0, 0.0, 0.0, 0.0};
@@ -333,11 +225,7 @@ struct Pass {
             const TC pz = cz[0] + cz[1] * v1 + cz[2] * v2 + cz[3] * vsq;
             const TC pb = cb[0] + cb[1] * v1 + cb[2] * v2 + cb[3] * vsq;
             const TC gss = ce[m] + dt * (pz * M - zy(m, lo, ce, hi, idy));
-            TC gh = base[m] - pb * M;
-            if (WALL) {
-                const TC pm = cm[0] + cm[1] * v1 + cm[2] * v2 + cm[3] * vsq;
-                gh -= cl.itau * (mup[WALL ? m : 0] - pm * M);
-            }
+            const TC gh = base[m] - pb * M;
             const TS gn = (TS)(ra * gss + rb * gh);
             if (p < P->nv) gout[p] = gn;
             const double g = (double)gn, w1 = v.x - cl.u1d, w2 = v.y - cl.u2d;
@@ -370,24 +258,10 @@ struct Pass {
         else if (P->bc[3].kind == BC_PERIODIC) xsweep(0, 2, win[HI]);
         else ghost(P->bc[3].kind, win[CE], win[HI]);
         const size_t c = (size_t)j * P->nx + i;
-        if (rec[c * REC + R_WALL] != 0.0) finish_row<true>(c, j & 1, win[LO], win[CE], win[HI]);
-        else finish_row<false>(c, j & 1, win[LO], win[CE], win[HI]);
+        if (rec[c * REC + R_WALL] != 0.0) wall_row(c, j & 1, win[LO], win[CE], win[HI]);
+        else finish_row(c, j & 1, win[LO], win[CE], win[HI]);
     }
 };
-
-// Geometry of the launch: columns are grouped WPG to a workgroup; rows are cut
-// into segments of `seg` rows.  Workgroup b works on tile t(b), where tiles
-// that share halo columns get consecutive ids on the same XCD (dispatch puts
-// workgroup b on XCD b mod 8).
-struct Geom {
-    int ncg, nseg, seg, ntiles;
-};
-
-__device__ __forceinline__ int tile_of(int b, int ntiles)
-{
-    const int per = (ntiles + 7) / 8;
-    return (b % 8) * per + b / 8;   // >= ntiles for padding workgroups
-}
 
 template <typename TS, typename TC, int NPT>
 __global__ __launch_bounds__(64 * WPG, (sizeof(TC) * NPT <= 32 ? 2 : 1)) void k_fused2d(const TS *__restrict__ G, TS *__restrict__ Gn,
@@ -424,11 +298,14 @@ __global__ __launch_bounds__(64 * WPG, (sizeof(TC) * NPT <= 32 ? 2 : 1)) void k_
     if (j0 > 0) ps.xsweep(j0 - 1, 2, win[0]);
     else if (P.bc[2].kind == BC_PERIODIC) ps.xsweep(P.ny - 1, 2, win[0]);
     else ps.ghost(P.bc[2].kind, win[1], win[0]);
-    for (int j = j0; j < j1; j += 3) {
+    int j = j0;
+    for (; j + 3 <= j1; j += 3) {
         ps.template step<0, 1, 2>(j, win);
-        if (j + 1 < j1) ps.template step<1, 2, 0>(j + 1, win);
-        if (j + 2 < j1) ps.template step<2, 0, 1>(j + 2, win);
+        ps.template step<1, 2, 0>(j + 1, win);
+        ps.template step<2, 0, 1>(j + 2, win);
     }
+    if (j < j1) ps.template step<0, 1, 2>(j, win);
+    if (j + 1 < j1) ps.template step<1, 2, 0>(j + 1, win);
 }
 
 template <typename TS, typename TC>
@@ -466,21 +343,6 @@ int npt_for(int nv)
     return 0;
 }
 
-Geom geometry(const Params &P)
-{
-    Geom g;
-    g.ncg = (P.nx + WPG - 1) / WPG;
-    // aim for >= 4 workgroups per CU on 256 CUs, segments of at least 16 rows
-    const int nseg = (4 * 256 + g.ncg - 1) / g.ncg;
-    int seg = (P.ny + nseg - 1) / nseg;
-    if (seg < 16) seg = 16;
-    if (seg > P.ny) seg = P.ny;
-    g.seg = seg;
-    g.nseg = (P.ny + seg - 1) / seg;
-    g.ntiles = g.ncg * g.nseg;
-    return g;
-}
-
 } // namespace
 
 bool fused_supported(const Params &P, int precision)
@@ -493,10 +355,13 @@ bool fused_supported(const Params &P, int precision)
 void launch_micro_fused2d(const void *G, void *Gn, double *H, const double *rec, const double *wrec,
                           const Params &P, const Params *Pd, int precision, hipStream_t st)
 {
-    const int npt = npt_for(P.nv);
-    const Geom geo = geometry(P);
-    if (precision == 0) launch_npt<double, double>(npt, G, Gn, H, rec, wrec, Pd, geo, st);
-    else launch_npt<float, float>(npt, G, Gn, H, rec, wrec, Pd, geo, st);
+    const Geom geo = geometry(P, 2);
+    if (std::getenv("MM_GENERIC_FUSED") || !launch_micro_lk2d(G, Gn, H, rec, wrec, P, Pd, precision, geo, st)) {
+        const int npt = npt_for(P.nv);
+        if (precision == 0) launch_npt<double, double>(npt, G, Gn, H, rec, wrec, Pd, geo, st);
+        else launch_npt<float, float>(npt, G, Gn, H, rec, wrec, Pd, geo, st);
+    }
+    launch_wall_relax2d(Gn, precision == 0 ? 8 : 4, H, rec, wrec, P, st);
 }
 
 } // namespace mm

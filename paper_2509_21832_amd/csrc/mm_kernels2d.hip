@@ -494,6 +494,97 @@ __global__ __launch_bounds__(256) void k_gmom2d(const TG *__restrict__ G, const 
 }
 
 // ---------------------------------------------------------------------------
+// wall-adjacent cells after a fused pass: Gn holds G** there.  This kernel
+// applies the wall form of G-hat (Sec. 6.3: -(1/tau)(I - Pi)[upwind v.grad M
+// with ghost Maxwellians] + (G - M)/eps), the relaxation (eqn5-98) and H
+// (eqn5-99), in FP64 for both storage types.  One workgroup per cell of the
+// boundary ring; cells that are not wall cells return at once.
+
+__device__ __forceinline__ void ring_cell(const Params &P, int r, int &i, int &j)
+{
+    if (r < P.nx) { i = r; j = 0; return; }
+    r -= P.nx;
+    if (r < P.nx) { i = r; j = P.ny - 1; return; }
+    r -= P.nx;
+    if (r < P.ny - 2) { i = 0; j = r + 1; return; }
+    r -= P.ny - 2;
+    i = P.nx - 1;
+    j = r + 1;
+}
+
+template <typename TS>
+__global__ __launch_bounds__(256) void k_wall_relax2d(TS *__restrict__ Gn, double *__restrict__ H,
+                                                      const double *__restrict__ rec,
+                                                      const double *__restrict__ wrec, Params P)
+{
+    __shared__ double lds[4 * 8];
+    int i, j;
+    ring_cell(P, blockIdx.x, i, j);
+    const size_t c = (size_t)j * P.nx + i;
+    const double *R = rec + c * REC;
+    if (R[R_WALL] == 0.0) return;
+    const double u1 = R[R_U1], u2 = R[R_U2], rsT = R[R_RST], i2T = R[R_I2T], mpre = R[R_MPRE];
+    const double dA = R[R_DA], dB = R[R_QB], dC = R[R_DC], lg = R[R_LG], ieps = R[R_IEPS], itau = R[R_ITAU];
+    const bool es_on = P.wall_es_term != 0, discrete = P.proj_mode == PROJ_DISCRETE;
+    double nb[16];
+    for (int t = 0; t < 16; ++t) nb[t] = wrec[c * WREC + t];
+    TS *g = Gn + c * (size_t)P.nv;
+    auto point = [&](int p, double &M, double &es, double &mup, double &w1, double &w2) {
+        const int k = p % P.nv1, l = p / P.nv1;
+        const double v1 = P.v1_lo + (k + 0.5) * P.dv1, v2 = P.v2_lo + (l + 0.5) * P.dv2;
+        w1 = v1 - u1;
+        w2 = v2 - u2;
+        M = mpre * exp(-(w1 * w1 + w2 * w2) * i2T);
+        es = es_on ? M * expm1(lg - (dA * w1 * w1 + 2.0 * dB * w1 * w2 + dC * w2 * w2)) * ieps : 0.0;
+        double Mn[4];
+        for (int d = 0; d < 4; ++d) {
+            const double a1 = v1 - nb[4 * d + 1], a2 = v2 - nb[4 * d + 2];
+            Mn[d] = nb[4 * d] * exp(-(a1 * a1 + a2 * a2) * nb[4 * d + 3]);
+        }
+        mup = (fmin(v1, 0.0) * (Mn[1] - M) + fmax(v1, 0.0) * (M - Mn[0])) / P.dx +
+              (fmin(v2, 0.0) * (Mn[3] - M) + fmax(v2, 0.0) * (M - Mn[2])) / P.dy;
+    };
+    double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int p = threadIdx.x; p < P.nv; p += 256) {
+        double M, es, mup, w1, w2;
+        point(p, M, es, mup, w1, w2);
+        const double f[4] = {1.0, w1 * rsT, w2 * rsT, (w1 * w1 + w2 * w2) * i2T - 1.0};
+        for (int a = 0; a < 4; ++a) {
+            s[a] += f[a] * mup;
+            s[4 + a] += f[a] * es;
+        }
+    }
+    block_sum<8, 4>(s, lds);
+    double AM[4], AE[4];
+    proj_coef(R, s, AM);
+    proj_coef(R, s + 4, AE);
+    if (!discrete)
+        for (int a = 0; a < 4; ++a) AE[a] = 0.0;
+    const double ra = R[R_A], rb = R[R_B];
+    double h[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int p = threadIdx.x; p < P.nv; p += 256) {
+        double M, es, mup, w1, w2;
+        point(p, M, es, mup, w1, w2);
+        const double f1 = w1 * rsT, f2 = w2 * rsT, f3 = (w1 * w1 + w2 * w2) * i2T - 1.0;
+        const double PM = (AM[0] + AM[1] * f1 + AM[2] * f2 + AM[3] * f3) * M;
+        const double PE = (AE[0] + AE[1] * f1 + AE[2] * f2 + AE[3] * f3) * M;
+        const double gh = -itau * (mup - PM) + (es - PE);
+        const TS gn = (TS)(ra * (double)g[p] + rb * gh);
+        g[p] = gn;
+        const double gv = (double)gn;
+        h[0] += w1 * w1 * w1 * gv;
+        h[1] += w1 * w1 * w2 * gv;
+        h[2] += w1 * w2 * w2 * gv;
+        h[3] += w2 * w2 * w2 * gv;
+    }
+    block_sum<4, 4>(h, lds);
+    if (threadIdx.x == 0) {
+        const double f = P.eps * P.dv1 * P.dv2;
+        for (int a = 0; a < 4; ++a) H[c * 4 + a] = f * h[a];
+    }
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 
 void launch_prep2d(const double *Q, double *rec, double *wrec, int *flag, int step, const Params &P, hipStream_t st)
@@ -515,6 +606,19 @@ void launch_macro2d(double *Q, double *Qs, const double *H, int *flag, int step,
     const int n = P.nx * P.ny;
     hipLaunchKernelGGL(k_macro2d<0>, dim3((n + 127) / 128), dim3(128), 0, st, Q, H, Qs, flag, step, P);
     hipLaunchKernelGGL(k_macro2d<1>, dim3((n + 127) / 128), dim3(128), 0, st, Qs, H, Q, flag, step, P);
+}
+
+void launch_wall_relax2d(void *Gn, int g_bytes, double *H, const double *rec, const double *wrec, const Params &P,
+                         hipStream_t st)
+{
+    bool any = false;
+    for (int s = 0; s < 4; ++s) any = any || is_open(P.bc[s].kind);
+    if (!any) return;
+    const int n = 2 * P.nx + 2 * (P.ny - 2);
+    if (g_bytes == 8)
+        hipLaunchKernelGGL(k_wall_relax2d<double>, dim3(n), dim3(256), 0, st, (double *)Gn, H, rec, wrec, P);
+    else
+        hipLaunchKernelGGL(k_wall_relax2d<float>, dim3(n), dim3(256), 0, st, (float *)Gn, H, rec, wrec, P);
 }
 
 void launch_gmom2d(const void *G, int g_bytes, const double *rec, double *out, const Params &P, hipStream_t st)

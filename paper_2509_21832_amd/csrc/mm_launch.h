@@ -11,7 +11,11 @@ void launch_micro_ref2d(const double *G, double *Gs, double *Gn, double *H, cons
 void launch_macro2d(double *Q, double *Qs, const double *H, int *flag, int step, const Params &P, hipStream_t st);
 void launch_gmom2d(const void *G, int g_bytes, const double *rec, double *out, const Params &P, hipStream_t st);
 
-// fused phase-space pass; returns false when the shape is not supported
+// wall-adjacent cells after a fused pass (Gn holds G** there)
+void launch_wall_relax2d(void *Gn, int g_bytes, double *H, const double *rec, const double *wrec, const Params &P,
+                         hipStream_t st);
+
+// fused phase-space pass (including the wall-cell kernel); false when the shape is not supported
 bool fused_supported(const Params &P, int precision);
 // P: host copy of the parameters; Pd: the same parameters in device memory
 void launch_micro_fused2d(const void *G, void *Gn, double *H, const double *rec, const double *wrec,
