@@ -178,12 +178,17 @@ int mm_failed_step(const mm_ctx *ctx);
 const char *mm_strerror(int status);
 
 /*
- * Kernel timing (HIP events on the context's stream around every launch of
- * the phase-space pass).  mm_timing(ctx, 1) enables and resets the counters;
- * mm_timing_get() returns the number of timed launches and their summed
- * duration in milliseconds for kernel class `which`:
- *   0 = phase-space (micro) pass, 1 = per-cell preparation, 2 = macro sweeps.
+ * Kernel timing (HIP events recorded on the context's stream around every
+ * kernel launch of a step).  mm_timing(ctx, 1) enables and resets the
+ * counters; mm_timing_get() returns the number of timed launches and their
+ * summed duration in milliseconds for kernel class `which`:
+ *   0 = phase-space (micro) pass: the fused kernel, or both sweeps of the
+ *       unfused pass, or the whole 1D step,
+ *   1 = per-cell preparation, 2 = macro sweeps,
+ *   3 = wall-adjacent cells after a fused pass.
+ * Any other `which` gives MM_EINVAL.
  */
+#define MM_TIMING_CLASSES 4
 int mm_timing(mm_ctx *ctx, int enable);
 int mm_timing_get(mm_ctx *ctx, int which, int *count, double *total_ms);
 

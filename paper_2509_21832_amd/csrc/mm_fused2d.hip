@@ -283,7 +283,7 @@ __global__ __launch_bounds__(64 * WPG, (sizeof(TC) * NPT <= 32 ? 2 : 1)) void k_
     const int t = tile_of(blockIdx.x, geo.ntiles);
     if (t >= geo.ntiles) return;
     const int cg = t % geo.ncg, sg = t / geo.ncg;
-    const int wv = threadIdx.x >> 6;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform: cell indices live in SGPRs
     Pass<TS, TC, NPT> ps;
     ps.G = G; ps.Gn = Gn; ps.H = H; ps.rec = rec; ps.wrec = wrec; ps.P = Pd;
     ps.sv = s_v; ps.skl = s_kl; ps.tab = s_tab[wv];
@@ -355,13 +355,14 @@ bool fused_supported(const Params &P, int precision)
 void launch_micro_fused2d(const void *G, void *Gn, double *H, const double *rec, const double *wrec,
                           const Params &P, const Params *Pd, int precision, hipStream_t st)
 {
-    const Geom geo = geometry(P, 2);
-    if (std::getenv("MM_GENERIC_FUSED") || !launch_micro_lk2d(G, Gn, H, rec, wrec, P, Pd, precision, geo, st)) {
+    // MM_GENERIC_FUSED (read per launch) forces the generic kernel, so that its
+    // parity can be tested on shapes the lane-k kernel also covers
+    if (std::getenv("MM_GENERIC_FUSED") || !launch_micro_lk2d(G, Gn, H, rec, wrec, P, Pd, precision, st)) {
+        const Geom geo = geometry(P, 2);
         const int npt = npt_for(P.nv);
         if (precision == 0) launch_npt<double, double>(npt, G, Gn, H, rec, wrec, Pd, geo, st);
         else launch_npt<float, float>(npt, G, Gn, H, rec, wrec, Pd, geo, st);
     }
-    launch_wall_relax2d(Gn, precision == 0 ? 8 : 4, H, rec, wrec, P, st);
 }
 
 } // namespace mm

@@ -15,8 +15,6 @@
 //     recurrence r(m+1) = r(m) q(m), q(m+1) = q(m) kappa (FP64), or exp m1 of a
 //     directly evaluated delta (FP32), so there is no per-node exponential in
 //     the FP64 pass.
-#include <cstdlib>
-
 #include "mm_fused_common.h"
 #include "mm_launch.h"
 
@@ -26,7 +24,7 @@ namespace {
 
 using namespace fused;
 
-template <typename TS, typename TC, int NPT, bool PF>
+template <typename TS, typename TC, int NPT, bool RC>
 struct PassLK {
     const TS *__restrict__ G;
     TS *__restrict__ Gn;
@@ -38,8 +36,6 @@ struct PassLK {
     int lane, i, k, l0, L;
     double v1d, v2bd, hd;   // v1 of this lane; v2(m) = v2b + m h
     TC v1, ax, bx, v2b, h, idy;
-    // next row's G (centre, x-1, x+1), loaded while the current row is finished
-    TC pfc[PF ? NPT : 1], pfm[PF ? NPT : 1], pfp[PF ? NPT : 1];
 
     __device__ __forceinline__ TC v2(int m) const { return v2b + (TC)m * h; }
     __device__ __forceinline__ double v2d(int m) const { return v2bd + (double)m * hd; }
@@ -75,22 +71,8 @@ struct PassLK {
         for (int m = 0; m < NPT; ++m) out[m] = (TC)g[64 * m];
     }
 
-    // issue the loads of row r (centre and x neighbours) into the prefetch registers
-    __device__ __forceinline__ void prefetch(int r)
-    {
-        if constexpr (PF) {
-            const size_t c = (size_t)r * P->nx + i;
-            load(c, pfc);
-            if (i > 0) load(c - 1, pfm);
-            else if (P->bc[0].kind == BC_PERIODIC) load(c + P->nx - 1, pfm);
-            if (i < P->nx - 1) load(c + 1, pfp);
-            else if (P->bc[1].kind == BC_PERIODIC) load(c - (P->nx - 1), pfp);
-        }
-    }
-
     // x-sweep of row r: G*(i, r) into out; tables of cell (i, r) go to `slot`.
-    // With `pre` the rows come from the prefetch registers (filled by prefetch(r)).
-    __device__ __forceinline__ void xsweep(int r, int slot, TC (&out)[NPT], bool pre = false) const
+    __device__ __forceinline__ void xsweep(int r, int slot, TC (&out)[NPT]) const
     {
         const size_t c = (size_t)r * P->nx + i;
         const double *R = rec + c * REC;
@@ -98,20 +80,11 @@ struct PassLK {
         TC gc[NPT], Z[NPT];
         {
             TC gm[NPT], gp[NPT];
-            if (PF && pre) {
-#pragma unroll
-                for (int m = 0; m < NPT; ++m) {
-                    gc[m] = pfc[PF ? m : 0];
-                    gm[m] = pfm[PF ? m : 0];
-                    gp[m] = pfp[PF ? m : 0];
-                }
-            } else {
-                load(c, gc);
-                if (i > 0) load(c - 1, gm);
-                else if (P->bc[0].kind == BC_PERIODIC) load(c + P->nx - 1, gm);
-                if (i < P->nx - 1) load(c + 1, gp);
-                else if (P->bc[1].kind == BC_PERIODIC) load(c - (P->nx - 1), gp);
-            }
+            load(c, gc);
+            if (i > 0) load(c - 1, gm);
+            else if (P->bc[0].kind == BC_PERIODIC) load(c + P->nx - 1, gm);
+            if (i < P->nx - 1) load(c + 1, gp);
+            else if (P->bc[1].kind == BC_PERIODIC) load(c - (P->nx - 1), gp);
             if (i == 0 && P->bc[0].kind != BC_PERIODIC) {
                 const bool open = is_open(P->bc[0].kind);
 #pragma unroll
@@ -148,6 +121,80 @@ struct PassLK {
             const TC w = v2(m);
             const TC pm = (cp[3] * w + cp[2]) * w + K;
             out[m] = gc[m] + dt * (pm * maxw(t, E1, m) - Z[m]);
+        }
+    }
+
+    // Same x-sweep in chunks of CH nodes without holding G and Z of the whole
+    // cell: the second pass reloads the chunk (L1/L2 hits) and recomputes Z.
+    static constexpr int CH = NPT < 8 ? NPT : 8;
+
+    __device__ __forceinline__ void load_chunk(size_t cell, int m0, TC (&out)[CH]) const
+    {
+        const TS *g = G + cell * (size_t)(64 * NPT) + lane + 64 * m0;
+#pragma unroll
+        for (int m = 0; m < CH; ++m) out[m] = (TC)g[64 * m];
+    }
+
+    __device__ __forceinline__ void zx_chunk(size_t c, int m0, TC (&gc)[CH], TC (&Z)[CH]) const
+    {
+        TC gm[CH], gp[CH];
+        load_chunk(c, m0, gc);
+        if (i > 0) load_chunk(c - 1, m0, gm);
+        else if (P->bc[0].kind == BC_PERIODIC) load_chunk(c + P->nx - 1, m0, gm);
+        else {
+            const bool open = is_open(P->bc[0].kind);
+#pragma unroll
+            for (int m = 0; m < CH; ++m) gm[m] = open ? (TC)0 : gc[m];
+        }
+        if (i < P->nx - 1) load_chunk(c + 1, m0, gp);
+        else if (P->bc[1].kind == BC_PERIODIC) load_chunk(c - (P->nx - 1), m0, gp);
+        else {
+            const bool open = is_open(P->bc[1].kind);
+#pragma unroll
+            for (int m = 0; m < CH; ++m) gp[m] = open ? (TC)0 : gc[m];
+        }
+#pragma unroll
+        for (int m = 0; m < CH; ++m) Z[m] = ax * (gp[m] - gc[m]) + bx * (gc[m] - gm[m]);
+    }
+
+    __device__ __forceinline__ void xsweep_rc(int r, int slot, TC (&out)[NPT]) const
+    {
+        const size_t c = (size_t)r * P->nx + i;
+        const double *R = rec + c * REC;
+        build_tables(slot, R);
+        double t0 = 0.0, t2 = 0.0, t22 = 0.0;
+#pragma unroll
+        for (int m0 = 0; m0 < NPT; m0 += CH) {
+            TC gc[CH], Z[CH];
+            zx_chunk(c, m0, gc, Z);
+#pragma unroll
+            for (int m = 0; m < CH; ++m) {
+                const double z = (double)Z[m], w = v2d(m0 + m), u = w * z;
+                t0 += z;
+                t2 += u;
+                t22 += w * u;
+            }
+        }
+        double s[4] = {t0, v1d * t0, t2, v1d * v1d * t0 + t22};
+        wave_sum<4>(s, lane);
+        Cell<TC> cl;
+        load_cell(R, cl);
+        TC cp[4];
+        proj_poly(cl, s, cp);
+        const TC K = cp[0] + cp[1] * v1 + cp[3] * v1 * v1;
+        const double *t = slot_tab(slot);
+        const TC E1 = (TC)t[k];
+        const TC dt = (TC)P->dt;
+#pragma unroll
+        for (int m0 = 0; m0 < NPT; m0 += CH) {
+            TC gc[CH], Z[CH];
+            zx_chunk(c, m0, gc, Z);
+#pragma unroll
+            for (int m = 0; m < CH; ++m) {
+                const TC w = v2(m0 + m);
+                const TC pm = (cp[3] * w + cp[2]) * w + K;
+                out[m0 + m] = gc[m] + dt * (pm * maxw(t, E1, m0 + m) - Z[m]);
+            }
         }
     }
 
@@ -290,6 +337,122 @@ struct PassLK {
         }
     }
 
+    // y-sweep, G-hat (eqn5-97), relaxation and H for interior row j with window (lo, ce, hi)
+    __device__ __forceinline__ void finish_row_rc(size_t c, int slot, const TC (&lo)[NPT], const TC (&ce)[NPT],
+                                               const TC (&hi)[NPT]) const
+    {
+        const double *R = rec + c * REC;
+        Cell<TC> cl;
+        load_cell(R, cl);
+        const bool discrete = P->proj_mode == PROJ_DISCRETE;
+        const double *t = slot_tab(slot);
+        const TC E1 = (TC)t[k];
+        const double a = v1d - cl.u1d;              // w1 of this lane
+        const double w2b = v2bd - cl.u2d;           // w2 at m = 0
+        // closed form of G-hat (eqn5-97) as a cubic in w2, times -1/tau
+        TC C0, C1, C2, C3;
+        {
+            const double i2T = R[R_I2T], iT = R[R_IT], itau = R[R_ITAU];
+            const double s11 = R[R_S11], s12 = R[R_S12], dTx = R[R_DTX], dTy = R[R_DTY];
+            const double q = a * a * i2T - 2.0;
+            C0 = (TC)(-itau * (s11 * a * a * i2T + iT * q * a * dTx));
+            C1 = (TC)(-itau * (2.0 * s12 * a * i2T + iT * q * dTy));
+            C2 = (TC)(-itau * (-s11 * i2T + iT * i2T * a * dTx));
+            C3 = (TC)(-itau * (iT * i2T * dTy));
+        }
+        // ES term: delta(m) = lg - (dA w1^2 + 2 dB w1 w2(m) + dC w2(m)^2)
+        const double dA = R[R_DA], dB = R[R_QB], dC = R[R_DC], lg = R[R_LG];
+        double r = 0.0, q = 0.0, kq = 0.0;
+        TC A0 = (TC)0, Bq = (TC)0, Cq = (TC)0;
+        if constexpr (sizeof(TC) == 8) {
+            const double d0 = lg - (dA * a * a + 2.0 * dB * a * w2b + dC * w2b * w2b);
+            const double d1 = -(2.0 * dB * a * hd + dC * (2.0 * w2b * hd + hd * hd));
+            r = exp(d0);
+            q = exp(d1);
+            kq = exp(-2.0 * dC * hd * hd);
+        } else {
+            A0 = (TC)(lg - dA * a * a);
+            Bq = (TC)(-2.0 * dB * a);
+            Cq = (TC)(-dC);
+        }
+        const TC u2 = cl.u2, ieps = cl.ieps;
+        const double r0 = r, q0 = q;
+        double acc[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+        for (int m = 0; m < NPT; ++m) {
+            const TC w = v2(m), w2 = w - u2;
+            const TC zyv = w * idy * (w < (TC)0 ? hi[m] - ce[m] : ce[m] - lo[m]);
+            const TC M = maxw(t, E1, m);
+            TC es;
+            if constexpr (sizeof(TC) == 8) {
+                es = (TC)(r - 1.0) * M * ieps;
+                r *= q;
+                q *= kq;
+            } else {
+                es = M * expm1f(A0 + (Bq + Cq * w2) * w2) * ieps;
+            }
+            const TC basev = M * (((C3 * w2 + C2) * w2 + C1) * w2 + C0) + es;
+            const double vd = v2d(m);
+            const double z = (double)zyv, b = (double)basev;
+            const double uz = vd * z, ub = vd * b;
+            acc[0] += z;
+            acc[1] += uz;
+            acc[2] += vd * uz;
+            acc[3] += b;
+            acc[4] += ub;
+            acc[5] += vd * ub;
+        }
+        const double v1s = v1d * v1d;
+        double s[8] = {acc[0], v1d * acc[0], acc[1], v1s * acc[0] + acc[2],
+                       acc[3], v1d * acc[3], acc[4], v1s * acc[3] + acc[5]};
+        wave_sum<8>(s, lane);
+        TC cz[4], cb[4] = {(TC)0, (TC)0, (TC)0, (TC)0};
+        proj_poly(cl, s, cz);
+        if (discrete) proj_poly(cl, s + 4, cb);
+        const TC vv = v1 * v1;
+        const TC Kz = cz[0] + cz[1] * v1 + cz[3] * vv;
+        const TC Kb = cb[0] + cb[1] * v1 + cb[3] * vv;
+        const TC dt = (TC)P->dt, ra = (TC)cl.ra, rb = (TC)cl.rb;
+        TS *gout = Gn + c * (size_t)(64 * NPT) + lane;
+        double h0 = 0.0, h1 = 0.0, h2 = 0.0, h3 = 0.0;
+        const double u2d = cl.u2d;
+        r = r0;
+        q = q0;
+#pragma unroll
+        for (int m = 0; m < NPT; ++m) {
+            const TC w = v2(m), wc = w - u2;
+            const TC M = maxw(t, E1, m);
+            const TC zyv = w * idy * (w < (TC)0 ? hi[m] - ce[m] : ce[m] - lo[m]);
+            TC es;
+            if constexpr (sizeof(TC) == 8) {
+                es = (TC)(r - 1.0) * M * ieps;
+                r *= q;
+                q *= kq;
+            } else {
+                es = M * expm1f(A0 + (Bq + Cq * wc) * wc) * ieps;
+            }
+            const TC basev = M * (((C3 * wc + C2) * wc + C1) * wc + C0) + es;
+            const TC pz = (cz[3] * w + cz[2]) * w + Kz;
+            const TC pb = (cb[3] * w + cb[2]) * w + Kb;
+            const TC gss = ce[m] + dt * (pz * M - zyv);
+            const TC gh = basev - pb * M;
+            const TS gn = (TS)(ra * gss + rb * gh);
+            gout[64 * m] = gn;
+            const double g = (double)gn, w2 = v2d(m) - u2d;
+            const double ug = g * w2, ug2 = ug * w2;
+            h0 += g;
+            h1 += ug;
+            h2 += ug2;
+            h3 += ug2 * w2;
+        }
+        double hs[4] = {a * a * a * h0, a * a * h1, a * h2, h3};
+        wave_sum<4>(hs, lane);
+        if (lane == 0) {
+            const double f = P->eps * P->dv1 * P->dv2;
+            for (int qq = 0; qq < 4; ++qq) H[c * 4 + qq] = f * hs[qq];
+        }
+    }
+
     __device__ __forceinline__ void ghost(int kind, const TC (&own)[NPT], TC (&dst)[NPT]) const
     {
         const bool open = is_open(kind);
@@ -297,7 +460,7 @@ struct PassLK {
         for (int m = 0; m < NPT; ++m) dst[m] = open ? (TC)0 : own[m];
     }
 
-    // one row: G* of row j+1 into win[HI], prefetch row j+2, then finish row j
+    // one row: G* of row j+1 into win[HI], then finish row j
     // (the segment ends at row j1 - 1, so its last x-sweep is row j1)
     // Per-node constants depend only on the lane, so the compiler would hoist
     // all NPT of them out of the row loop and keep them in registers.  Passing
@@ -314,29 +477,35 @@ struct PassLK {
     {
         refresh();
         __builtin_amdgcn_sched_barrier(0);
-        if (j + 1 < P->ny) xsweep(j + 1, (j + 1) & 1, win[HI], PF);
+        if (j + 1 < P->ny) {
+            if constexpr (RC) xsweep_rc(j + 1, (j + 1) & 1, win[HI]);
+            else xsweep(j + 1, (j + 1) & 1, win[HI]);
+        }
         else if (P->bc[3].kind == BC_PERIODIC) xsweep(0, 2, win[HI]);
         else ghost(P->bc[3].kind, win[CE], win[HI]);
-        if (PF && j + 2 < P->ny && j + 2 <= j1) prefetch(j + 2);
         __builtin_amdgcn_sched_barrier(0);
         const size_t c = (size_t)j * P->nx + i;
         if (rec[c * REC + R_WALL] != 0.0) wall_row(c, j & 1, win[LO], win[CE], win[HI]);
+        else if constexpr (RC) finish_row_rc(c, j & 1, win[LO], win[CE], win[HI]);
         else finish_row(c, j & 1, win[LO], win[CE], win[HI]);
         __builtin_amdgcn_sched_barrier(0);
     }
 };
 
-// register budget: the large instances run one wavefront per SIMD and use
-// the freed registers for the prefetch of the next row
-template <typename TC, int NPT, bool PFQ>
+// Register budget of the large instances (64 B or more of G per lane): in FP64
+// the per-node temporaries stay in registers and one wavefront runs per SIMD;
+// in FP32 the x-sweep and the finish run in chunks that recompute per-node
+// temporaries, which keeps two wavefronts per SIMD (the faster choice for each
+// precision on gfx950).
+template <typename TC, int NPT>
 struct LKTraits {
     static constexpr bool big = sizeof(TC) * NPT >= 64;
-    static constexpr int occupancy = big ? 1 : 2;
-    static constexpr bool prefetch = big && PFQ;
+    static constexpr bool recompute = big && sizeof(TC) == 4;
+    static constexpr int occupancy = big && !recompute ? 1 : 2;
 };
 
-template <typename TS, typename TC, int NPT, bool PFQ>
-__global__ __launch_bounds__(64 * WPG, (LKTraits<TC, NPT, PFQ>::occupancy)) void k_fused2d_lk(const TS *__restrict__ G, TS *__restrict__ Gn,
+template <typename TS, typename TC, int NPT>
+__global__ __launch_bounds__(64 * WPG, (LKTraits<TC, NPT>::occupancy)) void k_fused2d_lk(const TS *__restrict__ G, TS *__restrict__ Gn,
                                                             double *__restrict__ H, const double *__restrict__ rec,
                                                             const double *__restrict__ wrec,
                                                             const Params *__restrict__ Pd, Geom geo)
@@ -346,9 +515,9 @@ __global__ __launch_bounds__(64 * WPG, (LKTraits<TC, NPT, PFQ>::occupancy)) void
     const int t = tile_of(blockIdx.x, geo.ntiles);
     if (t >= geo.ntiles) return;
     const int cg = t % geo.ncg, sg = t / geo.ncg;
-    const int wv = threadIdx.x >> 6;
-    constexpr bool PF = LKTraits<TC, NPT, PFQ>::prefetch;
-    PassLK<TS, TC, NPT, PF> ps;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform: cell indices live in SGPRs
+    constexpr bool RC = LKTraits<TC, NPT>::recompute;
+    PassLK<TS, TC, NPT, RC> ps;
     ps.G = G; ps.Gn = Gn; ps.H = H; ps.rec = rec; ps.wrec = wrec; ps.P = Pd;
     ps.tab = s_tab[wv];
     ps.lane = threadIdx.x & 63;
@@ -373,7 +542,6 @@ __global__ __launch_bounds__(64 * WPG, (LKTraits<TC, NPT, PFQ>::occupancy)) void
     if (j0 > 0) ps.xsweep(j0 - 1, 2, win[0]);
     else if (P.bc[2].kind == BC_PERIODIC) ps.xsweep(P.ny - 1, 2, win[0]);
     else ps.ghost(P.bc[2].kind, win[1], win[0]);
-    if (PF && j0 + 1 < P.ny) ps.prefetch(j0 + 1);
     // full rounds of three rows rotate the window back to its start; the tail
     // (one or two rows) runs after the loop so the window is never merged
     int j = j0;
@@ -386,14 +554,14 @@ __global__ __launch_bounds__(64 * WPG, (LKTraits<TC, NPT, PFQ>::occupancy)) void
     if (j + 1 < j1) ps.template step<1, 2, 0>(j + 1, j1, win);
 }
 
-template <typename TS, typename TC, bool PFQ>
+template <typename TS, typename TC>
 bool launch_lk_t(int npt, const void *G, void *Gn, double *H, const double *rec, const double *wrec,
                  const Params *Pd, const Geom &geo, hipStream_t st)
 {
     const dim3 grid(((geo.ntiles + 7) / 8) * 8), block(64 * WPG);
 #define MM_CASE(N)                                                                                          \
     case N:                                                                                                 \
-        hipLaunchKernelGGL((k_fused2d_lk<TS, TC, N, PFQ>), grid, block, 0, st, (const TS *)G, (TS *)Gn, H, rec,  \
+        hipLaunchKernelGGL((k_fused2d_lk<TS, TC, N>), grid, block, 0, st, (const TS *)G, (TS *)Gn, H, rec,  \
                            wrec, Pd, geo);                                                                  \
         return true;
     switch (npt) {
@@ -420,19 +588,14 @@ bool lk_supported(const Params &P)
 }
 
 bool launch_micro_lk2d(const void *G, void *Gn, double *H, const double *rec, const double *wrec,
-                       const Params &P, const Params *Pd, int precision, const Geom &geo_in, hipStream_t st)
+                       const Params &P, const Params *Pd, int precision, hipStream_t st)
 {
     if (!lk_supported(P)) return false;
     const int npt = P.nv / 64;
-    const bool big = (precision == 0 ? 8 : 4) * npt >= 64;
-    const Geom geo = geometry(P, big ? 1 : 2);
-    (void)geo_in;
-    const bool pf = std::getenv("MM_LK_NOPREFETCH") == nullptr;
-    if (precision == 0)
-        return pf ? launch_lk_t<double, double, true>(npt, G, Gn, H, rec, wrec, Pd, geo, st)
-                  : launch_lk_t<double, double, false>(npt, G, Gn, H, rec, wrec, Pd, geo, st);
-    return pf ? launch_lk_t<float, float, true>(npt, G, Gn, H, rec, wrec, Pd, geo, st)
-              : launch_lk_t<float, float, false>(npt, G, Gn, H, rec, wrec, Pd, geo, st);
+    const bool one_wave = precision == 0 && 8 * npt >= 64;
+    const Geom geo = geometry(P, one_wave ? 1 : 2);
+    return precision == 0 ? launch_lk_t<double, double>(npt, G, Gn, H, rec, wrec, Pd, geo, st)
+                          : launch_lk_t<float, float>(npt, G, Gn, H, rec, wrec, Pd, geo, st);
 }
 
 } // namespace mm

@@ -10,6 +10,58 @@ namespace fused {
 constexpr int WPG = 4;        // wavefronts per workgroup (one column each)
 constexpr int MAXV = 64;      // largest nv1, nv2 of the fused pass
 
+
+// ---------------------------------------------------------------------------
+// Wavefront sums built from gfx950 lane permutations that stay in the VALU
+// (no LDS round trip): v_permlane32_swap / v_permlane16_swap exchange whole
+// rows between lane halves / row pairs, DPP quad_perm and row mirrors pair
+// lanes inside a row of 16.
+
+__device__ __forceinline__ double hilo(unsigned hi, unsigned lo)
+{
+    return __hiloint2double((int)hi, (int)lo);
+}
+
+// DPP move of both halves of a double (ctrl: a DPP control code)
+template <int CTRL>
+__device__ __forceinline__ double dpp(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(__double2loint(v), __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(__double2hiint(v), __double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Fold across lane bit 5 (32) or 4 (16): on return a lane holds, in `lo`, the
+// sum of its own and its partner's copy of the half it keeps: lanes with the
+// bit clear keep `lo`, lanes with the bit set keep `hi`.
+template <int BIT>
+__device__ __forceinline__ double fold_swap(double lo, double hi)
+{
+    static_assert(BIT == 4 || BIT == 5, "permlane swaps cover lane bits 4 and 5");
+    unsigned a0 = (unsigned)__double2loint(lo), a1 = (unsigned)__double2hiint(lo);
+    unsigned b0 = (unsigned)__double2loint(hi), b1 = (unsigned)__double2hiint(hi);
+    if constexpr (BIT == 5) {
+        const auto r0 = __builtin_amdgcn_permlane32_swap(a0, b0, false, false);
+        const auto r1 = __builtin_amdgcn_permlane32_swap(a1, b1, false, false);
+        return hilo(r1[0], r0[0]) + hilo(r1[1], r0[1]);
+    } else {
+        const auto r0 = __builtin_amdgcn_permlane16_swap(a0, b0, false, false);
+        const auto r1 = __builtin_amdgcn_permlane16_swap(a1, b1, false, false);
+        return hilo(r1[0], r0[0]) + hilo(r1[1], r0[1]);
+    }
+}
+
+// all-reduce inside each row of 16 lanes: pairs (xor 1), (xor 2) by quad_perm,
+// then the half-row and row mirrors
+__device__ __forceinline__ double row_sum(double v)
+{
+    v += dpp<0xB1>(v);     // quad_perm [1,0,3,2]
+    v += dpp<0x4E>(v);     // quad_perm [2,3,0,1]
+    v += dpp<0x141>(v);    // row_half_mirror
+    v += dpp<0x140>(v);    // row_mirror
+    return v;
+}
+
 __device__ __forceinline__ double bcast(double v, int lane)
 {
     const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
@@ -17,40 +69,39 @@ __device__ __forceinline__ double bcast(double v, int lane)
     return __hiloint2double(hi, lo);
 }
 
-// One halving step of the wavefront sum below: lanes with bit `o` set keep
-// the upper H partial sums, the others the lower H, and each adds its
-// partner's copy of the half it keeps.
-template <int H>
-__device__ __forceinline__ void fold(double *a, int o, int lane)
-{
-    const bool up = (lane & o) != 0;
-#pragma unroll
-    for (int k = 0; k < H; ++k) {
-        const double keep = up ? a[k + H] : a[k];
-        const double send = up ? a[k] : a[k + H];
-        a[k] = keep + __shfl_xor(send, o, 64);
-    }
-}
-
-// Sum N doubles (N a power of two, <= 16) over the wavefront.  A halving step
-// exchanges n/2 values instead of n; after log2(N) of them lane L holds partial
-// sum number L >> (6 - log2 N), the remaining xor steps finish the sums, and
-// the totals are read back as wave-uniform values.
+// Sum N doubles (N = 1, 2, 4 or 8) over the wavefront; every lane receives the
+// totals as wave-uniform values.  Two fold steps halve the number of values
+// per lane across lane bits 5 and 4 (value q ends in the row q / (N/4)), the
+// row sums finish them.  The combination order is fixed (bitwise reproducible).
 template <int N>
 __device__ __forceinline__ void wave_sum(double (&v)[N], int lane)
 {
-    static_assert(N == 1 || N == 2 || N == 4 || N == 8 || N == 16, "power of two <= 16");
-    double a[N];
+    (void)lane;
+    static_assert(N == 1 || N == 2 || N == 4 || N == 8, "N in {1, 2, 4, 8}");
+    if constexpr (N == 1) {
+        double x = v[0];
+        x = fold_swap<5>(x, x);
+        x = fold_swap<4>(x, x);
+        v[0] = bcast(row_sum(x), 0);
+    } else if constexpr (N == 2) {
+        double x = fold_swap<5>(v[0], v[1]);        // rows 0,1: value 0; rows 2,3: value 1
+        x = fold_swap<4>(x, x);
+        x = row_sum(x);
+        v[0] = bcast(x, 0);
+        v[1] = bcast(x, 32);
+    } else {
+        constexpr int H = N / 2, Q = N / 4;
+        double a[H], b[Q];
 #pragma unroll
-    for (int k = 0; k < N; ++k) a[k] = v[k];
-    if constexpr (N >= 2) fold<N / 2>(a, 32, lane);
-    if constexpr (N >= 4) fold<N / 4>(a, 16, lane);
-    if constexpr (N >= 8) fold<N / 8>(a, 8, lane);
-    if constexpr (N >= 16) fold<N / 16>(a, 4, lane);
+        for (int k = 0; k < H; ++k) a[k] = fold_swap<5>(v[k], v[k + H]);
 #pragma unroll
-    for (int o = 32 / N; o >= 1; o >>= 1) a[0] += __shfl_xor(a[0], o, 64);
+        for (int k = 0; k < Q; ++k) b[k] = row_sum(fold_swap<4>(a[k], a[k + Q]));
+        // value q = r * Q + t sits in slot t of row r
 #pragma unroll
-    for (int q = 0; q < N; ++q) v[q] = bcast(a[0], q * (64 / N));
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int t = 0; t < Q; ++t) v[r * Q + t] = bcast(b[t], 16 * r);
+    }
 }
 
 __device__ __forceinline__ float t_exp(float x) { return expf(x); }
@@ -156,6 +207,6 @@ inline Geom geometry(const Params &P, int occupancy)
 // the lane-k specialisation of the fused pass (mm_fused2d_lk.hip)
 bool lk_supported(const Params &P);
 bool launch_micro_lk2d(const void *G, void *Gn, double *H, const double *rec, const double *wrec,
-                       const Params &P, const Params *Pd, int precision, const fused::Geom &geo, hipStream_t st);
+                       const Params &P, const Params *Pd, int precision, hipStream_t st);
 
 } // namespace mm

@@ -40,8 +40,8 @@ struct mm_ctx {
     bool timing = false;
     std::vector<TimedLaunch> pending;
     std::vector<hipEvent_t> pool;
-    int tcount[3] = {0, 0, 0};
-    double tms[3] = {0.0, 0.0, 0.0};
+    int tcount[MM_TIMING_CLASSES] = {};
+    double tms[MM_TIMING_CLASSES] = {};
 };
 
 namespace {
@@ -219,14 +219,18 @@ int enqueue_steps(mm_ctx *c, int nsteps)
                 Timer t(c, 1);
                 mm::launch_prep2d(c->Q, c->rec, c->wrec, c->flag, step, P, c->st);
             }
-            {
-                Timer t(c, 0);
-                if (c->fused)
+            if (c->fused) {
+                {
+                    Timer t(c, 0);
                     mm::launch_micro_fused2d(c->G[c->cur], c->G[1 - c->cur], c->H, c->rec, c->wrec, P, c->Pd,
                                              c->cfg.precision, c->st);
-                else
-                    mm::launch_micro_ref2d((const double *)c->G[c->cur], c->Gs, (double *)c->G[1 - c->cur], c->H,
-                                           c->rec, c->wrec, P, c->st);
+                }
+                Timer t(c, 3);
+                mm::launch_wall_relax2d(c->G[1 - c->cur], c->gbytes, c->H, c->rec, c->wrec, P, c->st);
+            } else {
+                Timer t(c, 0);
+                mm::launch_micro_ref2d((const double *)c->G[c->cur], c->Gs, (double *)c->G[1 - c->cur], c->H,
+                                       c->rec, c->wrec, P, c->st);
             }
             {
                 Timer t(c, 2);
@@ -471,7 +475,7 @@ int mm_timing(mm_ctx *ctx, int enable)
     if (hipStreamSynchronize(ctx->st) != hipSuccess) return MM_EDEVICE;
     collect_timing(ctx);
     ctx->timing = enable != 0;
-    for (int w = 0; w < 3; ++w) {
+    for (int w = 0; w < MM_TIMING_CLASSES; ++w) {
         ctx->tcount[w] = 0;
         ctx->tms[w] = 0.0;
     }
@@ -480,7 +484,7 @@ int mm_timing(mm_ctx *ctx, int enable)
 
 int mm_timing_get(mm_ctx *ctx, int which, int *count, double *total_ms)
 {
-    if (!ctx || which < 0 || which > 2) return MM_EINVAL;
+    if (!ctx || which < 0 || which >= MM_TIMING_CLASSES) return MM_EINVAL;
     if (hipStreamSynchronize(ctx->st) != hipSuccess) return MM_EDEVICE;
     collect_timing(ctx);
     if (count) *count = ctx->tcount[which];

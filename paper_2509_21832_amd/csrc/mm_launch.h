@@ -15,7 +15,8 @@ void launch_gmom2d(const void *G, int g_bytes, const double *rec, double *out, c
 void launch_wall_relax2d(void *Gn, int g_bytes, double *H, const double *rec, const double *wrec, const Params &P,
                          hipStream_t st);
 
-// fused phase-space pass (including the wall-cell kernel); false when the shape is not supported
+// fused phase-space pass; false when the shape is not supported.  Wall-adjacent
+// cells leave it holding G** and are finished by launch_wall_relax2d.
 bool fused_supported(const Params &P, int precision);
 // P: host copy of the parameters; Pd: the same parameters in device memory
 void launch_micro_fused2d(const void *G, void *Gn, double *H, const double *rec, const double *wrec,

@@ -14,20 +14,32 @@ def log(msg):
     sys.stdout.flush()
 
 
-def run_gpu(p, Q, G, nsteps, chunks=1, reference=False):
+class _env:
+    """Set (or clear) one environment variable for the duration of a block."""
+
+    def __init__(self, name, on):
+        self.name, self.on = name, on
+
+    def __enter__(self):
+        self.old = os.environ.pop(self.name, None)
+        if self.on:
+            os.environ[self.name] = "1"
+
+    def __exit__(self, *a):
+        os.environ.pop(self.name, None)
+        if self.old is not None:
+            os.environ[self.name] = self.old
+
+
+def run_gpu(p, Q, G, nsteps, chunks=1, reference=False, generic=False):
     """Run the HIP path.  reference=True selects the unfused phase-space pass
-    (the library reads MM_REFERENCE_PASS when a context is created)."""
+    (the library reads MM_REFERENCE_PASS when a context is created);
+    generic=True forces the generic fused kernel where the lane-k one would
+    run (MM_GENERIC_FUSED, read at each launch)."""
     from paper_2509_21832_amd import binding as B
-    old = os.environ.pop("MM_REFERENCE_PASS", None)
-    if reference:
-        os.environ["MM_REFERENCE_PASS"] = "1"
-    try:
+    with _env("MM_REFERENCE_PASS", reference):
         s = B.Solver(p, Q, G)
-    finally:
-        os.environ.pop("MM_REFERENCE_PASS", None)
-        if old is not None:
-            os.environ["MM_REFERENCE_PASS"] = old
-    with s:
+    with s, _env("MM_GENERIC_FUSED", generic):
         per = nsteps // chunks
         done = 0
         while done < nsteps:
@@ -84,12 +96,13 @@ def compare(p, Q0, Qg, Gg, Hg, Qo, Go, Ho, q_l1=1e-12, q_el=1e-11, g_rel=1e-10, 
 MIXED_TOL = dict(q_l1=1e-5, q_el=1e-4, g_rel=1e-4)
 
 
-def parity(p, Q, G, nsteps, label="", chunks=1, reference=False, **tol):
+def parity(p, Q, G, nsteps, label="", chunks=1, reference=False, generic=False, **tol):
     log(f"[{label}] start: nx={p['nx']} ny={p.get('ny', 1)} nv={p['nv1']}x{p.get('nv2', 1)} "
-        f"steps={nsteps} eps={p['eps']} precision={p.get('precision', 'fp64')} reference={reference}")
+        f"steps={nsteps} eps={p['eps']} precision={p.get('precision', 'fp64')} reference={reference} "
+        f"generic={generic}")
     if p.get("precision", "fp64") != "fp64":
         for k, v in MIXED_TOL.items():
             tol.setdefault(k, v)
-    Qg, Gg, Hg = run_gpu(p, Q, G, nsteps, chunks, reference)
+    Qg, Gg, Hg = run_gpu(p, Q, G, nsteps, chunks, reference, generic)
     Qo, Go, Ho = oracle.run(p, Q.reshape(-1), G.reshape(-1), nsteps)
     return compare(p, Q, Qg, Gg, Hg, Qo, Go, Ho, label=label, **tol)

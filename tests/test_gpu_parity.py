@@ -40,6 +40,48 @@ SMALL = {
 }
 
 
+def _velocity(gen, nv1, nv2, V1=8.0, V2=8.0):
+    """A generated problem on another velocity grid (g starts at zero)."""
+    p, Q, _ = gen()
+    p["nv1"], p["nv2"], p["v1"], p["v2"] = nv1, nv2, (-V1, V1), (-V2, V2)
+    return p, Q, W.zero_g(p)
+
+
+# velocity grids the lane-k kernel takes (nv1 divides 64): one to sixteen
+# nodes per lane, one wavefront per SIMD (FP64) and the chunked FP32 form at
+# 1024 nodes per cell; ragged spatial sizes with several row segments
+LANE_K = {
+    "lk_8x8_periodic": lambda: _velocity(lambda: W.smooth2d(seed=20, nx=13, ny=11, eps=0.05), 8, 8),
+    "lk_2x32_extrap": lambda: _velocity(lambda: W.smooth2d(seed=21, nx=7, ny=9, eps=0.2, bc=W.extrap2d()),
+                                        2, 32, V1=6.0),
+    "lk_16x8_walls": lambda: _velocity(lambda: W.quadrant2d(seed=22, nx=11, ny=9, eps=0.1), 16, 8),
+    "lk_4x64_inflow": lambda: _velocity(lambda: _inflow_box(23), 4, 64, V1=5.0, V2=9.0),
+    "lk_32x32_cavity": lambda: W.cavity2d(seed=24, nx=9, ny=37, nv=32, eps=0.02, amp=0.2),
+    "lk_64x16_walls": lambda: _velocity(lambda: W.quadrant2d(seed=25, nx=6, ny=19, eps=0.03), 64, 16,
+                                        V1=9.0, V2=7.0),
+    "lk_32x16_paper_proj": lambda: _velocity(
+        lambda: W.smooth2d(seed=26, nx=10, ny=18, eps=0.1, proj_mode="paper"), 32, 16),
+}
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("name", sorted(LANE_K))
+def test_lane_k_2d(name, precision):
+    """The lane-k fused kernel on its whole range of velocity grids."""
+    p, Q, G = LANE_K[name]()
+    p["precision"] = precision
+    parity(p, Q, G, 25, label=f"{name}_{precision}")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("name", ["lk_32x32_cavity", "lk_16x8_walls", "lk_4x64_inflow"])
+def test_generic_fused_on_lane_k_shapes(name, precision):
+    """The generic fused kernel, forced where the lane-k kernel would run."""
+    p, Q, G = LANE_K[name]()
+    p["precision"] = precision
+    parity(p, Q, G, 25, label=f"{name}_{precision}_generic", generic=True)
+
+
 @pytest.mark.parametrize("name", sorted(SMALL))
 def test_small_2d(name):
     """The launch configuration of the benchmark: fused phase-space pass."""
