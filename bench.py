@@ -138,6 +138,9 @@ def main():
     ap.add_argument("--eps", type=float, default=1e-2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-error", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="first run one plain device-to-device copy of MIB MiB (the reference kernel that "
+                         "scales the HBM byte counters of a profiler run)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the solver has no multi-GPU path "
@@ -147,6 +150,16 @@ def main():
     import torch
     from paper_2509_21832_amd import binding as B
     assert torch.cuda.is_available(), "no GPU"
+
+    if args.copy_probe:
+        n = args.copy_probe * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"copy probe: {args.copy_probe} MiB read, {args.copy_probe} MiB written")
+        del a, b
 
     p, Q, G = W.cavity2d(seed=0, eps=args.eps)
     pts = p["nx"] * p["ny"] * p["nv1"] * p["nv2"]
