@@ -158,6 +158,11 @@ int mm_moments(mm_ctx *ctx, double *q_out, double *h_out, double *gmom_out);
 /* mm_get_g -- copy G out as FP64 (host [ny][nx][nv2][nv1]). */
 int mm_get_g(mm_ctx *ctx, double *g_out);
 
+/* mm_get_g_cells -- copy G of n cells out as FP64: cells[t] is the cell index
+ * j * nx + i (host, 0 <= cells[t] < nx * ny), g_out is host [n][nv2][nv1].
+ * MM_EINVAL for an index out of range (nothing is copied then). */
+int mm_get_g_cells(mm_ctx *ctx, const int *cells, int n, double *g_out);
+
 /* mm_set_state -- replace Q (required) and G (NULL: zero) with host data;
  * together with mm_moments/mm_get_g this is checkpoint / restart. */
 int mm_set_state(mm_ctx *ctx, const double *q, const double *g);

@@ -21,7 +21,8 @@ PRECISION = {"fp64": 0, "mixed": 1, "closure": 2}
 
 # every entry point declared in include/mm.h
 EXPORTS = ("mm_init", "mm_step", "mm_step_async", "mm_sync", "mm_moments", "mm_get_g", "mm_set_state",
-           "mm_free", "mm_dt", "mm_failed_step", "mm_strerror", "mm_timing", "mm_timing_get", "mm_device_ptrs")
+           "mm_free", "mm_dt", "mm_failed_step", "mm_strerror", "mm_timing", "mm_timing_get", "mm_device_ptrs",
+           "mm_get_g_cells")
 
 
 class MMError(RuntimeError):
@@ -63,6 +64,7 @@ def _load():
     L.mm_sync.argtypes = [vp]
     L.mm_moments.argtypes = [vp, dp, dp, dp]
     L.mm_get_g.argtypes = [vp, dp]
+    L.mm_get_g_cells.argtypes = [vp, C.POINTER(C.c_int), C.c_int, dp]
     L.mm_set_state.argtypes = [vp, dp, dp]
     L.mm_free.argtypes = [vp]
     L.mm_free.restype = None
@@ -205,6 +207,14 @@ class Solver:
     def get_g(self):
         G = np.empty(self.ncell * self.nv)
         _check(_lib.mm_get_g(self._ctx, _dp(G)), "mm_get_g")
+        return G
+
+    def get_g_cells(self, cells):
+        """g of the given cells (cell index j * nx + i) as FP64, shape [len(cells), nv]."""
+        idx = np.ascontiguousarray(cells, dtype=np.int32).reshape(-1)
+        G = np.empty((idx.size, self.nv))
+        _check(_lib.mm_get_g_cells(self._ctx, idx.ctypes.data_as(C.POINTER(C.c_int)), int(idx.size), _dp(G)),
+               "mm_get_g_cells")
         return G
 
     def set_state(self, Q, G=None):

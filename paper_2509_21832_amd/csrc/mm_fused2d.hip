@@ -329,17 +329,27 @@ bool launch_npt(int npt, const void *G, void *Gn, double *H, const double *rec, 
         MM_CASE(12)
         MM_CASE(16)
     default:
+        if constexpr (sizeof(TC) == 4) {
+            switch (npt) {
+                MM_CASE(24)
+                MM_CASE(36)
+            default:
+                return false;
+            }
+        }
         return false;
     }
 #undef MM_CASE
 }
 
-int npt_for(int nv)
+// nodes per lane of the generic kernel: up to 16 (1024 nodes) in FP64; with g in
+// FP32 also 24 and 36 (up to 2304 nodes, e.g. a 48 x 48 velocity grid)
+int npt_for(int nv, int precision)
 {
-    static const int opts[] = {1, 2, 3, 4, 6, 8, 9, 12, 16};
+    static const int opts[] = {1, 2, 3, 4, 6, 8, 9, 12, 16, 24, 36};
     const int need = (nv + 63) / 64;
     for (int o : opts)
-        if (o >= need) return o;
+        if (o >= need) return (o > 16 && precision == 0) ? 0 : o;
     return 0;
 }
 
@@ -347,9 +357,8 @@ int npt_for(int nv)
 
 bool fused_supported(const Params &P, int precision)
 {
-    (void)precision;
     if (P.nv1 > MAXV || P.nv2 > MAXV) return false;
-    return npt_for(P.nv) != 0;
+    return npt_for(P.nv, precision) != 0;
 }
 
 void launch_micro_fused2d(const void *G, void *Gn, double *H, const double *rec, const double *wrec,
@@ -359,7 +368,7 @@ void launch_micro_fused2d(const void *G, void *Gn, double *H, const double *rec,
     // parity can be tested on shapes the lane-k kernel also covers
     if (std::getenv("MM_GENERIC_FUSED") || !launch_micro_lk2d(G, Gn, H, rec, wrec, P, Pd, precision, st)) {
         const Geom geo = geometry(P, 2);
-        const int npt = npt_for(P.nv);
+        const int npt = npt_for(P.nv, precision);
         if (precision == 0) launch_npt<double, double>(npt, G, Gn, H, rec, wrec, Pd, geo, st);
         else launch_npt<float, float>(npt, G, Gn, H, rec, wrec, Pd, geo, st);
     }

@@ -64,7 +64,7 @@ int check_cfg(const mm_config *c)
     if (c->dim == 2 && (!(c->nu >= -1.0) || !(c->nu < 1.0))) return MM_EINVAL;
     if (c->tau_model < 0 || c->tau_model > 3 || !(c->tau_coef > 0.0)) return MM_EINVAL;
     if (c->proj_mode != MM_PROJ_DISCRETE && c->proj_mode != MM_PROJ_PAPER) return MM_EINVAL;
-    if (c->precision < MM_FP64 || c->precision > MM_CLOSURE) return MM_EINVAL;
+    if (c->precision != MM_FP64 && c->precision != MM_MIXED) return MM_EINVAL;   // MM_CLOSURE: not built
     if (c->dim == 1 && c->precision != MM_FP64) return MM_EINVAL;
     const int nside = c->dim == 2 ? 4 : 2;
     for (int s = 0; s < nside; ++s) {
@@ -439,6 +439,28 @@ int mm_get_g(mm_ctx *ctx, double *g_out)
         std::vector<float> tmp(n);
         HIP_TRY(hipMemcpy(tmp.data(), ctx->G[ctx->cur], n * 4, hipMemcpyDeviceToHost));
         for (size_t i = 0; i < n; ++i) g_out[i] = tmp[i];
+    }
+    return MM_OK;
+}
+
+int mm_get_g_cells(mm_ctx *ctx, const int *cells, int n, double *g_out)
+{
+    if (!ctx || n < 0 || (n > 0 && (!cells || !g_out))) return MM_EINVAL;
+    if (ctx->broken) return MM_ESTATE;
+    for (int t = 0; t < n; ++t)
+        if (cells[t] < 0 || cells[t] >= ctx->ncell) return MM_EINVAL;
+    if (hipStreamSynchronize(ctx->st) != hipSuccess) return MM_EDEVICE;
+    const size_t nv = (size_t)ctx->nv;
+    std::vector<float> tmp(ctx->gbytes == 4 ? nv : 0);
+    for (int t = 0; t < n; ++t) {
+        const char *src = (const char *)ctx->G[ctx->cur] + (size_t)cells[t] * nv * ctx->gbytes;
+        double *dst = g_out + (size_t)t * nv;
+        if (ctx->gbytes == 8) {
+            HIP_TRY(hipMemcpy(dst, src, nv * 8, hipMemcpyDeviceToHost));
+        } else {
+            HIP_TRY(hipMemcpy(tmp.data(), src, nv * 4, hipMemcpyDeviceToHost));
+            for (size_t p = 0; p < nv; ++p) dst[p] = tmp[p];
+        }
     }
     return MM_OK;
 }

@@ -175,3 +175,58 @@ def test_c3_full_100_steps_vs_golden(precision, tol):
         log(f"[c3_100 {key} {precision}] sampled Q rel-L1 {e:.3e}; domain sums rel {es.max():.3e}")
         assert e <= tol
         assert es.max() <= tol
+
+
+def _c4_reference():
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "c4_blast_checkpoints.npz")
+    return np.load(path)
+
+
+def test_c4_blast_mixed_vs_golden():
+    """Config 4 at full size (512^2 x 48^2 = 604M points, g in FP32): macro state after 10 and
+    100 steps against the oracle's stored result (tests/golden/make_c4_reference.py), sampled
+    every 8th cell, domain sums over all cells, and g of 16 cells (corners, wall rows, blast core)."""
+    from paper_2509_21832_amd import binding as B
+    ref = _c4_reference()
+    st = int(ref["stride"])
+    p, Q, G = W.blast2d(seed=0)
+    p["precision"] = "mixed"
+    cells = ref["g_cells"][:, 0] * p["nx"] + ref["g_cells"][:, 1]
+    with B.Solver(p, Q, G) as s:
+        done = 0
+        for n in ref["steps"]:
+            log(f"[c4 mixed] to step {n}")
+            s.step(int(n) - done)
+            done = int(n)
+            Qg = s.moments().reshape(p["ny"], p["nx"], 6)
+            e = rel_l1(Qg[::st, ::st, :], ref[f"step{n}_sample"])
+            sums = Qg.reshape(-1, 6).sum(0)
+            es = np.abs(sums - ref[f"step{n}_sum"]) / ref[f"step{n}_abssum"]
+            gg = s.get_g_cells(cells)
+            gr = ref[f"step{n}_g"]
+            ge = np.abs(gg - gr).max() / np.abs(gr).max()
+            log(f"[c4 mixed step {n}] sampled Q rel-L1 {e:.3e}; sums rel {es.max():.3e}; g max rel {ge:.3e}")
+            assert e <= 1e-5 and es.max() <= 1e-5
+            assert ge <= 1e-4
+
+
+def test_c4_blast_mixed_500_steps_properties():
+    """Config 4's full run (500 steps, g in FP32): no non-physical state, total mass conserved to
+    round-off (diffuse walls have zero net mass flux), conserved moments of g zero to FP32 rounding."""
+    from paper_2509_21832_amd import binding as B
+    p, Q, G = W.blast2d(seed=0)
+    p["precision"] = "mixed"
+    with B.Solver(p, Q, G) as s:
+        s.step(500)
+        Qg, H, M = s.moments(with_h=True, with_gmom=True)
+    Q0 = Q.reshape(-1, 6)
+    Qg = Qg.reshape(-1, 6)
+    M = M.reshape(-1, 7)
+    dm = abs(Qg[:, 0].sum() - Q0[:, 0].sum()) / Q0[:, 0].sum()
+    stress = np.abs(M[:, 4:7]).max() / p["eps"]
+    cons = np.abs(M[:, 0:4]).max()
+    log(f"[c4 500] mass drift {dm:.3e}; max |conserved g-moment| {cons:.3e} vs stress scale {stress:.3e}")
+    assert np.all(np.isfinite(Qg)) and np.all(np.isfinite(H))
+    assert dm <= 1e-12
+    assert cons <= 1e-5 * stress
