@@ -4,7 +4,7 @@ TEST INFRASTRUCTURE ONLY: imported by ``tests/``, ``__graft_entry__.smoke()``
 and the CPU-baseline leg of ``bench.py``; never by the product package.
 
 The arithmetic lives in ``mm_oracle.c`` (plain C, FP64, compensated velocity
-sums).  This module only builds it, marshals arguments through ctypes and
+sums) and, for the learned-closure form, ``mm_closure_oracle.c``.  This module only builds it, marshals arguments through ctypes and
 turns problem dictionaries (see ``mm_workloads``) into the oracle's own
 configuration struct.
 """
@@ -16,6 +16,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "mm_oracle.c")
+_SRCS = [_SRC, os.path.join(_HERE, "mm_closure_oracle.c")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 BC = {"extrap": 0, "periodic": 1, "wall": 2, "inflow": 3}
@@ -27,7 +28,7 @@ CFL = {"min": 0, "sum": 1}
 def build(verbose=False):
     """Compile the oracle (gcc, -O2, no fast-math, no FMA contraction)."""
     cmd = ["gcc", "-O2", "-std=c11", "-fno-fast-math", "-ffp-contract=off", "-fopenmp",
-           "-fPIC", "-shared", "-o", _LIB + ".tmp", _SRC, "-lm"]
+           "-fPIC", "-shared", "-o", _LIB + ".tmp"] + _SRCS + ["-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.check_call(cmd)
@@ -55,7 +56,7 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(os.path.getmtime(f) for f in _SRCS):
             build()
         L = C.CDLL(_LIB)
         dp = C.POINTER(C.c_double)
@@ -81,6 +82,21 @@ def lib():
         L.o_set_threads.argtypes = [C.c_int]
         L.o_set_threads.restype = None
         L.o_get_threads.restype = C.c_int
+        L.o_features2d.argtypes = [cp, dp, dp, dp, ip]
+        L.o_mlp_nparam.restype = C.c_int
+        L.o_mlp_forward.argtypes = [dp, dp, dp, C.c_int, C.c_int, dp]
+        L.o_mlp_grad.argtypes = [dp, dp, dp, dp, C.c_int, C.c_int, dp, dp]
+        L.o_gelu.argtypes = [C.c_double]
+        L.o_gelu.restype = C.c_double
+        L.o_gelu_d.argtypes = [C.c_double]
+        L.o_gelu_d.restype = C.c_double
+        L.o_bf16.argtypes = [C.c_double]
+        L.o_bf16.restype = C.c_double
+        L.o_closure_H.argtypes = [dp, dp]
+        L.o_closure_H.restype = None
+        L.o_closure_grec.argtypes = [cp, dp, dp, dp, dp]
+        L.o_nsf_closure.argtypes = [cp, dp, dp, dp]
+        L.o_nsf_closure.restype = None
         _lib = L
     return _lib
 
@@ -215,3 +231,82 @@ def trbdf2_W(eps, tau, nu, dt_):
 
 def wall_R(u, Taa, T_wall, sign):
     return lib().o_wall_R(u, Taa, T_wall, int(sign))
+
+
+# ---------------------------------------------------------------- closure form
+
+N_FEAT, N_HID, N_OUT = 21, 64, 5
+
+
+def mlp_nparam():
+    return lib().o_mlp_nparam()
+
+
+def features2d(p, Q):
+    """Per-cell features [ncell, 21], local Knudsen indicator [ncell] and the
+    always-micro mask of cells next to non-periodic sides [ncell]."""
+    n = p["nx"] * p["ny"]
+    F = np.zeros(n * N_FEAT)
+    kn = np.zeros(n)
+    edge = np.zeros(n, dtype=np.int32)
+    rc = lib().o_features2d(C.byref(cfg(p)), _dp(_f64(Q)), _dp(F), _dp(kn), edge.ctypes.data_as(C.POINTER(C.c_int)))
+    if rc:
+        raise ValueError(rc)
+    return F.reshape(n, N_FEAT), kn, edge.astype(bool)
+
+
+def _norm(norm):
+    return _f64(np.concatenate([np.ravel(norm[k]) for k in ("in_mean", "in_std", "out_mean", "out_std")]))
+
+
+def mlp_forward(params, norm, X, bf16=False):
+    """Raw outputs [n, 5] of the closure network for raw features X [n, 21];
+    norm: dict of in_mean, in_std (21), out_mean, out_std (5)."""
+    X = _f64(X).reshape(-1, N_FEAT)
+    Y = np.zeros((X.shape[0], N_OUT))
+    lib().o_mlp_forward(_dp(_f64(params)), _dp(_norm(norm)), _dp(X), X.shape[0], int(bf16), _dp(Y))
+    return Y
+
+
+def mlp_grad(params, norm, X, Y, bf16=False):
+    """(gradient of the normalised mean-square loss w.r.t. every parameter, loss)."""
+    X = _f64(X).reshape(-1, N_FEAT)
+    Y = _f64(Y).reshape(-1, N_OUT)
+    g = np.zeros(mlp_nparam())
+    loss = C.c_double(0.0)
+    lib().o_mlp_grad(_dp(_f64(params)), _dp(_norm(norm)), _dp(X), _dp(Y), X.shape[0], int(bf16), _dp(g),
+                     C.byref(loss))
+    return g, loss.value
+
+
+def gelu(x):
+    return lib().o_gelu(float(x))
+
+
+def gelu_d(x):
+    return lib().o_gelu_d(float(x))
+
+
+def bf16(x):
+    return lib().o_bf16(float(x))
+
+
+def closure_H(q):
+    H = np.zeros(4)
+    lib().o_closure_H(_dp(_f64(q)), _dp(H))
+    return H
+
+
+def closure_grec(p, q, qt, St):
+    g = np.zeros(p["nv1"] * p["nv2"])
+    rc = lib().o_closure_grec(C.byref(cfg(p)), _dp(_f64(q)), _dp(_f64(qt)), _dp(_f64(St)), _dp(g))
+    if rc:
+        raise ValueError(rc)
+    return g
+
+
+def nsf_closure(p, f):
+    qt = np.zeros(2)
+    St = np.zeros(3)
+    lib().o_nsf_closure(C.byref(cfg(p)), _dp(_f64(f)), _dp(qt), _dp(St))
+    return qt, St
