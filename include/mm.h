@@ -85,7 +85,9 @@ enum {
     MM_MIXED = 1,   /* g stored and transported in FP32; velocity reductions, cell
                        coefficients, Gaussian / pressure-tensor algebra and the macro
                        update in FP64                                                 */
-    MM_CLOSURE = 2  /* MM_MIXED plus the learned closure in near-continuum cells     */
+    MM_CLOSURE = 2  /* MM_MIXED plus the learned closure in near-continuum cells
+                       (2D, velocity grids with nv1 dividing 64, nv1 nv2 a power-of-two
+                       multiple of 64 up to 1024); see mm_closure_attach()             */
 };
 
 /* one side of the box: 0 = x_lo, 1 = x_hi, 2 = y_lo, 3 = y_hi */
@@ -191,9 +193,10 @@ const char *mm_strerror(int status);
  *       unfused pass, or the whole 1D step,
  *   1 = per-cell preparation, 2 = macro sweeps,
  *   3 = wall-adjacent cells after a fused pass.
+ *   4 = closure-form kernels (features, network, classes, rebuilt micro parts).
  * Any other `which` gives MM_EINVAL.
  */
-#define MM_TIMING_CLASSES 4
+#define MM_TIMING_CLASSES 5
 int mm_timing(mm_ctx *ctx, int enable);
 int mm_timing_get(mm_ctx *ctx, int which, int *count, double *total_ms);
 
@@ -201,6 +204,101 @@ int mm_timing_get(mm_ctx *ctx, int which, int *count, double *total_ms);
  * zero-copy interop, e.g. wrapping them as torch tensors).  G is FP64 or FP32
  * according to cfg->precision; *g_bytes receives its element size. */
 int mm_device_ptrs(mm_ctx *ctx, void **q, void **g, void **h, int *g_bytes);
+
+/* =====================================================================
+ * Learned closure (2D).  Not part of the paper; built on its macro system:
+ * the macro update of Sec. 5.4 needs from the micro part only the heat-flux
+ * tensor H (eq5-41).  In near-continuum cells a network predicts, from the
+ * local macro state, the heat-flux vector q and the stress deviation S of
+ * eps g, and H is taken in the isotropic form
+ *   H_abc = (q_a d_bc + q_b d_ac + q_c d_ab) / 2,
+ * whose contraction (H111 + H122, H112 + H222) / 2 is the heat-flux vector h
+ * of Sec. 6.3.
+ *
+ * Features of a cell (21, FP32): (rho, u1, u2, T, P11, P12, P22) and their
+ * centred x and y differences (one-sided next to a non-periodic side), in that
+ * order.  Targets (5, FP32): (q1, q2, S11, S12, S22) / eps with
+ *   q = (H111 + H122, H112 + H222) / 2,  S = eps dv sum (w w^T) g.
+ * Local Knudsen indicator:
+ *   kn = (eps sqrt(T) / tau) max(|grad rho| / rho, |grad T| / T, |grad u|_F / sqrt(T)).
+ * A step of an MM_CLOSURE context solves the micro part (as MM_MIXED) in cells
+ * next to a non-periodic side and where kn > kn_max; elsewhere H comes from
+ * the closure.  Micro parts of closure cells that a solved cell needs (its
+ * 3 x 3 neighbourhood) are rebuilt, when not current, as
+ *   g = M / (2 p T) [S' : w w^T + (q . w)(|w|^2 / (2T) - 2)],  then (I - Pi) g
+ * (S' the traceless part of S), which under M has exactly the moments q, S.
+ * G of closure cells is not kept current: mm_get_g and the g-moments of
+ * mm_moments are meaningful only in solved cells.
+ * ===================================================================== */
+
+/* the network: 21 -> 64 -> 64 -> 5, GELU (erf form), bf16 weights and
+ * activations on the matrix cores with FP32 accumulation, FP32 master weights */
+typedef struct mm_mlp mm_mlp;
+#define MM_MLP_NPARAM 5893   /* W1[64][21], b1[64], W2[64][64], b2[64], W3[5][64], b3[5] */
+#define MM_MLP_NNORM 52      /* in_mean[21], in_std[21], out_mean[5], out_std[5]         */
+
+/* mm_mlp_create -- a network on `device` with Glorot-uniform weights drawn
+ * from `seed` (SplitMix64), zero biases and identity normalisation; stream as
+ * in mm_config.  Every mm_mlp_* call returns when its work is done. */
+int mm_mlp_create(int device, void *stream, unsigned long long seed, mm_mlp **out);
+void mm_mlp_free(mm_mlp *net);
+
+/* mm_mlp_fit_norm -- set the normalisation to the mean and standard deviation
+ * of the n rows of x_dev [n][21] and y_dev [n][5] (device FP32). */
+int mm_mlp_fit_norm(mm_mlp *net, const float *x_dev, const float *y_dev, int n);
+
+/* mm_mlp_get / mm_mlp_set -- FP32 parameters [MM_MLP_NPARAM] and normalisation
+ * [MM_MLP_NNORM] (host; either may be NULL).  mm_mlp_set resets the Adam state;
+ * a standard deviation <= 0 gives MM_EINVAL. */
+int mm_mlp_get(mm_mlp *net, float *params, float *norm);
+int mm_mlp_set(mm_mlp *net, const float *params, const float *norm);
+
+/* mm_mlp_forward -- raw outputs y_dev [n][5] of raw features x_dev [n][21]:
+ * y = MLP((x - in_mean) / in_std) * out_std + out_mean (device FP32). */
+int mm_mlp_forward(mm_mlp *net, const float *x_dev, int n, float *y_dev);
+
+/* mm_mlp_grad -- gradient (host FP32 [MM_MLP_NPARAM], parameter order above)
+ * and value (host) of L = mean over the n samples and 5 outputs of
+ * (MLP(xn) - (y - out_mean) / out_std)^2; no parameter changes. */
+int mm_mlp_grad(mm_mlp *net, const float *x_dev, const float *y_dev, int n, float *grad, double *loss);
+
+/* mm_mlp_train -- `epochs` passes of Adam (beta = 0.9, 0.999; step size lr with
+ * cosine decay to 0.05 lr) over mini-batches of `batch` samples (>= 32) in an
+ * order drawn per epoch from `seed`; epoch_loss (host [epochs] or NULL)
+ * receives the mean batch loss of each epoch. */
+int mm_mlp_train(mm_mlp *net, const float *x_dev, const float *y_dev, int n, int epochs, int batch, double lr,
+                 unsigned long long seed, double *epoch_loss);
+
+/* mm_closure_attach -- closure of an MM_CLOSURE context: the network `net`
+ * (kept by pointer: it must outlive its use and not be trained while the
+ * context steps), or NULL for the Navier-Stokes-Fourier values
+ *   q = -eps (2 p / tau) grad T,  S = -eps (p / tau) sigma + nu (P - p I)
+ * (sigma = grad u + grad u^T - (div u) I); threshold kn_max >= 0.  Stepping an
+ * MM_CLOSURE context without a closure gives MM_EINVAL. */
+int mm_closure_attach(mm_ctx *ctx, mm_mlp *net, double kn_max);
+
+/* mm_closure_cells -- number of closure cells summed over the steps since the
+ * previous call, and (cls_host [ny][nx] or NULL) 1 for solved, 0 for closure
+ * cells of the last step. */
+int mm_closure_cells(mm_ctx *ctx, long long *n_closure, unsigned char *cls_host);
+
+/* mm_closure_snapshot -- training data from a full micro solve (MM_FP64 or
+ * MM_MIXED context): the features of the current state, one step, the targets
+ * of the new micro part.  Rows of cells with kn <= kn_max that are not next to
+ * a non-periodic side are appended in cell order to x_dev [capacity][21] and
+ * y_dev [capacity][5] (device FP32) from row *count on; *count is updated
+ * (at most capacity rows are written). */
+int mm_closure_snapshot(mm_ctx *ctx, double kn_max, float *x_dev, float *y_dev, int capacity, int *count);
+
+/* mm_closure_features -- features [ny][nx][21], kn [ny][nx] and the
+ * next-to-a-non-periodic-side mask [ny][nx] of the current state (host;
+ * kn_host and edge_host may be NULL). */
+int mm_closure_features(mm_ctx *ctx, float *feat_host, float *kn_host, unsigned char *edge_host);
+
+/* mm_closure_rebuild -- replace the current G of the cells with mask[c] != 0
+ * (host [ny][nx]) by the micro part rebuilt from out_host [ny][nx][5] =
+ * (q1, q2, S11, S12, S22) / eps of each cell, as a closure step does. */
+int mm_closure_rebuild(mm_ctx *ctx, const float *out_host, const unsigned char *mask);
 
 #ifdef __cplusplus
 }

@@ -22,7 +22,13 @@ PRECISION = {"fp64": 0, "mixed": 1, "closure": 2}
 # every entry point declared in include/mm.h
 EXPORTS = ("mm_init", "mm_step", "mm_step_async", "mm_sync", "mm_moments", "mm_get_g", "mm_set_state",
            "mm_free", "mm_dt", "mm_failed_step", "mm_strerror", "mm_timing", "mm_timing_get", "mm_device_ptrs",
-           "mm_get_g_cells")
+           "mm_get_g_cells", "mm_mlp_create", "mm_mlp_free", "mm_mlp_fit_norm", "mm_mlp_get", "mm_mlp_set",
+           "mm_mlp_forward", "mm_mlp_grad", "mm_mlp_train", "mm_closure_attach", "mm_closure_cells",
+           "mm_closure_snapshot", "mm_closure_features", "mm_closure_rebuild")
+
+MLP_NPARAM = 5893
+MLP_NNORM = 52
+N_FEAT, N_OUT = 21, 5
 
 
 class MMError(RuntimeError):
@@ -76,6 +82,22 @@ def _load():
     L.mm_timing.argtypes = [vp, C.c_int]
     L.mm_timing_get.argtypes = [vp, C.c_int, C.POINTER(C.c_int), dp]
     L.mm_device_ptrs.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), C.POINTER(C.c_int)]
+    fp = C.POINTER(C.c_float)
+    bp = C.POINTER(C.c_ubyte)
+    L.mm_mlp_create.argtypes = [C.c_int, vp, C.c_ulonglong, C.POINTER(vp)]
+    L.mm_mlp_free.argtypes = [vp]
+    L.mm_mlp_free.restype = None
+    L.mm_mlp_fit_norm.argtypes = [vp, vp, vp, C.c_int]
+    L.mm_mlp_get.argtypes = [vp, fp, fp]
+    L.mm_mlp_set.argtypes = [vp, fp, fp]
+    L.mm_mlp_forward.argtypes = [vp, vp, C.c_int, vp]
+    L.mm_mlp_grad.argtypes = [vp, vp, vp, C.c_int, fp, dp]
+    L.mm_mlp_train.argtypes = [vp, vp, vp, C.c_int, C.c_int, C.c_int, C.c_double, C.c_ulonglong, dp]
+    L.mm_closure_attach.argtypes = [vp, vp, C.c_double]
+    L.mm_closure_cells.argtypes = [vp, C.POINTER(C.c_longlong), bp]
+    L.mm_closure_snapshot.argtypes = [vp, C.c_double, vp, vp, C.c_int, C.POINTER(C.c_int)]
+    L.mm_closure_features.argtypes = [vp, fp, fp, bp]
+    L.mm_closure_rebuild.argtypes = [vp, fp, bp]
     for name in EXPORTS:
         getattr(L, name)
     return L
@@ -122,6 +144,24 @@ def config(p, stream=None, device=0):
 
 def _dp(a):
     return a.ctypes.data_as(C.POINTER(C.c_double)) if a is not None else None
+
+
+def _fp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_float)) if a is not None else None
+
+
+def _bp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_ubyte)) if a is not None else None
+
+
+def _dev(t, cols):
+    """Device address of a contiguous float32 GPU tensor with `cols` columns."""
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+        raise TypeError("expected a contiguous float32 tensor on the GPU")
+    if t.dim() != 2 or t.shape[1] != cols:
+        raise ValueError(f"expected shape [n, {cols}], got {tuple(t.shape)}")
+    return t.data_ptr()
 
 
 def _check(rc, what):
@@ -236,3 +276,98 @@ class Solver:
         gb = C.c_int(0)
         _check(_lib.mm_device_ptrs(self._ctx, C.byref(q), C.byref(g), C.byref(h), C.byref(gb)), "mm_device_ptrs")
         return q.value, g.value, h.value, gb.value
+
+    # ---- closure form
+    def closure_attach(self, net, kn_max):
+        """net: an Mlp, or None for the Navier-Stokes-Fourier closure."""
+        self._net = net       # the context keeps the network by pointer
+        _check(_lib.mm_closure_attach(self._ctx, net._h if net is not None else None, float(kn_max)),
+               "mm_closure_attach")
+
+    def closure_cells(self):
+        """(closure cells summed over the steps since the last call, classes of the last step [ncell])."""
+        n = C.c_longlong(0)
+        cls = np.empty(self.ncell, dtype=np.uint8)
+        _check(_lib.mm_closure_cells(self._ctx, C.byref(n), _bp(cls)), "mm_closure_cells")
+        return n.value, cls
+
+    def closure_snapshot(self, kn_max, X, Y, count):
+        """Append training rows to the device tensors X [cap, 21], Y [cap, 5]; returns the new count."""
+        cap = X.shape[0]
+        if Y.shape[0] != cap:
+            raise ValueError("X and Y capacities differ")
+        c = C.c_int(int(count))
+        _check(_lib.mm_closure_snapshot(self._ctx, float(kn_max), _dev(X, N_FEAT), _dev(Y, N_OUT), int(cap),
+                                        C.byref(c)), "mm_closure_snapshot")
+        return c.value
+
+    def closure_features(self):
+        F = np.empty((self.ncell, N_FEAT), dtype=np.float32)
+        kn = np.empty(self.ncell, dtype=np.float32)
+        edge = np.empty(self.ncell, dtype=np.uint8)
+        _check(_lib.mm_closure_features(self._ctx, _fp(F), _fp(kn), _bp(edge)), "mm_closure_features")
+        return F, kn, edge.astype(bool)
+
+    def closure_rebuild(self, out, mask):
+        o = np.ascontiguousarray(out, dtype=np.float32).reshape(-1)
+        m = np.ascontiguousarray(mask, dtype=np.uint8).reshape(-1)
+        if o.size != self.ncell * N_OUT or m.size != self.ncell:
+            raise ValueError("wrong sizes")
+        _check(_lib.mm_closure_rebuild(self._ctx, _fp(o), _bp(m)), "mm_closure_rebuild")
+
+
+class Mlp:
+    """The closure network (mm_mlp): FP32 master weights on the device, bf16 matrix-core kernels."""
+
+    def __init__(self, seed=0, device=0, stream=None):
+        self._h = C.c_void_p()
+        _check(_lib.mm_mlp_create(int(device), stream, int(seed), C.byref(self._h)), "mm_mlp_create")
+
+    def close(self):
+        if self._h:
+            _lib.mm_mlp_free(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def fit_norm(self, X, Y):
+        _check(_lib.mm_mlp_fit_norm(self._h, _dev(X, N_FEAT), _dev(Y, N_OUT), int(X.shape[0])), "mm_mlp_fit_norm")
+
+    def get(self):
+        P = np.empty(MLP_NPARAM, dtype=np.float32)
+        N = np.empty(MLP_NNORM, dtype=np.float32)
+        _check(_lib.mm_mlp_get(self._h, _fp(P), _fp(N)), "mm_mlp_get")
+        return P, N
+
+    def set(self, params=None, norm=None):
+        P = None if params is None else np.ascontiguousarray(params, dtype=np.float32).reshape(-1)
+        N = None if norm is None else np.ascontiguousarray(norm, dtype=np.float32).reshape(-1)
+        if (P is not None and P.size != MLP_NPARAM) or (N is not None and N.size != MLP_NNORM):
+            raise ValueError("wrong sizes")
+        _check(_lib.mm_mlp_set(self._h, _fp(P), _fp(N)), "mm_mlp_set")
+
+    def forward(self, X, Y=None):
+        import torch
+        n = X.shape[0]
+        if Y is None:
+            Y = torch.empty((n, N_OUT), dtype=torch.float32, device=X.device)
+        _check(_lib.mm_mlp_forward(self._h, _dev(X, N_FEAT), int(n), _dev(Y, N_OUT)), "mm_mlp_forward")
+        return Y
+
+    def grad(self, X, Y):
+        g = np.empty(MLP_NPARAM, dtype=np.float32)
+        loss = C.c_double(0.0)
+        _check(_lib.mm_mlp_grad(self._h, _dev(X, N_FEAT), _dev(Y, N_OUT), int(X.shape[0]), _fp(g), C.byref(loss)),
+               "mm_mlp_grad")
+        return g, loss.value
+
+    def train(self, X, Y, epochs=10, batch=1024, lr=2e-3, seed=0):
+        """Adam epochs over (X, Y) on the GPU; returns the mean batch loss per epoch."""
+        L = np.empty(int(epochs))
+        _check(_lib.mm_mlp_train(self._h, _dev(X, N_FEAT), _dev(Y, N_OUT), int(X.shape[0]), int(epochs), int(batch),
+                                 float(lr), int(seed), _dp(L)), "mm_mlp_train")
+        return L

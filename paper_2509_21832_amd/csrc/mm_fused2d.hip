@@ -355,6 +355,14 @@ int npt_for(int nv, int precision)
 
 } // namespace
 
+bool closure_pass_supported(const Params &P) { return lk_supported(P); }
+
+bool launch_micro_closure2d(const void *G, void *Gn, double *H, const double *rec, const double *wrec,
+                            const Params &P, const Params *Pd, const uint8_t *cls, hipStream_t st)
+{
+    return launch_micro_lk2d(G, Gn, H, rec, wrec, P, Pd, 1, cls, st);
+}
+
 bool fused_supported(const Params &P, int precision)
 {
     if (P.nv1 > MAXV || P.nv2 > MAXV) return false;
@@ -366,7 +374,7 @@ void launch_micro_fused2d(const void *G, void *Gn, double *H, const double *rec,
 {
     // MM_GENERIC_FUSED (read per launch) forces the generic kernel, so that its
     // parity can be tested on shapes the lane-k kernel also covers
-    if (std::getenv("MM_GENERIC_FUSED") || !launch_micro_lk2d(G, Gn, H, rec, wrec, P, Pd, precision, st)) {
+    if (std::getenv("MM_GENERIC_FUSED") || !launch_micro_lk2d(G, Gn, H, rec, wrec, P, Pd, precision, nullptr, st)) {
         const Geom geo = geometry(P, 2);
         const int npt = npt_for(P.nv, precision);
         if (precision == 0) launch_npt<double, double>(npt, G, Gn, H, rec, wrec, Pd, geo, st);

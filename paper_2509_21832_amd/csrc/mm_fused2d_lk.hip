@@ -24,8 +24,9 @@ namespace {
 
 using namespace fused;
 
-template <typename TS, typename TC, int NPT, bool RC>
+template <typename TS, typename TC, int NPT, bool RC, bool CL>
 struct PassLK {
+    const uint8_t *__restrict__ cls;   // closure form: 1 where the micro part is solved
     const TS *__restrict__ G;
     TS *__restrict__ Gn;
     double *__restrict__ H;
@@ -472,11 +473,29 @@ struct PassLK {
         v2b = (TC)v2bd;
     }
 
+    // closure form: is the micro part of cell (i, r) solved?  Rows beyond a
+    // periodic side wrap; beyond any other side there are no cells.
+    __device__ __forceinline__ bool micro_row(int r) const
+    {
+        if (r < 0 || r >= P->ny) {
+            if (P->bc[2].kind != BC_PERIODIC) return false;
+            r = r < 0 ? r + P->ny : r - P->ny;
+        }
+        return cls[(size_t)r * P->nx + i] != 0;
+    }
+
+    // (closure form: G* of row j+1 is made only if one of rows j, j+1, j+2 is
+    // solved, and row j is finished only if it is solved)
     template <int LO, int CE, int HI>
     __device__ __forceinline__ void step(int j, int j1, TC (&win)[3][NPT])
     {
         refresh();
         __builtin_amdgcn_sched_barrier(0);
+        bool solve = true;
+        if constexpr (CL) {
+            solve = micro_row(j);
+            if (!solve && !micro_row(j + 1) && !micro_row(j + 2)) return;
+        }
         if (j + 1 < P->ny) {
             if constexpr (RC) xsweep_rc(j + 1, (j + 1) & 1, win[HI]);
             else xsweep(j + 1, (j + 1) & 1, win[HI]);
@@ -484,6 +503,7 @@ struct PassLK {
         else if (P->bc[3].kind == BC_PERIODIC) xsweep(0, 2, win[HI]);
         else ghost(P->bc[3].kind, win[CE], win[HI]);
         __builtin_amdgcn_sched_barrier(0);
+        if (CL && !solve) return;
         const size_t c = (size_t)j * P->nx + i;
         if (rec[c * REC + R_WALL] != 0.0) wall_row(c, j & 1, win[LO], win[CE], win[HI]);
         else if constexpr (RC) finish_row_rc(c, j & 1, win[LO], win[CE], win[HI]);
@@ -504,11 +524,12 @@ struct LKTraits {
     static constexpr int occupancy = big && !recompute ? 1 : 2;
 };
 
-template <typename TS, typename TC, int NPT>
+template <typename TS, typename TC, int NPT, bool CL>
 __global__ __launch_bounds__(64 * WPG, (LKTraits<TC, NPT>::occupancy)) void k_fused2d_lk(const TS *__restrict__ G, TS *__restrict__ Gn,
                                                             double *__restrict__ H, const double *__restrict__ rec,
                                                             const double *__restrict__ wrec,
-                                                            const Params *__restrict__ Pd, Geom geo)
+                                                            const Params *__restrict__ Pd, Geom geo,
+                                                            const uint8_t *__restrict__ cls)
 {
     const Params &P = *Pd;
     __shared__ double s_tab[WPG][3 * 2 * MAXV];
@@ -517,7 +538,8 @@ __global__ __launch_bounds__(64 * WPG, (LKTraits<TC, NPT>::occupancy)) void k_fu
     const int cg = t % geo.ncg, sg = t / geo.ncg;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform: cell indices live in SGPRs
     constexpr bool RC = LKTraits<TC, NPT>::recompute;
-    PassLK<TS, TC, NPT, RC> ps;
+    PassLK<TS, TC, NPT, RC, CL> ps;
+    ps.cls = cls;
     ps.G = G; ps.Gn = Gn; ps.H = H; ps.rec = rec; ps.wrec = wrec; ps.P = Pd;
     ps.tab = s_tab[wv];
     ps.lane = threadIdx.x & 63;
@@ -538,10 +560,13 @@ __global__ __launch_bounds__(64 * WPG, (LKTraits<TC, NPT>::occupancy)) void k_fu
     const int j0 = sg * geo.seg, j1 = min(P.ny, j0 + geo.seg);
 
     TC win[3][NPT];
-    ps.xsweep(j0, j0 & 1, win[1]);
-    if (j0 > 0) ps.xsweep(j0 - 1, 2, win[0]);
-    else if (P.bc[2].kind == BC_PERIODIC) ps.xsweep(P.ny - 1, 2, win[0]);
-    else ps.ghost(P.bc[2].kind, win[1], win[0]);
+    // closure form: the prologue rows are needed only for solved rows of the segment
+    if (!CL || ps.micro_row(j0 - 1) || ps.micro_row(j0) || ps.micro_row(j0 + 1)) ps.xsweep(j0, j0 & 1, win[1]);
+    if (!CL || ps.micro_row(j0)) {
+        if (j0 > 0) ps.xsweep(j0 - 1, 2, win[0]);
+        else if (P.bc[2].kind == BC_PERIODIC) ps.xsweep(P.ny - 1, 2, win[0]);
+        else ps.ghost(P.bc[2].kind, win[1], win[0]);
+    }
     // full rounds of three rows rotate the window back to its start; the tail
     // (one or two rows) runs after the loop so the window is never merged
     int j = j0;
@@ -554,15 +579,15 @@ __global__ __launch_bounds__(64 * WPG, (LKTraits<TC, NPT>::occupancy)) void k_fu
     if (j + 1 < j1) ps.template step<1, 2, 0>(j + 1, j1, win);
 }
 
-template <typename TS, typename TC>
+template <typename TS, typename TC, bool CL>
 bool launch_lk_t(int npt, const void *G, void *Gn, double *H, const double *rec, const double *wrec,
-                 const Params *Pd, const Geom &geo, hipStream_t st)
+                 const Params *Pd, const Geom &geo, const uint8_t *cls, hipStream_t st)
 {
     const dim3 grid(((geo.ntiles + 7) / 8) * 8), block(64 * WPG);
 #define MM_CASE(N)                                                                                          \
     case N:                                                                                                 \
-        hipLaunchKernelGGL((k_fused2d_lk<TS, TC, N>), grid, block, 0, st, (const TS *)G, (TS *)Gn, H, rec,  \
-                           wrec, Pd, geo);                                                                  \
+        hipLaunchKernelGGL((k_fused2d_lk<TS, TC, N, CL>), grid, block, 0, st, (const TS *)G, (TS *)Gn, H,   \
+                           rec, wrec, Pd, geo, cls);                                                        \
         return true;
     switch (npt) {
         MM_CASE(1)
@@ -588,14 +613,16 @@ bool lk_supported(const Params &P)
 }
 
 bool launch_micro_lk2d(const void *G, void *Gn, double *H, const double *rec, const double *wrec,
-                       const Params &P, const Params *Pd, int precision, hipStream_t st)
+                       const Params &P, const Params *Pd, int precision, const uint8_t *cls, hipStream_t st)
 {
     if (!lk_supported(P)) return false;
     const int npt = P.nv / 64;
     const bool one_wave = precision == 0 && 8 * npt >= 64;
     const Geom geo = geometry(P, one_wave ? 1 : 2);
-    return precision == 0 ? launch_lk_t<double, double>(npt, G, Gn, H, rec, wrec, Pd, geo, st)
-                          : launch_lk_t<float, float>(npt, G, Gn, H, rec, wrec, Pd, geo, st);
+    if (cls)   // closure form: g in FP32 only
+        return precision != 0 && launch_lk_t<float, float, true>(npt, G, Gn, H, rec, wrec, Pd, geo, cls, st);
+    return precision == 0 ? launch_lk_t<double, double, false>(npt, G, Gn, H, rec, wrec, Pd, geo, nullptr, st)
+                          : launch_lk_t<float, float, false>(npt, G, Gn, H, rec, wrec, Pd, geo, nullptr, st);
 }
 
 } // namespace mm

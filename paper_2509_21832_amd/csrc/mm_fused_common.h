@@ -206,7 +206,8 @@ inline Geom geometry(const Params &P, int occupancy)
 
 // the lane-k specialisation of the fused pass (mm_fused2d_lk.hip)
 bool lk_supported(const Params &P);
+// cls: nullptr, or (closure form, g in FP32) the per-cell flags of solved cells
 bool launch_micro_lk2d(const void *G, void *Gn, double *H, const double *rec, const double *wrec,
-                       const Params &P, const Params *Pd, int precision, hipStream_t st);
+                       const Params &P, const Params *Pd, int precision, const uint8_t *cls, hipStream_t st);
 
 } // namespace mm

@@ -11,7 +11,9 @@
 #include <vector>
 
 #include "../../include/mm.h"
+#include "mm_closure.h"
 #include "mm_launch.h"
+#include "mm_mlp_impl.h"
 
 namespace {
 
@@ -42,6 +44,15 @@ struct mm_ctx {
     std::vector<hipEvent_t> pool;
     int tcount[MM_TIMING_CLASSES] = {};
     double tms[MM_TIMING_CLASSES] = {};
+    // closure form (and the snapshot / feature entry points)
+    bool closure = false, closure_set = false;
+    mm_mlp *net = nullptr;           // NULL with closure_set: the NSF closure
+    float kn_max = 0.0f;
+    float *cl_feat = nullptr, *cl_kn = nullptr, *cl_out = nullptr;
+    uint8_t *cl_edge = nullptr, *cl_cls = nullptr, *cl_valid[2] = {nullptr, nullptr};
+    int cl_vcur = 0;
+    unsigned long long *cl_ncl = nullptr;   // closure cells, summed over steps (device)
+    int *cl_snap = nullptr;                  // rows of the snapshot buffers (device)
 };
 
 namespace {
@@ -64,7 +75,7 @@ int check_cfg(const mm_config *c)
     if (c->dim == 2 && (!(c->nu >= -1.0) || !(c->nu < 1.0))) return MM_EINVAL;
     if (c->tau_model < 0 || c->tau_model > 3 || !(c->tau_coef > 0.0)) return MM_EINVAL;
     if (c->proj_mode != MM_PROJ_DISCRETE && c->proj_mode != MM_PROJ_PAPER) return MM_EINVAL;
-    if (c->precision != MM_FP64 && c->precision != MM_MIXED) return MM_EINVAL;   // MM_CLOSURE: not built
+    if (c->precision != MM_FP64 && c->precision != MM_MIXED && c->precision != MM_CLOSURE) return MM_EINVAL;
     if (c->dim == 1 && c->precision != MM_FP64) return MM_EINVAL;
     const int nside = c->dim == 2 ? 4 : 2;
     for (int s = 0; s < nside; ++s) {
@@ -127,6 +138,10 @@ void release(mm_ctx *c)
     double *bufs[] = {c->Q, c->Qs, c->H, c->rec, c->wrec, c->gmom, c->Gs};
     for (double *b : bufs)
         if (b) hipFree(b);
+    void *cbufs[] = {c->cl_feat, c->cl_kn, c->cl_out, c->cl_edge, c->cl_cls, c->cl_valid[0], c->cl_valid[1],
+                     c->cl_ncl, c->cl_snap};
+    for (void *b : cbufs)
+        if (b) hipFree(b);
     for (void *g : c->G)
         if (g) hipFree(g);
     if (c->flag) hipFree(c->flag);
@@ -151,9 +166,44 @@ int upload_state(mm_ctx *c, const double *q, const double *g)
     }
     const int none = INT_MAX;
     HIP_TRY(hipMemcpyAsync(c->flag, &none, sizeof(int), hipMemcpyHostToDevice, c->st));
+    // closure form: the given G is current everywhere
+    for (uint8_t *v : c->cl_valid)
+        if (v) HIP_TRY(hipMemsetAsync(v, 1, c->ncell, c->st));
     HIP_TRY(hipMemsetAsync(c->H, 0, sizeof(double) * 4 * c->ncell, c->st));
     HIP_TRY(hipStreamSynchronize(c->st));
     c->failed = -1;
+    return MM_OK;
+}
+
+// feature / class buffers of the closure form and of the snapshot entry points
+int ensure_closure_buffers(mm_ctx *c, bool stepping)
+{
+    const size_t n = c->ncell;
+    bool ok = true;
+    if (!c->cl_feat) ok = ok && hipMalloc(&c->cl_feat, sizeof(float) * mm::closure::NF * n) == hipSuccess;
+    if (!c->cl_kn) ok = ok && hipMalloc(&c->cl_kn, sizeof(float) * n) == hipSuccess;
+    if (!c->cl_edge) ok = ok && hipMalloc(&c->cl_edge, n) == hipSuccess;
+    if (!c->cl_out) ok = ok && hipMalloc(&c->cl_out, sizeof(float) * mm::closure::NO * n) == hipSuccess;
+    if (!c->cl_ncl) {
+        ok = ok && hipMalloc(&c->cl_ncl, sizeof(unsigned long long)) == hipSuccess;
+        if (ok) ok = hipMemset(c->cl_ncl, 0, sizeof(unsigned long long)) == hipSuccess;
+    }
+    if (!c->cl_snap) ok = ok && hipMalloc(&c->cl_snap, sizeof(int)) == hipSuccess;
+    if (stepping) {
+        if (!c->cl_cls) {
+            ok = ok && hipMalloc(&c->cl_cls, n) == hipSuccess;
+            if (ok) ok = hipMemset(c->cl_cls, 1, n) == hipSuccess;
+        }
+        for (uint8_t *&v : c->cl_valid)
+            if (!v) {
+                ok = ok && hipMalloc(&v, n) == hipSuccess;
+                if (ok) ok = hipMemset(v, 1, n) == hipSuccess;
+            }
+    }
+    if (!ok) {
+        hipGetLastError();
+        return MM_ENOMEM;
+    }
     return MM_OK;
 }
 
@@ -205,6 +255,7 @@ void collect_timing(mm_ctx *c)
 int enqueue_steps(mm_ctx *c, int nsteps)
 {
     const mm::Params &P = c->P;
+    if (c->closure && !c->closure_set) return MM_EINVAL;
     for (int s = 0; s < nsteps; ++s) {
         const int step = c->steps_done;
         if (c->cfg.dim == 1) {
@@ -219,7 +270,27 @@ int enqueue_steps(mm_ctx *c, int nsteps)
                 Timer t(c, 1);
                 mm::launch_prep2d(c->Q, c->rec, c->wrec, c->flag, step, P, c->st);
             }
-            if (c->fused) {
+            if (c->closure) {
+                {
+                    Timer t(c, 4);
+                    const int n = c->ncell;
+                    mm::closure::launch_features2d(c->Q, P, c->cl_feat, c->cl_kn, c->cl_edge, c->st);
+                    if (c->net) mm::closure::launch_mlp_forward(c->cl_feat, n, c->net->view(), c->cl_out, c->st);
+                    else mm::closure::launch_nsf2d(c->cl_feat, n, P, c->cl_out, c->st);
+                    mm::closure::launch_classify2d(c->cl_kn, c->cl_edge, c->cl_out, n, c->kn_max, P.eps, c->cl_cls,
+                                                   c->H, c->cl_ncl, c->st);
+                    mm::closure::launch_rebuild2d(c->G[c->cur], c->gbytes, c->rec, c->cl_out, c->cl_cls,
+                                                  c->cl_valid[c->cl_vcur], c->cl_valid[1 - c->cl_vcur], P, c->st);
+                }
+                {
+                    Timer t(c, 0);
+                    mm::launch_micro_closure2d(c->G[c->cur], c->G[1 - c->cur], c->H, c->rec, c->wrec, P, c->Pd,
+                                               c->cl_cls, c->st);
+                }
+                c->cl_vcur = 1 - c->cl_vcur;
+                Timer t(c, 3);
+                mm::launch_wall_relax2d(c->G[1 - c->cur], c->gbytes, c->H, c->rec, c->wrec, P, c->st);
+            } else if (c->fused) {
                 {
                     Timer t(c, 0);
                     mm::launch_micro_fused2d(c->G[c->cur], c->G[1 - c->cur], c->H, c->rec, c->wrec, P, c->Pd,
@@ -338,6 +409,11 @@ int mm_init(const mm_config *cfg, const double *q0, const double *g0, mm_ctx **o
         delete c;
         return MM_EINVAL;          // the FP32-storage forms exist only as the fused pass
     }
+    c->closure = cfg->precision == MM_CLOSURE;
+    if (c->closure && !mm::closure_pass_supported(P)) {
+        delete c;
+        return MM_EINVAL;          // the closure form runs on the lane-k pass only
+    }
     if (hipSetDevice(cfg->device) != hipSuccess) {
         delete c;
         return MM_EDEVICE;
@@ -365,6 +441,10 @@ int mm_init(const mm_config *cfg, const double *q0, const double *g0, mm_ctx **o
     if (ok && c->fused) ok = hipMalloc(&c->Pd, sizeof(mm::Params)) == hipSuccess;
     if (!ok) {
         hipGetLastError();
+        release(c);
+        return MM_ENOMEM;
+    }
+    if (c->closure && ensure_closure_buffers(c, true) != MM_OK) {
         release(c);
         return MM_ENOMEM;
     }
@@ -522,6 +602,114 @@ int mm_device_ptrs(mm_ctx *ctx, void **q, void **g, void **h, int *g_bytes)
     if (h) *h = ctx->H;
     if (g_bytes) *g_bytes = ctx->gbytes;
     return MM_OK;
+}
+
+int mm_closure_attach(mm_ctx *ctx, mm_mlp *net, double kn_max)
+{
+    if (!ctx || !ctx->closure || !(kn_max >= 0.0)) return MM_EINVAL;
+    if (net && net->device != ctx->cfg.device) return MM_EINVAL;
+    if (hipStreamSynchronize(ctx->st) != hipSuccess) return MM_EDEVICE;
+    ctx->net = net;
+    ctx->kn_max = (float)kn_max;
+    ctx->closure_set = true;
+    return MM_OK;
+}
+
+int mm_closure_cells(mm_ctx *ctx, long long *n_closure, unsigned char *cls_host)
+{
+    if (!ctx || !ctx->closure) return MM_EINVAL;
+    if (ctx->broken) return MM_ESTATE;
+    if (hipStreamSynchronize(ctx->st) != hipSuccess) return MM_EDEVICE;
+    if (n_closure) {
+        unsigned long long v = 0;
+        HIP_TRY(hipMemcpy(&v, ctx->cl_ncl, sizeof(v), hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemset(ctx->cl_ncl, 0, sizeof(v)));
+        *n_closure = (long long)v;
+    }
+    if (cls_host) HIP_TRY(hipMemcpy(cls_host, ctx->cl_cls, ctx->ncell, hipMemcpyDeviceToHost));
+    return MM_OK;
+}
+
+int mm_closure_snapshot(mm_ctx *ctx, double kn_max, float *x_dev, float *y_dev, int capacity, int *count)
+{
+    if (!ctx || ctx->cfg.dim != 2 || ctx->closure || !x_dev || !y_dev || !count || *count < 0 || capacity < 0)
+        return MM_EINVAL;
+    if (ctx->broken) return MM_ESTATE;
+    if (hipSetDevice(ctx->cfg.device) != hipSuccess) return MM_EDEVICE;
+    int rc = ensure_closure_buffers(ctx, false);
+    if (rc) return rc;
+    if (!ctx->gmom && hipMalloc(&ctx->gmom, sizeof(double) * 7 * ctx->ncell) != hipSuccess) return MM_ENOMEM;
+    mm::closure::launch_features2d(ctx->Q, ctx->P, ctx->cl_feat, ctx->cl_kn, ctx->cl_edge, ctx->st);
+    rc = enqueue_steps(ctx, 1);
+    if (rc) return rc;
+    // g-moments of G^{n+1}; the cell records still hold the velocities of Q^n
+    mm::launch_gmom2d(ctx->G[ctx->cur], ctx->gbytes, ctx->rec, ctx->gmom, ctx->P, ctx->st);
+    int *dcount = ctx->cl_snap;
+    mm::closure::launch_snapshot2d(ctx->cl_feat, ctx->cl_kn, ctx->cl_edge, ctx->H, ctx->gmom, ctx->ncell,
+                                   ctx->P.eps, (float)kn_max, x_dev, y_dev, *count, capacity, dcount, ctx->st);
+    if (hipGetLastError() != hipSuccess) {
+        ctx->broken = true;
+        return MM_EDEVICE;
+    }
+    rc = finish(ctx);
+    int v = 0;
+    HIP_TRY(hipMemcpy(&v, dcount, sizeof(int), hipMemcpyDeviceToHost));
+    *count = v;
+    return rc;
+}
+
+int mm_closure_features(mm_ctx *ctx, float *feat_host, float *kn_host, unsigned char *edge_host)
+{
+    if (!ctx || ctx->cfg.dim != 2 || !feat_host) return MM_EINVAL;
+    if (ctx->broken) return MM_ESTATE;
+    if (hipSetDevice(ctx->cfg.device) != hipSuccess) return MM_EDEVICE;
+    int rc = ensure_closure_buffers(ctx, false);
+    if (rc) return rc;
+    mm::closure::launch_features2d(ctx->Q, ctx->P, ctx->cl_feat, ctx->cl_kn, ctx->cl_edge, ctx->st);
+    if (hipStreamSynchronize(ctx->st) != hipSuccess) return MM_EDEVICE;
+    const size_t n = ctx->ncell;
+    HIP_TRY(hipMemcpy(feat_host, ctx->cl_feat, sizeof(float) * mm::closure::NF * n, hipMemcpyDeviceToHost));
+    if (kn_host) HIP_TRY(hipMemcpy(kn_host, ctx->cl_kn, sizeof(float) * n, hipMemcpyDeviceToHost));
+    if (edge_host) HIP_TRY(hipMemcpy(edge_host, ctx->cl_edge, n, hipMemcpyDeviceToHost));
+    return MM_OK;
+}
+
+int mm_closure_rebuild(mm_ctx *ctx, const float *out_host, const unsigned char *mask)
+{
+    if (!ctx || ctx->cfg.dim != 2 || ctx->cfg.precision == MM_FP64 || !out_host || !mask) return MM_EINVAL;
+    if (ctx->broken) return MM_ESTATE;
+    if (hipSetDevice(ctx->cfg.device) != hipSuccess) return MM_EDEVICE;
+    int rc = ensure_closure_buffers(ctx, false);
+    if (rc) return rc;
+    const size_t n = ctx->ncell;
+    // classes = mask and validity = not mask: exactly the masked cells are rebuilt
+    uint8_t *cls = nullptr, *valid = nullptr, *vnext = nullptr;
+    if (hipMalloc(&cls, n) != hipSuccess || hipMalloc(&valid, n) != hipSuccess || hipMalloc(&vnext, n) != hipSuccess) {
+        hipGetLastError();
+        if (cls) hipFree(cls);
+        if (valid) hipFree(valid);
+        return MM_ENOMEM;
+    }
+    std::vector<uint8_t> m(n), v(n);
+    for (size_t k = 0; k < n; ++k) {
+        m[k] = mask[k] ? 1 : 0;
+        v[k] = 1 - m[k];
+    }
+    rc = MM_OK;
+    if (hipMemcpy(cls, m.data(), n, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(valid, v.data(), n, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(ctx->cl_out, out_host, sizeof(float) * mm::closure::NO * n, hipMemcpyHostToDevice) != hipSuccess)
+        rc = MM_EDEVICE;
+    if (!rc) {
+        mm::launch_prep2d(ctx->Q, ctx->rec, ctx->wrec, ctx->flag, ctx->steps_done, ctx->P, ctx->st);
+        mm::closure::launch_rebuild2d(ctx->G[ctx->cur], ctx->gbytes, ctx->rec, ctx->cl_out, cls, valid, vnext, ctx->P,
+                                      ctx->st);
+        if (hipGetLastError() != hipSuccess || hipStreamSynchronize(ctx->st) != hipSuccess) rc = MM_EDEVICE;
+    }
+    hipFree(cls);
+    hipFree(valid);
+    hipFree(vnext);
+    return rc;
 }
 
 } // extern "C"

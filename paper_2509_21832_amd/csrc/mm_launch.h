@@ -22,6 +22,12 @@ bool fused_supported(const Params &P, int precision);
 void launch_micro_fused2d(const void *G, void *Gn, double *H, const double *rec, const double *wrec,
                           const Params &P, const Params *Pd, int precision, hipStream_t st);
 
+// closure form (g in FP32): the fused pass on the cells flagged in cls only
+// (and the G* rows their y-sweep needs); shapes of the lane-k kernel only
+bool closure_pass_supported(const Params &P);
+bool launch_micro_closure2d(const void *G, void *Gn, double *H, const double *rec, const double *wrec,
+                            const Params &P, const Params *Pd, const uint8_t *cls, hipStream_t st);
+
 // 1D
 void launch_step1d(const double *Q, double *Qn, const double *G, double *Gn, double *H, int *flag, int step,
                    const Params &P, hipStream_t st);

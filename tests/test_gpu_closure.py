@@ -1,0 +1,401 @@
+"""The learned-closure form on the GPU (through the C ABI) against the oracle:
+features and indicator, the network's forward pass and gradient (bf16 matrix
+cores vs an FP64 evaluation at the same rounding points), the rebuilt micro
+part, two hybrid steps assembled from oracle pieces, and the trained closure
+judged by the full micro solve."""
+import numpy as np
+import pytest
+
+import mm_workloads as W
+import oracle
+from gpu_common import log, rel_l1
+
+pytestmark = pytest.mark.gpu
+
+NF, NO = 21, 5
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _B():
+    from paper_2509_21832_amd import binding as B
+    return B
+
+
+def _cavity(seed=3, nx=13, ny=11, nv=16, eps=0.01, amp=0.2):
+    return W.cavity2d(seed=seed, nx=nx, ny=ny, nv=nv, eps=eps, amp=amp)
+
+
+def _developed(p, Q, G, steps=5):
+    """A state with nonzero velocity and g: a few oracle steps."""
+    Qo, Go, Ho = oracle.run(p, Q.reshape(-1), G.reshape(-1), steps)
+    return Qo, Go
+
+
+# ---------------------------------------------------------------- features
+
+@pytest.mark.parametrize("case", ["cavity_walls", "periodic"])
+def test_features_vs_oracle(case):
+    if case == "cavity_walls":
+        p, Q, G = _cavity()
+    else:
+        p, Q, G = W.smooth2d(seed=4, nx=12, ny=10, nv=16, eps=0.05)
+    Q, G = _developed(p, Q, G)
+    B = _B()
+    with B.Solver(p, Q, G) as s:
+        F, kn, edge = s.closure_features()
+    Fo, kno, edgeo = oracle.features2d(p, Q)
+    scale = np.abs(Fo).mean(0) + 1e-30
+    err = np.abs(F - Fo) / (np.abs(Fo) + scale)
+    log(f"[features {case}] max rel {err.max():.3e}; kn max rel {np.max(np.abs(kn - kno) / kno):.3e}")
+    assert err.max() <= 1e-6
+    assert np.allclose(kn, kno, rtol=1e-5, atol=1e-12)
+    assert np.array_equal(edge, edgeo)
+
+
+# ---------------------------------------------------------------- network
+
+def _net(seed, scale=0.25):
+    rng = np.random.default_rng(seed)
+    P = (rng.standard_normal(oracle.mlp_nparam()) * scale).astype(np.float32)
+    N = np.concatenate([rng.standard_normal(NF), rng.uniform(0.5, 2.0, NF), rng.standard_normal(NO),
+                        rng.uniform(0.5, 2.0, NO)]).astype(np.float32)
+    return P, N
+
+
+def _oracle_params(P):
+    """The parameters as the kernels see them: weight matrices rounded to bf16, biases FP32."""
+    P64 = P.astype(np.float64)
+    nw1, nb1, nw2, nb2, nw3 = 64 * 21, 64, 64 * 64, 64, 5 * 64
+    o = 0
+    out = P64.copy()
+    for n, is_w in ((nw1, True), (nb1, False), (nw2, True), (nb2, False), (nw3, True)):
+        if is_w:
+            out[o:o + n] = [oracle.bf16(v) for v in P64[o:o + n]]
+        o += n
+    return out
+
+
+def _norm_dict(N):
+    N = N.astype(np.float64)
+    return {"in_mean": N[:NF], "in_std": N[NF:2 * NF], "out_mean": N[2 * NF:2 * NF + NO],
+            "out_std": N[2 * NF + NO:]}
+
+
+def _inputs(N, n, seed):
+    rng = np.random.default_rng(seed)
+    X = rng.standard_normal((n, NF)) * N[NF:2 * NF] + N[:NF]
+    return X.astype(np.float32)
+
+
+def test_mlp_forward_vs_oracle():
+    torch = _torch()
+    B = _B()
+    P, N = _net(1)
+    n = 1000                                  # 31 full tiles of 32 and a ragged tail of 8
+    X = _inputs(N, n, 2)
+    net = B.Mlp(seed=0)
+    net.set(P, N)
+    Y = net.forward(torch.from_numpy(X).cuda()).cpu().numpy()
+    Yo = oracle.mlp_forward(_oracle_params(P), _norm_dict(N), X.astype(np.float64), bf16=True)
+    e = np.abs(Y - Yo) / N[2 * NF + NO:]
+    log(f"[mlp forward] max {e.max():.3e} mean {e.mean():.3e} (in units of out_std)")
+    # the two sides round the same quantities to bf16; they differ by FP32 vs FP64
+    # sums and rare one-ulp (2^-8) flips of an activation at a rounding boundary
+    assert e.mean() <= 1e-4
+    assert e.max() <= 1e-2
+
+
+def test_mlp_forward_empty_and_tiny():
+    torch = _torch()
+    B = _B()
+    P, N = _net(3)
+    net = B.Mlp(seed=0)
+    net.set(P, N)
+    for n in (1, 31, 33):
+        X = _inputs(N, n, 4)
+        Y = net.forward(torch.from_numpy(X).cuda()).cpu().numpy()
+        Yo = oracle.mlp_forward(_oracle_params(P), _norm_dict(N), X.astype(np.float64), bf16=True)
+        assert np.abs(Y - Yo).max() <= 1e-2 * N[2 * NF + NO:].max()
+    Y0 = net.forward(torch.empty((0, NF), dtype=torch.float32, device="cuda"))
+    assert Y0.shape == (0, NO)
+
+
+def test_mlp_grad_vs_oracle():
+    torch = _torch()
+    B = _B()
+    P, N = _net(5)
+    n = 777
+    X = _inputs(N, n, 6)
+    rng = np.random.default_rng(7)
+    Yt = (rng.standard_normal((n, NO)) * N[2 * NF + NO:] + N[2 * NF:2 * NF + NO]).astype(np.float32)
+    net = B.Mlp(seed=0)
+    net.set(P, N)
+    g, L = net.grad(torch.from_numpy(X).cuda(), torch.from_numpy(Yt).cuda())
+    go, Lo = oracle.mlp_grad(_oracle_params(P), _norm_dict(N), X.astype(np.float64), Yt.astype(np.float64),
+                             bf16=True)
+    e = np.linalg.norm(g - go) / np.linalg.norm(go)
+    blocks = {"W1": (0, 1344), "b1": (1344, 1408), "W2": (1408, 5504), "b2": (5504, 5568), "W3": (5568, 5888),
+              "b3": (5888, 5893)}
+    eb = {k: np.linalg.norm(g[a:b] - go[a:b]) / np.linalg.norm(go[a:b]) for k, (a, b) in blocks.items()}
+    log(f"[mlp grad] rel L2 {e:.3e}; per block " + " ".join(f"{k} {v:.2e}" for k, v in eb.items()) +
+        f"; loss {L:.6f} vs {Lo:.6f}")
+    assert abs(L - Lo) <= 1e-4 * Lo
+    assert e <= 1e-3
+    assert max(eb.values()) <= 3e-3
+
+
+def test_mlp_train_reduces_loss():
+    """Adam on the GPU fits a smooth map of real features."""
+    torch = _torch()
+    B = _B()
+    p, Q, G = W.cavity2d(seed=8, nx=48, ny=48, nv=16, eps=0.01, amp=0.3)
+    with B.Solver(p, Q, G) as s:
+        s.step(5)
+        F, kn, edge = s.closure_features()
+    X = F.astype(np.float64)
+    # targets: a smooth function of the features (stand-in for the micro moments)
+    Yt = np.stack([X[:, 10] * X[:, 0], X[:, 17] * X[:, 3], X[:, 8] - X[:, 16], np.tanh(X[:, 15] + X[:, 9]),
+                   X[:, 4] - X[:, 6]], 1).astype(np.float32)
+    Xt = torch.from_numpy(F).cuda()
+    Yd = torch.from_numpy(Yt).cuda()
+    net = B.Mlp(seed=1)
+    net.fit_norm(Xt, Yd)
+    _, L0 = net.grad(Xt, Yd)
+    losses = net.train(Xt, Yd, epochs=30, batch=256, lr=3e-3, seed=2)
+    _, L1 = net.grad(Xt, Yd)
+    log(f"[mlp train] loss {L0:.4f} -> {L1:.5f}; epochs {np.round(losses[[0, 9, 19, 29]], 5)}")
+    assert np.all(np.isfinite(losses))
+    assert L1 < 0.05 * L0
+
+
+# ---------------------------------------------------------------- rebuilt micro part
+
+@pytest.mark.parametrize("proj", ["discrete", "paper"])
+def test_closure_rebuild_vs_oracle(proj):
+    B = _B()
+    p, Q, G = _cavity(seed=9, nx=9, ny=7, nv=16)
+    p["proj_mode"] = proj
+    Q, G = _developed(p, Q, G, 3)
+    p["precision"] = "mixed"
+    ncell = p["nx"] * p["ny"]
+    rng = np.random.default_rng(10)
+    out = (rng.standard_normal((ncell, NO)) * 0.3).astype(np.float32)
+    mask = rng.uniform(size=ncell) < 0.4
+    with B.Solver(p, Q, G) as s:
+        s.closure_rebuild(out, mask)
+        cells = np.nonzero(mask)[0]
+        Gg = s.get_g_cells(cells)
+        keep = s.get_g_cells(np.nonzero(~mask)[0])
+    Qc = Q.reshape(ncell, 6)
+    ref = np.stack([oracle.closure_grec(p, Qc[c], out[c, :2].astype(np.float64), out[c, 2:].astype(np.float64))
+                    for c in cells])
+    e = np.abs(Gg - ref).max() / np.abs(ref).max()
+    log(f"[rebuild {proj}] {len(cells)} cells, max rel {e:.3e}")
+    assert e <= 1e-6
+    # untouched cells keep their g (FP32 copy of the input)
+    Gc = G.reshape(ncell, -1)[~mask]
+    assert np.abs(keep - Gc).max() <= 1e-6 * np.abs(Gc).max()
+
+
+# ---------------------------------------------------------------- hybrid steps
+
+def test_closure_with_all_cells_solved_equals_mixed():
+    """kn_max = 0 on a non-uniform state: every cell keeps its micro solve, so the closure
+    form must reproduce the FP32-storage form exactly."""
+    B = _B()
+    p, Q, G = _cavity(seed=11, nx=14, ny=12, nv=16)
+    pm = dict(p, precision="mixed")
+    pc = dict(p, precision="closure")
+    with B.Solver(pm, Q, G) as s:
+        s.step(10)
+        Qm, Hm = s.moments(with_h=True)
+        Gm = s.get_g()
+    with B.Solver(pc, Q, G) as s:
+        s.closure_attach(None, 0.0)
+        s.step(10)
+        Qc, Hc = s.moments(with_h=True)
+        Gc = s.get_g()
+        ncl, cls = s.closure_cells()
+    log(f"[all solved] closure cells {ncl}; max |dQ| {np.abs(Qc - Qm).max():.3e}")
+    assert ncl == 0 and cls.all()
+    assert np.array_equal(Qc, Qm) and np.array_equal(Hc, Hm) and np.array_equal(Gc, Gm)
+
+
+def test_closure_without_closure_attached_is_rejected():
+    B = _B()
+    p, Q, G = _cavity(seed=12, nx=8, ny=8, nv=16)
+    p["precision"] = "closure"
+    with B.Solver(p, Q, G) as s:
+        with pytest.raises(B.MMError):
+            s.step(1)
+
+
+def _nsf_out(p, Q):
+    F, kn, edge = oracle.features2d(p, Q)
+    out = np.array([np.concatenate(oracle.nsf_closure(p, f)) for f in F])
+    return F, kn, edge, out
+
+
+def _dilate(cls, p):
+    """cells within the 3 x 3 block of a solved cell (walls: no wrap)"""
+    c = cls.reshape(p["ny"], p["nx"]).astype(bool)
+    per_x = p["bc"][0]["kind"] == "periodic"
+    per_y = p["bc"][2]["kind"] == "periodic"
+    out = np.zeros_like(c)
+    for dj in (-1, 0, 1):
+        for di in (-1, 0, 1):
+            s = np.roll(np.roll(c, dj, 0), di, 1)
+            if not per_y:
+                if dj == 1:
+                    s[0, :] = False
+                if dj == -1:
+                    s[-1, :] = False
+            if not per_x:
+                if di == 1:
+                    s[:, 0] = False
+                if di == -1:
+                    s[:, -1] = False
+            out |= s
+    return out.reshape(-1)
+
+
+@pytest.mark.parametrize("case", ["cavity_walls", "periodic"])
+def test_two_hybrid_steps_vs_oracle_pieces(case):
+    """Two closure steps (NSF closure, threshold at the median indicator) against the oracle
+    composed the same way: classes from the oracle indicator, H = isotropic form of eps q in
+    closure cells, the oracle micro step on the cells it solves with the rebuilt micro parts
+    of the closure cells they need, and the oracle macro step with the assembled H."""
+    B = _B()
+    if case == "cavity_walls":
+        p, Q, G = _cavity(seed=13, nx=16, ny=13, nv=16, eps=0.01)
+    else:
+        p, Q, G = W.smooth2d(seed=14, nx=14, ny=12, nv=16, eps=0.02)
+    Q, G = _developed(p, Q, G, 4)
+    ncell = p["nx"] * p["ny"]
+    F0, kn0, edge0, out0 = _nsf_out(p, Q)
+    thr = float(np.median(kn0[~edge0]))
+    pc = dict(p, precision="closure")
+    with B.Solver(pc, Q, G) as s:
+        s.closure_attach(None, thr)
+        s.step(1)
+        Q1, H1 = s.moments(with_h=True)
+        _, cls1 = s.closure_cells()
+        G1 = s.get_g()
+        s.step(1)
+        Q2, H2 = s.moments(with_h=True)
+        _, cls2 = s.closure_cells()
+        G2 = s.get_g()
+    nv = p["nv1"] * p["nv2"]
+    tol_gap = 1e-5 * thr
+
+    def check_step(Qn, Gn_valid, valid, out_or, kn_or, edge_or, cls_gpu, Qg, Hg, Gg, label):
+        clear = np.abs(kn_or - thr) > tol_gap          # cells not at the threshold
+        cls_or = edge_or | (kn_or > thr)
+        assert np.array_equal(cls_gpu.astype(bool)[clear], cls_or[clear]), label
+        cls = cls_gpu.astype(bool)
+        need = _dilate(cls, p)
+        Gmod = Gn_valid.reshape(ncell, nv).copy()
+        Qc = Qn.reshape(ncell, 6)
+        for c in np.nonzero(need & ~valid)[0]:
+            Gmod[c] = oracle.closure_grec(p, Qc[c], out_or[c, :2], out_or[c, 2:])
+        Go, Ho = oracle.micro2d(p, Qn, Gmod.reshape(-1))
+        Go = Go.reshape(ncell, nv)
+        Ho = Ho.reshape(ncell, 4)
+        Hg = Hg.reshape(ncell, 4)
+        # closure cells: isotropic H of eps q
+        hc = np.array([oracle.closure_H(p["eps"] * out_or[c, :2]) for c in range(ncell)])
+        ecl = np.abs(Hg[~cls] - hc[~cls]).max() / (np.abs(hc[~cls]).max() + 1e-300) if (~cls).any() else 0.0
+        # solved cells: the micro step
+        gsc = np.abs(Go[cls]).max()
+        eg = np.abs(Gg.reshape(ncell, nv)[cls] - Go[cls]).max() / gsc
+        eh = np.abs(Hg[cls] - Ho[cls]).max() / np.abs(Ho[cls]).max()
+        # macro step with the assembled H
+        Qo = oracle.macro2d(p, Qn, Hg.reshape(-1))
+        eq = rel_l1(Qg.reshape(-1), Qo)
+        log(f"[{label}] closure cells {int((~cls).sum())}/{ncell}; H closure rel {ecl:.2e}; g solved rel "
+            f"{eg:.2e}; H solved rel {eh:.2e}; Q rel-L1 {eq:.2e}")
+        assert ecl <= 1e-5
+        assert eg <= 1e-4 and eh <= 1e-4
+        assert eq <= 1e-12
+        return cls
+
+    cls1b = check_step(Q, G, np.ones(ncell, bool), out0, kn0, edge0, cls1, Q1, H1, G1, f"{case} step 1")
+    assert (~cls1b).sum() > 0 and cls1b.sum() > 0
+    F1, kn1, edge1, out1 = _nsf_out(p, Q1)
+    check_step(Q1, G1, cls1b, out1, kn1, edge1, cls2, Q2, H2, G2, f"{case} step 2")
+
+
+# ---------------------------------------------------------------- trained closure
+
+def _snapshots(B, torch, cases, steps, every, kn_max, cap):
+    X = torch.zeros((cap, NF), dtype=torch.float32, device="cuda")
+    Y = torch.zeros((cap, NO), dtype=torch.float32, device="cuda")
+    count = 0
+    for p, Q, G in cases:
+        p = dict(p, precision="mixed")
+        with B.Solver(p, Q, G) as s:
+            for k in range(steps):
+                if k % every == every - 1:
+                    count = s.closure_snapshot(kn_max, X, Y, count)
+                else:
+                    s.step(1)
+    return X[:count].contiguous(), Y[:count].contiguous()
+
+
+def test_trained_closure_judged_by_micro_solve():
+    """Train the network on snapshots the solver generates (cavity and quadrant states), then
+    run the closure form on a held-out cavity: macro rel-L1 against the FP64 full micro solve
+    (the judge) <= 1e-2, most cells on the closure, and the network closer to the micro
+    solve than the Navier-Stokes-Fourier closure in the predicted heat flux."""
+    torch = _torch()
+    B = _B()
+    eps_train = (1e-3, 1e-2)
+    cases = []
+    for k, eps in enumerate(eps_train):
+        cases.append(W.cavity2d(seed=20 + k, nx=64, ny=64, nv=16, eps=eps, amp=0.2))
+        cases.append(W.quadrant2d(seed=30 + k, nx=64, ny=64, nv=16, eps=eps))
+    X, Y = _snapshots(B, torch, cases, steps=120, every=6, kn_max=0.1, cap=2_000_000)
+    log(f"[train] {X.shape[0]} samples")
+    net = B.Mlp(seed=3)
+    net.fit_norm(X, Y)
+    losses = net.train(X, Y, epochs=25, batch=512, lr=2e-3, seed=4)
+    log(f"[train] epoch losses {np.round(losses[[0, 4, 9, 14, 19, 24]], 5)}")
+    assert losses[-1] < 0.2 * losses[0]
+
+    # held-out: a cavity at eps = 3e-3 (between the training values), another seed
+    p, Q, G = W.cavity2d(seed=40, nx=64, ny=64, nv=16, eps=3e-3, amp=0.2)
+    steps = 100
+    with B.Solver(p, Q, G) as s:                                    # judge: FP64 full solve
+        s.step(steps)
+        Qref = s.moments()
+    res = {}
+    for name, closure in (("net", net), ("nsf", None)):
+        with B.Solver(dict(p, precision="closure"), Q, G) as s:
+            s.closure_attach(closure, 0.05)
+            s.step(steps)
+            Qc = s.moments()
+            ncl, _ = s.closure_cells()
+        res[name] = (rel_l1(Qc, Qref), ncl / (steps * p["nx"] * p["ny"]))
+    with B.Solver(dict(p, precision="mixed"), Q, G) as s:
+        s.step(steps)
+        emix = rel_l1(s.moments(), Qref)
+    log(f"[judge] macro rel-L1 vs FP64 full solve: net {res['net'][0]:.3e} (closure fraction "
+        f"{res['net'][1]:.2f}), NSF {res['nsf'][0]:.3e}, FP32-storage full solve {emix:.3e}")
+    assert res["net"][0] <= 1e-2
+    assert res["net"][1] >= 0.5
+
+    # offline: predicted heat flux on held-out snapshots vs the micro solve
+    Xh, Yh = _snapshots(B, torch, [(p, Q, G)], steps=60, every=6, kn_max=0.05, cap=500_000)
+    Yn = net.forward(Xh).cpu().numpy()
+    Yh = Yh.cpu().numpy()
+    Fh = Xh.cpu().numpy().astype(np.float64)
+    Yf = np.array([np.concatenate(oracle.nsf_closure(p, f)) for f in Fh[::7]])
+    e_net = np.sqrt(np.mean((Yn[::7, :2] - Yh[::7, :2]) ** 2))
+    e_nsf = np.sqrt(np.mean((Yf[:, :2] - Yh[::7, :2]) ** 2))
+    log(f"[gain] heat-flux RMS error on held-out snapshots: net {e_net:.4e}, NSF {e_nsf:.4e} "
+        f"(rms of target {np.sqrt(np.mean(Yh[::7, :2] ** 2)):.4e})")
+    assert e_net < e_nsf
