@@ -269,13 +269,20 @@ int mm_mlp_grad(mm_mlp *net, const float *x_dev, const float *y_dev, int n, floa
 int mm_mlp_train(mm_mlp *net, const float *x_dev, const float *y_dev, int n, int epochs, int batch, double lr,
                  unsigned long long seed, double *epoch_loss);
 
-/* mm_closure_attach -- closure of an MM_CLOSURE context: the network `net`
- * (kept by pointer: it must outlive its use and not be trained while the
- * context steps), or NULL for the Navier-Stokes-Fourier values
- *   q = -eps (2 p / tau) grad T,  S = -eps (p / tau) sigma + nu (P - p I)
- * (sigma = grad u + grad u^T - (div u) I); threshold kn_max >= 0.  Stepping an
- * MM_CLOSURE context without a closure gives MM_EINVAL. */
-int mm_closure_attach(mm_ctx *ctx, mm_mlp *net, double kn_max);
+/* mm_closure_attach -- closure of an MM_CLOSURE context, threshold kn_max >= 0:
+ *   net == NULL: the Navier-Stokes-Fourier values
+ *       q = -eps (2 p / tau) grad T,  S = -eps (p / tau) sigma + nu (P - p I)
+ *     (sigma = grad u + grad u^T - (div u) I), the moments of the first-order
+ *     micro part G-hat (eqn5-97);
+ *   net, residual = 0: (q, S) / eps = the network's outputs;
+ *   net, residual = 1: (q, S) / eps = the NSF values plus the network's outputs;
+ *   net, residual = 2: (q, S) / eps = the NSF values plus eps times the
+ *     network's outputs (networks trained on snapshots of the same residual
+ *     kind, see mm_closure_snapshot).
+ * The network is kept by pointer: it must outlive its use and not be trained
+ * while the context steps.  Stepping an MM_CLOSURE context without a closure
+ * gives MM_EINVAL. */
+int mm_closure_attach(mm_ctx *ctx, mm_mlp *net, double kn_max, int residual);
 
 /* mm_closure_cells -- number of closure cells summed over the steps since the
  * previous call, and (cls_host [ny][nx] or NULL) 1 for solved, 0 for closure
@@ -284,11 +291,13 @@ int mm_closure_cells(mm_ctx *ctx, long long *n_closure, unsigned char *cls_host)
 
 /* mm_closure_snapshot -- training data from a full micro solve (MM_FP64 or
  * MM_MIXED context): the features of the current state, one step, the targets
- * of the new micro part.  Rows of cells with kn <= kn_max that are not next to
- * a non-periodic side are appended in cell order to x_dev [capacity][21] and
- * y_dev [capacity][5] (device FP32) from row *count on; *count is updated
- * (at most capacity rows are written). */
-int mm_closure_snapshot(mm_ctx *ctx, double kn_max, float *x_dev, float *y_dev, int capacity, int *count);
+ * of the new micro part (residual = 1: minus the NSF values of the cell).
+ * Rows of cells with kn <= kn_max that are not next to a non-periodic side are
+ * appended in cell order to x_dev [capacity][21] and y_dev [capacity][5]
+ * (device FP32) from row *count on; *count is updated (at most capacity rows
+ * are written). */
+int mm_closure_snapshot(mm_ctx *ctx, double kn_max, int residual, float *x_dev, float *y_dev, int capacity,
+                        int *count);
 
 /* mm_closure_features -- features [ny][nx][21], kn [ny][nx] and the
  * next-to-a-non-periodic-side mask [ny][nx] of the current state (host;

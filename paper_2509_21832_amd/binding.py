@@ -93,9 +93,9 @@ def _load():
     L.mm_mlp_forward.argtypes = [vp, vp, C.c_int, vp]
     L.mm_mlp_grad.argtypes = [vp, vp, vp, C.c_int, fp, dp]
     L.mm_mlp_train.argtypes = [vp, vp, vp, C.c_int, C.c_int, C.c_int, C.c_double, C.c_ulonglong, dp]
-    L.mm_closure_attach.argtypes = [vp, vp, C.c_double]
+    L.mm_closure_attach.argtypes = [vp, vp, C.c_double, C.c_int]
     L.mm_closure_cells.argtypes = [vp, C.POINTER(C.c_longlong), bp]
-    L.mm_closure_snapshot.argtypes = [vp, C.c_double, vp, vp, C.c_int, C.POINTER(C.c_int)]
+    L.mm_closure_snapshot.argtypes = [vp, C.c_double, C.c_int, vp, vp, C.c_int, C.POINTER(C.c_int)]
     L.mm_closure_features.argtypes = [vp, fp, fp, bp]
     L.mm_closure_rebuild.argtypes = [vp, fp, bp]
     for name in EXPORTS:
@@ -278,11 +278,12 @@ class Solver:
         return q.value, g.value, h.value, gb.value
 
     # ---- closure form
-    def closure_attach(self, net, kn_max):
-        """net: an Mlp, or None for the Navier-Stokes-Fourier closure."""
+    def closure_attach(self, net, kn_max, residual=0):
+        """net: an Mlp, or None for the Navier-Stokes-Fourier closure; residual: 0 the network
+        predicts (q, S) / eps, 1 its correction to the NSF values, 2 that correction / eps."""
         self._net = net       # the context keeps the network by pointer
-        _check(_lib.mm_closure_attach(self._ctx, net._h if net is not None else None, float(kn_max)),
-               "mm_closure_attach")
+        _check(_lib.mm_closure_attach(self._ctx, net._h if net is not None else None, float(kn_max),
+                                      int(residual)), "mm_closure_attach")
 
     def closure_cells(self):
         """(closure cells summed over the steps since the last call, classes of the last step [ncell])."""
@@ -291,14 +292,14 @@ class Solver:
         _check(_lib.mm_closure_cells(self._ctx, C.byref(n), _bp(cls)), "mm_closure_cells")
         return n.value, cls
 
-    def closure_snapshot(self, kn_max, X, Y, count):
+    def closure_snapshot(self, kn_max, X, Y, count, residual=0):
         """Append training rows to the device tensors X [cap, 21], Y [cap, 5]; returns the new count."""
         cap = X.shape[0]
         if Y.shape[0] != cap:
             raise ValueError("X and Y capacities differ")
         c = C.c_int(int(count))
-        _check(_lib.mm_closure_snapshot(self._ctx, float(kn_max), _dev(X, N_FEAT), _dev(Y, N_OUT), int(cap),
-                                        C.byref(c)), "mm_closure_snapshot")
+        _check(_lib.mm_closure_snapshot(self._ctx, float(kn_max), int(residual), _dev(X, N_FEAT),
+                                        _dev(Y, N_OUT), int(cap), C.byref(c)), "mm_closure_snapshot")
         return c.value
 
     def closure_features(self):

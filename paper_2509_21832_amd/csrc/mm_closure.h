@@ -26,7 +26,9 @@ struct MlpDevMut {
 };
 
 void launch_features2d(const double *Q, const Params &P, float *feat, float *kn, uint8_t *edge, hipStream_t st);
-void launch_mlp_forward(const float *X, int n, const MlpDev &w, float *Y, hipStream_t st);
+// Y = MLP(X), or Y += scale MLP(X) with accumulate
+void launch_mlp_forward(const float *X, int n, const MlpDev &w, float *Y, bool accumulate, float scale,
+                        hipStream_t st);
 // nwaves must be even; part holds nwaves * NPARAM floats, loss_part nwaves
 void launch_mlp_grad(const float *X, const float *Y, const int *idx, int first, int count, const MlpDev &w,
                      float *part, float *loss_part, int nwaves, hipStream_t st);
@@ -37,13 +39,16 @@ void launch_mlp_adam(float *master, float *m1, float *m2, const float *grad, flo
 void launch_mlp_pack(const float *master, const MlpDevMut &w, hipStream_t st);
 void launch_mlp_norm(const float *X, const float *Y, int n, float *norm, hipStream_t st);
 void launch_nsf2d(const float *feat, int n, const Params &P, float *out, hipStream_t st);
+// classes and closure-cell H; also empties the rebuild list (*nrebuild = 0)
 void launch_classify2d(const float *kn, const uint8_t *edge, const float *out, int n, float kn_max, double eps,
-                       uint8_t *cls, double *H, unsigned long long *nclosure, hipStream_t st);
+                       uint8_t *cls, double *H, unsigned long long *nclosure, int *nrebuild, hipStream_t st);
+// list (ncell ints) the cells to rebuild, then rebuild them; *nrebuild must be 0 on entry
 void launch_rebuild2d(void *G, int g_bytes, const double *rec, const float *out, const uint8_t *cls,
-                      const uint8_t *valid, uint8_t *valid_next, const Params &P, hipStream_t st);
+                      const uint8_t *valid, uint8_t *valid_next, int *list, int *nrebuild, const Params &P,
+                      hipStream_t st);
 void launch_snapshot2d(const float *feat, const float *kn, const uint8_t *edge, const double *H, const double *gm,
-                       int n, double eps, float kn_max, float *Xo, float *Yo, int base, int capacity, int *count,
-                       hipStream_t st);
+                       int n, const Params &P, int residual, float kn_max, float *Xo, float *Yo, int base,
+                       int capacity, int *count, hipStream_t st);
 
 } // namespace closure
 } // namespace mm

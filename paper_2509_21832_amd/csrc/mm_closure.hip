@@ -171,8 +171,9 @@ __device__ void forward_tile(const SmemW &W, SmemFwd &F, SmemBwd *Bw, const floa
 
 // ------------------------------------------------------------- inference
 
+// Y = MLP(X) (accumulate = 0) or Y += scale MLP(X) (accumulate = 1)
 __global__ __launch_bounds__(256) void k_mlp_forward(const float *__restrict__ X, int n, MlpDev w,
-                                                     float *__restrict__ Y)
+                                                     float *__restrict__ Y, int accumulate, float scale)
 {
     __shared__ SmemW W;
     __shared__ SmemFwd F[4];
@@ -187,7 +188,10 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const float *__restrict__ X
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int o = 4 * (lane >> 5) + v;
-                if (o < NO) Y[(size_t)s * NO + o] = yh[v] * W.nrm[2 * NF + NO + o] + W.nrm[2 * NF + o];
+                if (o < NO) {
+                    const float y = yh[v] * W.nrm[2 * NF + NO + o] + W.nrm[2 * NF + o];
+                    Y[(size_t)s * NO + o] = accumulate ? Y[(size_t)s * NO + o] + scale * y : y;
+                }
             }
         }
         wave_sync();
@@ -477,20 +481,28 @@ __global__ void k_features2d(const double *__restrict__ Q, Params P, float *__re
     edge[c] = (!px && (i == 0 || i == P.nx - 1)) || (!py && (j == 0 || j == P.ny - 1));
 }
 
-// Navier-Stokes-Fourier values of (q, S) / eps from the features (the baseline closure)
+// Navier-Stokes-Fourier values of (q, S) / eps from the features of a cell:
+// q = -(2 p / tau) grad T and S = -(p / tau) sigma + nu (P - p I) / eps, the
+// moments of the first-order micro part G-hat (eqn5-97) with the ES term
+__device__ __forceinline__ void nsf5(const float *f, const Params &P, double o[NO])
+{
+    const double rho = f[0], T = f[3], p = rho * T, tau = tau_of(P, rho, p, T);
+    const double s11 = (double)f[8] - f[16], s12 = (double)f[15] + f[9];
+    o[0] = -2.0 * p / tau * f[10];
+    o[1] = -2.0 * p / tau * f[17];
+    o[2] = -(p / tau) * s11 + P.nu * (f[4] - p) / P.eps;
+    o[3] = -(p / tau) * s12 + P.nu * f[5] / P.eps;
+    o[4] = (p / tau) * s11 + P.nu * (f[6] - p) / P.eps;
+}
+
 __global__ void k_nsf2d(const float *__restrict__ feat, int n, Params P, float *__restrict__ out)
 {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= n) return;
-    const float *f = feat + (size_t)c * NF;
-    const double rho = f[0], T = f[3], p = rho * T, tau = tau_of(P, rho, p, T);
-    const double s11 = (double)f[8] - f[16], s12 = (double)f[15] + f[9];
-    float *o = out + (size_t)c * NO;
-    o[0] = (float)(-2.0 * p / tau * f[10]);
-    o[1] = (float)(-2.0 * p / tau * f[17]);
-    o[2] = (float)(-(p / tau) * s11 + P.nu * (f[4] - p) / P.eps);
-    o[3] = (float)(-(p / tau) * s12 + P.nu * f[5] / P.eps);
-    o[4] = (float)((p / tau) * s11 + P.nu * (f[6] - p) / P.eps);
+    double o[NO];
+    nsf5(feat + (size_t)c * NF, P, o);
+#pragma unroll
+    for (int k = 0; k < NO; ++k) out[(size_t)c * NO + k] = (float)o[k];
 }
 
 // Cell classes: micro (1) next to a non-periodic side or where kn > kn_max,
@@ -498,9 +510,10 @@ __global__ void k_nsf2d(const float *__restrict__ feat, int n, Params P, float *
 __global__ void k_classify2d(const float *__restrict__ kn, const uint8_t *__restrict__ edge,
                              const float *__restrict__ out, int n, float kn_max, double eps,
                              uint8_t *__restrict__ cls, double *__restrict__ H,
-                             unsigned long long *__restrict__ nclosure)
+                             unsigned long long *__restrict__ nclosure, int *__restrict__ nrebuild)
 {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c == 0) *nrebuild = 0;       // the list of k_need2d starts empty
     bool closure = false;
     if (c < n) {
         const bool micro = edge[c] || !(kn[c] <= kn_max);
@@ -519,86 +532,111 @@ __global__ void k_classify2d(const float *__restrict__ kn, const uint8_t *__rest
     if ((threadIdx.x & 63) == 0 && b) atomicAdd(nclosure, (unsigned long long)__popcll(b));
 }
 
-// Rebuild G^n of closure cells that a micro cell needs (the 3 x 3 block around
-// every micro cell) and whose G is not current, from their (q, S) / eps:
-//   g = M / (2 p T) [S' : w w^T + (q . w)(|w|^2 / (2T) - 2)],  then (I - Pi) g,
-// with S' the traceless part of S.  One wavefront per cell.  Also writes the
-// validity of G^{n+1} (= micro) to valid_next.
-template <typename TS>
-__global__ __launch_bounds__(256) void k_rebuild2d(TS *__restrict__ G, const double *__restrict__ rec,
-                                                   const float *__restrict__ out, const uint8_t *__restrict__ cls,
-                                                   const uint8_t *__restrict__ valid, uint8_t *__restrict__ valid_next,
-                                                   Params P)
+// Cells whose micro part a solved cell needs (its 3 x 3 block) but whose G^n is
+// not current go to a list; the validity of G^{n+1} (= solved) goes to
+// valid_next.  One thread per cell.
+__global__ void k_need2d(const uint8_t *__restrict__ cls, const uint8_t *__restrict__ valid,
+                         uint8_t *__restrict__ valid_next, int *__restrict__ list, int *__restrict__ nrebuild,
+                         Params P)
 {
-    const int lane = threadIdx.x & 63;
-    const int c = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= P.nx * P.ny) return;
     const int i = c % P.nx, j = c / P.nx;
     const bool px = P.bc[0].kind == BC_PERIODIC, py = P.bc[2].kind == BC_PERIODIC;
     bool need = false;
+#pragma unroll
     for (int dj = -1; dj <= 1; ++dj)
+#pragma unroll
         for (int di = -1; di <= 1; ++di) {
             int ii = i + di, jj = j + dj;
-            if (ii < 0 || ii >= P.nx) { if (!px) continue; ii = (ii + P.nx) % P.nx; }
-            if (jj < 0 || jj >= P.ny) { if (!py) continue; jj = (jj + P.ny) % P.ny; }
-            need = need || cls[jj * P.nx + ii];
+            bool in = true;
+            if (ii < 0 || ii >= P.nx) {
+                in = px;
+                ii = ii < 0 ? ii + P.nx : ii - P.nx;
+            }
+            if (jj < 0 || jj >= P.ny) {
+                in = in && py;
+                jj = jj < 0 ? jj + P.ny : jj - P.ny;
+            }
+            if (in && cls[jj * P.nx + ii]) need = true;
         }
-    if (lane == 0) valid_next[c] = cls[c];
-    if (!need || valid[c]) return;
-    const double *R = rec + (size_t)c * REC;
-    fused::Cell<double> cl;
-    fused::load_cell(R, cl);
-    const double T = R[R_T], rho = R[R_RHO], p = rho * T;
-    const float *o = out + (size_t)c * NO;
-    const double q1 = o[0], q2 = o[1];
-    const double tr = 0.5 * ((double)o[2] + o[4]);
-    const double a11 = o[2] - tr, a12 = o[3], a22 = o[4] - tr;
-    const double pre = 1.0 / (2.0 * p * T);
-    // raw values and their (1, v1, v2, |v|^2) sums
-    double s[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int n = lane; n < P.nv; n += 64) {
-        const int k = n % P.nv1, l = n / P.nv1;
-        const double v1 = P.v1_lo + (k + 0.5) * P.dv1, v2 = P.v2_lo + (l + 0.5) * P.dv2;
-        const double w1 = v1 - cl.u1d, w2 = v2 - cl.u2d, ww = w1 * w1 + w2 * w2;
-        const double M = R[R_MPRE] * exp(-ww * R[R_I2T]);
-        const double g = M * pre * (a11 * w1 * w1 + 2.0 * a12 * w1 * w2 + a22 * w2 * w2 +
-                                    (q1 * w1 + q2 * w2) * (ww / (2.0 * T) - 2.0));
-        s[0] += g;
-        s[1] += v1 * g;
-        s[2] += v2 * g;
-        s[3] += (v1 * v1 + v2 * v2) * g;
-    }
+    valid_next[c] = cls[c];
+    if (need && !valid[c]) list[atomicAdd(nrebuild, 1)] = c;
+}
+
+// Rebuild the listed cells from their (q, S) / eps:
+//   g = M / (2 p T) [S' : w w^T + (q . w)(|w|^2 / (2T) - 2)],  then (I - Pi) g,
+// with S' the traceless part of S.  A fixed grid of wavefronts walks the list,
+// one cell per wavefront at a time.
+template <typename TS>
+__global__ __launch_bounds__(256) void k_rebuild2d(TS *__restrict__ G, const double *__restrict__ rec,
+                                                   const float *__restrict__ out, const int *__restrict__ list,
+                                                   const int *__restrict__ nrebuild, Params P)
+{
+    const int lane = threadIdx.x & 63;
+    const int w0 = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+    const int nw = gridDim.x * 4;
+    const int count = *nrebuild;
+    for (int t = w0; t < count; t += nw) {
+        const int c = __builtin_amdgcn_readfirstlane(list[t]);
+        const double *R = rec + (size_t)c * REC;
+        fused::Cell<double> cl;
+        fused::load_cell(R, cl);
+        const double T = R[R_T], rho = R[R_RHO], p = rho * T;
+        const float *o = out + (size_t)c * NO;
+        const double q1 = o[0], q2 = o[1];
+        const double tr = 0.5 * ((double)o[2] + o[4]);
+        const double a11 = o[2] - tr, a12 = o[3], a22 = o[4] - tr;
+        const double pre = 1.0 / (2.0 * p * T);
+        // raw values and their (1, v1, v2, |v|^2) sums
+        double s[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int n = lane; n < P.nv; n += 64) {
+            const int k = n % P.nv1, l = n / P.nv1;
+            const double v1 = P.v1_lo + (k + 0.5) * P.dv1, v2 = P.v2_lo + (l + 0.5) * P.dv2;
+            const double w1 = v1 - cl.u1d, w2 = v2 - cl.u2d, ww = w1 * w1 + w2 * w2;
+            const double M = R[R_MPRE] * exp(-ww * R[R_I2T]);
+            const double g = M * pre * (a11 * w1 * w1 + 2.0 * a12 * w1 * w2 + a22 * w2 * w2 +
+                                        (q1 * w1 + q2 * w2) * (ww / (2.0 * T) - 2.0));
+            s[0] += g;
+            s[1] += v1 * g;
+            s[2] += v2 * g;
+            s[3] += (v1 * v1 + v2 * v2) * g;
+        }
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1)
+        for (int off = 32; off > 0; off >>= 1)
 #pragma unroll
-        for (int a = 0; a < 4; ++a) s[a] += __shfl_xor(s[a], off, 64);
-    double cp[4];
-    fused::proj_poly(cl, s, cp);
-    TS *gout = G + (size_t)c * P.nv;
-    for (int n = lane; n < P.nv; n += 64) {
-        const int k = n % P.nv1, l = n / P.nv1;
-        const double v1 = P.v1_lo + (k + 0.5) * P.dv1, v2 = P.v2_lo + (l + 0.5) * P.dv2;
-        const double w1 = v1 - cl.u1d, w2 = v2 - cl.u2d, ww = w1 * w1 + w2 * w2;
-        const double M = R[R_MPRE] * exp(-ww * R[R_I2T]);
-        const double g = M * pre * (a11 * w1 * w1 + 2.0 * a12 * w1 * w2 + a22 * w2 * w2 +
-                                    (q1 * w1 + q2 * w2) * (ww / (2.0 * T) - 2.0));
-        const double pg = (cp[0] + cp[1] * v1 + cp[2] * v2 + cp[3] * (v1 * v1 + v2 * v2)) * M;
-        gout[n] = (TS)(g - pg);
+            for (int a = 0; a < 4; ++a) s[a] += __shfl_xor(s[a], off, 64);
+        double cp[4];
+        fused::proj_poly(cl, s, cp);
+        TS *gout = G + (size_t)c * P.nv;
+        for (int n = lane; n < P.nv; n += 64) {
+            const int k = n % P.nv1, l = n / P.nv1;
+            const double v1 = P.v1_lo + (k + 0.5) * P.dv1, v2 = P.v2_lo + (l + 0.5) * P.dv2;
+            const double w1 = v1 - cl.u1d, w2 = v2 - cl.u2d, ww = w1 * w1 + w2 * w2;
+            const double M = R[R_MPRE] * exp(-ww * R[R_I2T]);
+            const double g = M * pre * (a11 * w1 * w1 + 2.0 * a12 * w1 * w2 + a22 * w2 * w2 +
+                                        (q1 * w1 + q2 * w2) * (ww / (2.0 * T) - 2.0));
+            const double pg = (cp[0] + cp[1] * v1 + cp[2] * v2 + cp[3] * (v1 * v1 + v2 * v2)) * M;
+            gout[n] = (TS)(g - pg);
+        }
     }
 }
 
 // Training targets of every cell from the micro solve: (q1, q2, S11, S12, S22) / eps
 // with q = (H111 + H122, H112 + H222) / 2 and S from the g-moments
 // gm = eps dv sum (w1^2 - w2^2, 2 w1 w2, |w|^2) G / 2 (entries 4..6).
+// With residual = 1 the Navier-Stokes-Fourier values of the cell are
+// subtracted; residual = 2 also divides that difference by eps.
 // Then the cells with kn <= kn_max that are not next to a non-periodic side are
 // appended, in cell order, to (Xo, Yo) from row base (one workgroup; at most
 // capacity rows in total); *count receives the new total.
 __global__ __launch_bounds__(1024) void k_snapshot2d(const float *__restrict__ feat, const float *__restrict__ kn,
                                                      const uint8_t *__restrict__ edge, const double *__restrict__ H,
-                                                     const double *__restrict__ gm, int n, double eps, float kn_max,
-                                                     float *__restrict__ Xo, float *__restrict__ Yo, int base,
-                                                     int capacity, int *__restrict__ count)
+                                                     const double *__restrict__ gm, int n, Params P, int residual,
+                                                     float kn_max, float *__restrict__ Xo, float *__restrict__ Yo,
+                                                     int base, int capacity, int *__restrict__ count)
 {
+    const double eps = P.eps;
     __shared__ int scan[1024];
     const int per = (n + blockDim.x - 1) / blockDim.x;
     const int c0 = threadIdx.x * per, c1 = min(n, c0 + per);
@@ -618,12 +656,18 @@ __global__ __launch_bounds__(1024) void k_snapshot2d(const float *__restrict__ f
         if (pos < capacity) {
             for (int a = 0; a < NF; ++a) Xo[(size_t)pos * NF + a] = feat[(size_t)c * NF + a];
             const double *h = H + 4 * (size_t)c, *m = gm + 7 * (size_t)c;
+            double t[NO] = {0.5 * (h[0] + h[2]) / eps, 0.5 * (h[1] + h[3]) / eps, (m[4] + m[6]) / eps, m[5] / eps,
+                            (m[6] - m[4]) / eps};
+            if (residual) {
+                double b[NO];
+                nsf5(feat + (size_t)c * NF, P, b);
+                const double f = residual == 2 ? 1.0 / eps : 1.0;
+#pragma unroll
+                for (int k = 0; k < NO; ++k) t[k] = (t[k] - b[k]) * f;
+            }
             float *y = Yo + (size_t)pos * NO;
-            y[0] = (float)(0.5 * (h[0] + h[2]) / eps);
-            y[1] = (float)(0.5 * (h[1] + h[3]) / eps);
-            y[2] = (float)((m[4] + m[6]) / eps);
-            y[3] = (float)(m[5] / eps);
-            y[4] = (float)((m[6] - m[4]) / eps);
+#pragma unroll
+            for (int k = 0; k < NO; ++k) y[k] = (float)t[k];
         }
         ++pos;
     }
@@ -642,13 +686,14 @@ void launch_features2d(const double *Q, const Params &P, float *feat, float *kn,
     hipLaunchKernelGGL(k_features2d, dim3((n + 255) / 256), dim3(256), 0, st, Q, P, feat, kn, edge);
 }
 
-void launch_mlp_forward(const float *X, int n, const MlpDev &w, float *Y, hipStream_t st)
+void launch_mlp_forward(const float *X, int n, const MlpDev &w, float *Y, bool accumulate, float scale,
+                        hipStream_t st)
 {
     const int ntile = (n + 31) / 32;
     int blocks = (ntile + 3) / 4;
     if (blocks > 2048) blocks = 2048;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(k_mlp_forward, dim3(blocks), dim3(256), 0, st, X, n, w, Y);
+    hipLaunchKernelGGL(k_mlp_forward, dim3(blocks), dim3(256), 0, st, X, n, w, Y, accumulate ? 1 : 0, scale);
 }
 
 void launch_mlp_grad(const float *X, const float *Y, const int *idx, int first, int count, const MlpDev &w,
@@ -688,29 +733,34 @@ void launch_nsf2d(const float *feat, int n, const Params &P, float *out, hipStre
 }
 
 void launch_classify2d(const float *kn, const uint8_t *edge, const float *out, int n, float kn_max, double eps,
-                       uint8_t *cls, double *H, unsigned long long *nclosure, hipStream_t st)
+                       uint8_t *cls, double *H, unsigned long long *nclosure, int *nrebuild, hipStream_t st)
 {
     hipLaunchKernelGGL(k_classify2d, dim3((n + 255) / 256), dim3(256), 0, st, kn, edge, out, n, kn_max, eps, cls, H,
-                       nclosure);
+                       nclosure, nrebuild);
 }
 
 void launch_rebuild2d(void *G, int g_bytes, const double *rec, const float *out, const uint8_t *cls,
-                      const uint8_t *valid, uint8_t *valid_next, const Params &P, hipStream_t st)
+                      const uint8_t *valid, uint8_t *valid_next, int *list, int *nrebuild, const Params &P,
+                      hipStream_t st)
 {
     const int n = P.nx * P.ny;
-    const dim3 grid((n + 3) / 4), block(256);
+    hipLaunchKernelGGL(k_need2d, dim3((n + 255) / 256), dim3(256), 0, st, cls, valid, valid_next, list, nrebuild, P);
+    int blocks = (n + 3) / 4;
+    if (blocks > 1024) blocks = 1024;
     if (g_bytes == 8)
-        hipLaunchKernelGGL(k_rebuild2d<double>, grid, block, 0, st, (double *)G, rec, out, cls, valid, valid_next, P);
+        hipLaunchKernelGGL(k_rebuild2d<double>, dim3(blocks), dim3(256), 0, st, (double *)G, rec, out, list, nrebuild,
+                           P);
     else
-        hipLaunchKernelGGL(k_rebuild2d<float>, grid, block, 0, st, (float *)G, rec, out, cls, valid, valid_next, P);
+        hipLaunchKernelGGL(k_rebuild2d<float>, dim3(blocks), dim3(256), 0, st, (float *)G, rec, out, list, nrebuild,
+                           P);
 }
 
 void launch_snapshot2d(const float *feat, const float *kn, const uint8_t *edge, const double *H, const double *gm,
-                       int n, double eps, float kn_max, float *Xo, float *Yo, int base, int capacity, int *count,
-                       hipStream_t st)
+                       int n, const Params &P, int residual, float kn_max, float *Xo, float *Yo, int base,
+                       int capacity, int *count, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_snapshot2d, dim3(1), dim3(1024), 0, st, feat, kn, edge, H, gm, n, eps, kn_max, Xo, Yo, base,
-                       capacity, count);
+    hipLaunchKernelGGL(k_snapshot2d, dim3(1), dim3(1024), 0, st, feat, kn, edge, H, gm, n, P, residual, kn_max,
+                       Xo, Yo, base, capacity, count);
 }
 
 } // namespace closure

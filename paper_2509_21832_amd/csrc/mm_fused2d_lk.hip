@@ -475,7 +475,7 @@ struct PassLK {
 
     // closure form: is the micro part of cell (i, r) solved?  Rows beyond a
     // periodic side wrap; beyond any other side there are no cells.
-    __device__ __forceinline__ bool micro_row(int r) const
+    __device__ __forceinline__ bool micro_load(int r) const
     {
         if (r < 0 || r >= P->ny) {
             if (P->bc[2].kind != BC_PERIODIC) return false;
@@ -483,6 +483,10 @@ struct PassLK {
         }
         return cls[(size_t)r * P->nx + i] != 0;
     }
+    // the same from the classes of rows cbase .. cbase + 63, read once per segment
+    uint64_t cmask = 0;
+    int cbase = 0;
+    __device__ __forceinline__ bool micro_row(int r) const { return (cmask >> (r - cbase)) & 1; }
 
     // (closure form: G* of row j+1 is made only if one of rows j, j+1, j+2 is
     // solved, and row j is finished only if it is solved)
@@ -559,6 +563,16 @@ __global__ __launch_bounds__(64 * WPG, (LKTraits<TC, NPT>::occupancy)) void k_fu
     ps.idy = (TC)(1.0 / P.dy);
     const int j0 = sg * geo.seg, j1 = min(P.ny, j0 + geo.seg);
 
+    if constexpr (CL) {
+        // classes of this segment's rows of the column, one per lane, in one ballot
+        // (segments are at most 61 rows); rows of other segments count as not
+        // solved here, since this wavefront finishes only its own rows
+        const int r = j0 - 1 + ps.lane;
+        const bool m = r >= j0 && r < j1 && ps.micro_load(r);
+        ps.cmask = __ballot(m);
+        ps.cbase = j0 - 1;
+        if (ps.cmask == 0) return;
+    }
     TC win[3][NPT];
     // closure form: the prologue rows are needed only for solved rows of the segment
     if (!CL || ps.micro_row(j0 - 1) || ps.micro_row(j0) || ps.micro_row(j0 + 1)) ps.xsweep(j0, j0 & 1, win[1]);
@@ -619,8 +633,15 @@ bool launch_micro_lk2d(const void *G, void *Gn, double *H, const double *rec, co
     const int npt = P.nv / 64;
     const bool one_wave = precision == 0 && 8 * npt >= 64;
     const Geom geo = geometry(P, one_wave ? 1 : 2);
-    if (cls)   // closure form: g in FP32 only
-        return precision != 0 && launch_lk_t<float, float, true>(npt, G, Gn, H, rec, wrec, Pd, geo, cls, st);
+    if (cls) {   // closure form: g in FP32 only
+        // the solved cells cluster along the walls: short row segments spread a
+        // fully solved column over many wavefronts
+        Geom gc = geo;
+        gc.seg = P.ny < 4 ? P.ny : 4;        // at most 61 (one class bit per lane)
+        gc.nseg = (P.ny + gc.seg - 1) / gc.seg;
+        gc.ntiles = gc.ncg * gc.nseg;
+        return precision != 0 && launch_lk_t<float, float, true>(npt, G, Gn, H, rec, wrec, Pd, gc, cls, st);
+    }
     return precision == 0 ? launch_lk_t<double, double, false>(npt, G, Gn, H, rec, wrec, Pd, geo, nullptr, st)
                           : launch_lk_t<float, float, false>(npt, G, Gn, H, rec, wrec, Pd, geo, nullptr, st);
 }

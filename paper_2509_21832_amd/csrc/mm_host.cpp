@@ -46,6 +46,7 @@ struct mm_ctx {
     double tms[MM_TIMING_CLASSES] = {};
     // closure form (and the snapshot / feature entry points)
     bool closure = false, closure_set = false;
+    int residual = 0;
     mm_mlp *net = nullptr;           // NULL with closure_set: the NSF closure
     float kn_max = 0.0f;
     float *cl_feat = nullptr, *cl_kn = nullptr, *cl_out = nullptr;
@@ -53,6 +54,7 @@ struct mm_ctx {
     int cl_vcur = 0;
     unsigned long long *cl_ncl = nullptr;   // closure cells, summed over steps (device)
     int *cl_snap = nullptr;                  // rows of the snapshot buffers (device)
+    int *cl_list = nullptr, *cl_nlist = nullptr;   // cells to rebuild (device)
 };
 
 namespace {
@@ -139,7 +141,7 @@ void release(mm_ctx *c)
     for (double *b : bufs)
         if (b) hipFree(b);
     void *cbufs[] = {c->cl_feat, c->cl_kn, c->cl_out, c->cl_edge, c->cl_cls, c->cl_valid[0], c->cl_valid[1],
-                     c->cl_ncl, c->cl_snap};
+                     c->cl_ncl, c->cl_snap, c->cl_list, c->cl_nlist};
     for (void *b : cbufs)
         if (b) hipFree(b);
     for (void *g : c->G)
@@ -189,6 +191,8 @@ int ensure_closure_buffers(mm_ctx *c, bool stepping)
         if (ok) ok = hipMemset(c->cl_ncl, 0, sizeof(unsigned long long)) == hipSuccess;
     }
     if (!c->cl_snap) ok = ok && hipMalloc(&c->cl_snap, sizeof(int)) == hipSuccess;
+    if (!c->cl_list) ok = ok && hipMalloc(&c->cl_list, sizeof(int) * n) == hipSuccess;
+    if (!c->cl_nlist) ok = ok && hipMalloc(&c->cl_nlist, sizeof(int)) == hipSuccess;
     if (stepping) {
         if (!c->cl_cls) {
             ok = ok && hipMalloc(&c->cl_cls, n) == hipSuccess;
@@ -275,12 +279,15 @@ int enqueue_steps(mm_ctx *c, int nsteps)
                     Timer t(c, 4);
                     const int n = c->ncell;
                     mm::closure::launch_features2d(c->Q, P, c->cl_feat, c->cl_kn, c->cl_edge, c->st);
-                    if (c->net) mm::closure::launch_mlp_forward(c->cl_feat, n, c->net->view(), c->cl_out, c->st);
-                    else mm::closure::launch_nsf2d(c->cl_feat, n, P, c->cl_out, c->st);
+                    if (!c->net || c->residual) mm::closure::launch_nsf2d(c->cl_feat, n, P, c->cl_out, c->st);
+                    if (c->net)
+                        mm::closure::launch_mlp_forward(c->cl_feat, n, c->net->view(), c->cl_out, c->residual != 0,
+                                                        c->residual == 2 ? (float)P.eps : 1.0f, c->st);
                     mm::closure::launch_classify2d(c->cl_kn, c->cl_edge, c->cl_out, n, c->kn_max, P.eps, c->cl_cls,
-                                                   c->H, c->cl_ncl, c->st);
+                                                   c->H, c->cl_ncl, c->cl_nlist, c->st);
                     mm::closure::launch_rebuild2d(c->G[c->cur], c->gbytes, c->rec, c->cl_out, c->cl_cls,
-                                                  c->cl_valid[c->cl_vcur], c->cl_valid[1 - c->cl_vcur], P, c->st);
+                                                  c->cl_valid[c->cl_vcur], c->cl_valid[1 - c->cl_vcur], c->cl_list,
+                                                  c->cl_nlist, P, c->st);
                 }
                 {
                     Timer t(c, 0);
@@ -604,12 +611,13 @@ int mm_device_ptrs(mm_ctx *ctx, void **q, void **g, void **h, int *g_bytes)
     return MM_OK;
 }
 
-int mm_closure_attach(mm_ctx *ctx, mm_mlp *net, double kn_max)
+int mm_closure_attach(mm_ctx *ctx, mm_mlp *net, double kn_max, int residual)
 {
-    if (!ctx || !ctx->closure || !(kn_max >= 0.0)) return MM_EINVAL;
+    if (!ctx || !ctx->closure || !(kn_max >= 0.0) || residual < 0 || residual > 2) return MM_EINVAL;
     if (net && net->device != ctx->cfg.device) return MM_EINVAL;
     if (hipStreamSynchronize(ctx->st) != hipSuccess) return MM_EDEVICE;
     ctx->net = net;
+    ctx->residual = residual;
     ctx->kn_max = (float)kn_max;
     ctx->closure_set = true;
     return MM_OK;
@@ -630,9 +638,11 @@ int mm_closure_cells(mm_ctx *ctx, long long *n_closure, unsigned char *cls_host)
     return MM_OK;
 }
 
-int mm_closure_snapshot(mm_ctx *ctx, double kn_max, float *x_dev, float *y_dev, int capacity, int *count)
+int mm_closure_snapshot(mm_ctx *ctx, double kn_max, int residual, float *x_dev, float *y_dev, int capacity,
+                        int *count)
 {
-    if (!ctx || ctx->cfg.dim != 2 || ctx->closure || !x_dev || !y_dev || !count || *count < 0 || capacity < 0)
+    if (!ctx || ctx->cfg.dim != 2 || ctx->closure || !x_dev || !y_dev || !count || *count < 0 || capacity < 0 ||
+        residual < 0 || residual > 2)
         return MM_EINVAL;
     if (ctx->broken) return MM_ESTATE;
     if (hipSetDevice(ctx->cfg.device) != hipSuccess) return MM_EDEVICE;
@@ -645,8 +655,8 @@ int mm_closure_snapshot(mm_ctx *ctx, double kn_max, float *x_dev, float *y_dev, 
     // g-moments of G^{n+1}; the cell records still hold the velocities of Q^n
     mm::launch_gmom2d(ctx->G[ctx->cur], ctx->gbytes, ctx->rec, ctx->gmom, ctx->P, ctx->st);
     int *dcount = ctx->cl_snap;
-    mm::closure::launch_snapshot2d(ctx->cl_feat, ctx->cl_kn, ctx->cl_edge, ctx->H, ctx->gmom, ctx->ncell,
-                                   ctx->P.eps, (float)kn_max, x_dev, y_dev, *count, capacity, dcount, ctx->st);
+    mm::closure::launch_snapshot2d(ctx->cl_feat, ctx->cl_kn, ctx->cl_edge, ctx->H, ctx->gmom, ctx->ncell, ctx->P,
+                                   residual, (float)kn_max, x_dev, y_dev, *count, capacity, dcount, ctx->st);
     if (hipGetLastError() != hipSuccess) {
         ctx->broken = true;
         return MM_EDEVICE;
@@ -702,8 +712,10 @@ int mm_closure_rebuild(mm_ctx *ctx, const float *out_host, const unsigned char *
         rc = MM_EDEVICE;
     if (!rc) {
         mm::launch_prep2d(ctx->Q, ctx->rec, ctx->wrec, ctx->flag, ctx->steps_done, ctx->P, ctx->st);
-        mm::closure::launch_rebuild2d(ctx->G[ctx->cur], ctx->gbytes, ctx->rec, ctx->cl_out, cls, valid, vnext, ctx->P,
-                                      ctx->st);
+        if (hipMemsetAsync(ctx->cl_nlist, 0, sizeof(int), ctx->st) != hipSuccess) rc = MM_EDEVICE;
+        else
+            mm::closure::launch_rebuild2d(ctx->G[ctx->cur], ctx->gbytes, ctx->rec, ctx->cl_out, cls, valid, vnext,
+                                          ctx->cl_list, ctx->cl_nlist, ctx->P, ctx->st);
         if (hipGetLastError() != hipSuccess || hipStreamSynchronize(ctx->st) != hipSuccess) rc = MM_EDEVICE;
     }
     hipFree(cls);

@@ -192,7 +192,7 @@ int mm_mlp_forward(mm_mlp *n, const float *x_dev, int count, float *y_dev)
     if (!n || count < 0 || (count > 0 && (!x_dev || !y_dev))) return MM_EINVAL;
     if (count == 0) return MM_OK;
     HIP_TRY(hipSetDevice(n->device));
-    launch_mlp_forward(x_dev, count, n->view(), y_dev, n->st);
+    launch_mlp_forward(x_dev, count, n->view(), y_dev, false, 1.0f, n->st);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(n->st));
     return MM_OK;

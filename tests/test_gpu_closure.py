@@ -331,42 +331,34 @@ def test_two_hybrid_steps_vs_oracle_pieces(case):
 
 # ---------------------------------------------------------------- trained closure
 
-def _snapshots(B, torch, cases, steps, every, kn_max, cap):
-    X = torch.zeros((cap, NF), dtype=torch.float32, device="cuda")
-    Y = torch.zeros((cap, NO), dtype=torch.float32, device="cuda")
-    count = 0
-    for p, Q, G in cases:
-        p = dict(p, precision="mixed")
-        with B.Solver(p, Q, G) as s:
-            for k in range(steps):
-                if k % every == every - 1:
-                    count = s.closure_snapshot(kn_max, X, Y, count)
-                else:
-                    s.step(1)
-    return X[:count].contiguous(), Y[:count].contiguous()
+def _snapshots(B, torch, cases, steps, first, every, kn_max, cap, residual):
+    from paper_2509_21832_amd import closure as CL
+    return CL.snapshots(cases, steps=steps, first=first, every=every, kn_max=kn_max, residual=residual, cap=cap)
 
 
-def test_trained_closure_judged_by_micro_solve():
-    """Train the network on snapshots the solver generates (cavity and quadrant states), then
-    run the closure form on a held-out cavity: macro rel-L1 against the FP64 full micro solve
-    (the judge) <= 1e-2, most cells on the closure, and the network closer to the micro
-    solve than the Navier-Stokes-Fourier closure in the predicted heat flux."""
+@pytest.fixture(scope="module")
+def trained():
+    """The closure network trained on the GPU on snapshots of cavity and quadrant runs at
+    eps = 1e-3, 2e-3, 5e-3, 1e-2 (64^2 cells, 16^2 velocity nodes): it learns the
+    correction of the micro solve's (q, S) / eps to the Navier-Stokes-Fourier values,
+    divided by eps."""
+    from paper_2509_21832_amd import closure as CL
+    net, losses, n = CL.trained_closure()
+    log(f"[train] {n} samples; epoch losses {np.round(losses[[0, 4, 9, 19, 29]], 5)}")
+    return net, losses
+
+
+def test_trained_closure_judged_by_micro_solve(trained):
+    """Held-out cavity at eps = 3e-3 (between training values, another seed): macro rel-L1
+    after 100 steps against the FP64 full micro solve (the judge) <= 1e-2 with most cells on
+    the closure and below the error of the Navier-Stokes-Fourier closure; on held-out
+    snapshots, the network's heat flux (the moment that closes the macro system) closer to
+    the micro solve than the NSF closure (the method without the network), its stress no
+    further than the NSF stress (within 10 %)."""
     torch = _torch()
     B = _B()
-    eps_train = (1e-3, 1e-2)
-    cases = []
-    for k, eps in enumerate(eps_train):
-        cases.append(W.cavity2d(seed=20 + k, nx=64, ny=64, nv=16, eps=eps, amp=0.2))
-        cases.append(W.quadrant2d(seed=30 + k, nx=64, ny=64, nv=16, eps=eps))
-    X, Y = _snapshots(B, torch, cases, steps=120, every=6, kn_max=0.1, cap=2_000_000)
-    log(f"[train] {X.shape[0]} samples")
-    net = B.Mlp(seed=3)
-    net.fit_norm(X, Y)
-    losses = net.train(X, Y, epochs=25, batch=512, lr=2e-3, seed=4)
-    log(f"[train] epoch losses {np.round(losses[[0, 4, 9, 14, 19, 24]], 5)}")
-    assert losses[-1] < 0.2 * losses[0]
-
-    # held-out: a cavity at eps = 3e-3 (between the training values), another seed
+    net, losses = trained
+    assert losses[-1] < 0.5 * losses[0]
     p, Q, G = W.cavity2d(seed=40, nx=64, ny=64, nv=16, eps=3e-3, amp=0.2)
     steps = 100
     with B.Solver(p, Q, G) as s:                                    # judge: FP64 full solve
@@ -375,7 +367,7 @@ def test_trained_closure_judged_by_micro_solve():
     res = {}
     for name, closure in (("net", net), ("nsf", None)):
         with B.Solver(dict(p, precision="closure"), Q, G) as s:
-            s.closure_attach(closure, 0.05)
+            s.closure_attach(closure, 0.05, residual=2 if closure is not None else 0)
             s.step(steps)
             Qc = s.moments()
             ncl, _ = s.closure_cells()
@@ -387,15 +379,65 @@ def test_trained_closure_judged_by_micro_solve():
         f"{res['net'][1]:.2f}), NSF {res['nsf'][0]:.3e}, FP32-storage full solve {emix:.3e}")
     assert res["net"][0] <= 1e-2
     assert res["net"][1] >= 0.5
+    assert res["net"][0] < res["nsf"][0]
 
-    # offline: predicted heat flux on held-out snapshots vs the micro solve
-    Xh, Yh = _snapshots(B, torch, [(p, Q, G)], steps=60, every=6, kn_max=0.05, cap=500_000)
-    Yn = net.forward(Xh).cpu().numpy()
-    Yh = Yh.cpu().numpy()
+    # offline, on held-out snapshots after the initial relaxation: raw targets of the micro
+    # solve vs NSF and vs NSF + network correction
+    Xh, Yh = _snapshots(B, torch, [(p, Q, G)], steps=100, first=40, every=5, kn_max=0.05, cap=500_000,
+                        residual=0)
+    Xr, Yr = _snapshots(B, torch, [(p, Q, G)], steps=100, first=40, every=5, kn_max=0.05, cap=500_000,
+                        residual=1)
+    Yh = Yh.cpu().numpy().astype(np.float64)
+    nsf = Yh - Yr.cpu().numpy()                      # the NSF values the kernels used
+    Yn = nsf + p["eps"] * net.forward(Xh).cpu().numpy()
+    rms = lambda a: float(np.sqrt(np.mean(a ** 2)))  # noqa: E731
+    e_q = (rms(Yn[:, :2] - Yh[:, :2]), rms(nsf[:, :2] - Yh[:, :2]))
+    e_s = (rms(Yn[:, 2:] - Yh[:, 2:]), rms(nsf[:, 2:] - Yh[:, 2:]))
+    log(f"[gain] held-out RMS error, heat flux: net {e_q[0]:.4e} NSF {e_q[1]:.4e} (target rms "
+        f"{rms(Yh[:, :2]):.3e}); stress: net {e_s[0]:.4e} NSF {e_s[1]:.4e} (target rms {rms(Yh[:, 2:]):.3e})")
     Fh = Xh.cpu().numpy().astype(np.float64)
-    Yf = np.array([np.concatenate(oracle.nsf_closure(p, f)) for f in Fh[::7]])
-    e_net = np.sqrt(np.mean((Yn[::7, :2] - Yh[::7, :2]) ** 2))
-    e_nsf = np.sqrt(np.mean((Yf[:, :2] - Yh[::7, :2]) ** 2))
-    log(f"[gain] heat-flux RMS error on held-out snapshots: net {e_net:.4e}, NSF {e_nsf:.4e} "
-        f"(rms of target {np.sqrt(np.mean(Yh[::7, :2] ** 2)):.4e})")
-    assert e_net < e_nsf
+    p_ = Fh[:, 0] * Fh[:, 3]
+    Sc = np.stack([Fh[:, 4] - p_, Fh[:, 5], Fh[:, 6] - p_], 1) / p["eps"]
+    log(f"[gain] stress of the macro state (P - p I) / eps: RMS error {rms(Sc - Yh[:, 2:]):.4e}")
+    assert e_q[0] < 0.8 * e_q[1]
+    assert e_s[0] <= 1.1 * e_s[1]
+
+
+def test_trained_closure_speedup_at_full_size(trained):
+    """256^2 cells x 32^2 velocity nodes, eps = 3e-3: the closure form against the
+    FP32-storage full micro solve on the same GPU (wall time of 30 synchronised steps),
+    its macro error against the FP64 full solve after 30 steps."""
+    import time
+    B = _B()
+    net, _ = trained
+    p, Q, G = W.cavity2d(seed=41, eps=3e-3)
+    steps = 30
+    with B.Solver(p, Q, G) as s:
+        s.step(steps)
+        Qref = s.moments()
+    times, errs = {}, {}
+    for form in ("mixed", "closure"):
+        with B.Solver(dict(p, precision=form), Q, G) as s:
+            if form == "closure":
+                s.closure_attach(net, 0.05, residual=2)
+            s.step(steps)
+            errs[form] = rel_l1(s.moments(), Qref)
+            s.step(3)
+            t0 = time.perf_counter()
+            s.step(steps)
+            times[form] = (time.perf_counter() - t0) / steps
+            s.timing(True)
+            s.step(5)
+            parts = {k: s.timing_get(c)[1] / 5 for k, c in
+                     (("pass", 0), ("prep", 1), ("macro", 2), ("wall", 3), ("closure", 4))}
+            s.timing(False)
+            log(f"[speed {form}] per step (ms): " + " ".join(f"{k} {v:.4f}" for k, v in parts.items()))
+            if form == "closure":
+                ncl, _ = s.closure_cells()
+                frac = ncl / ((steps + 3 + steps + 5) * p["nx"] * p["ny"])
+    sp = times["mixed"] / times["closure"]
+    log(f"[speed] ms/step mixed {1e3 * times['mixed']:.3f}, closure {1e3 * times['closure']:.3f} "
+        f"(x{sp:.2f}, closure fraction {frac:.2f}); macro rel-L1 vs FP64: mixed {errs['mixed']:.2e}, "
+        f"closure {errs['closure']:.2e}")
+    assert errs["closure"] <= 1e-2
+    assert sp >= 1.5
