@@ -3,13 +3,14 @@
 Workload (default): the 256 x 256 x 32 x 32 cavity box (67,108,864 phase-space
 points; walls, moving lid, seeded density/temperature perturbations, eps =
 1e-2), FP64.  A step is one full micro-macro step over the whole grid.  The
-same line reports the mixed-precision form (g stored in FP32) on the same
-workload, each form's macro-moment error against the FP64 oracle after 100
-steps, the phase-space pass's HBM roofline fraction, and the oracle timed on
-the host cores.
+same line reports the mixed-precision form (g stored in FP32) and the
+learned-closure form (network trained on the GPU before the timed region, on
+snapshots of the solver's own runs) on the same workload, each form's
+macro-moment error against the FP64 oracle after 100 steps, the phase-space
+pass's HBM roofline fraction, and the oracle timed on the host cores.
 
 Prints one JSON line.  Usage:
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--forms fp64,mixed] [--no-cpu]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--forms fp64,mixed,closure] [--no-cpu]
 """
 import argparse
 import hashlib
@@ -49,8 +50,15 @@ def bytes_per_point(precision):
     return 16 if precision == "fp64" else 8
 
 
-def time_form(B, torch, p, Q, G, steps, warmup):
+def make_solver(B, p, Q, G, closure):
     s = B.Solver(p, Q, G)
+    if p["precision"] == "closure":
+        s.closure_attach(closure["net"], closure["kn_max"], residual=closure["residual"])
+    return s
+
+
+def time_form(B, torch, p, Q, G, steps, warmup, closure=None):
+    s = make_solver(B, p, Q, G, closure)
     s.step(warmup)
     torch.cuda.synchronize()
     s.timing(True)
@@ -63,6 +71,7 @@ def time_form(B, torch, p, Q, G, steps, warmup):
     n_prep, ms_prep = s.timing_get(1)
     n_macro, ms_macro = s.timing_get(2)
     n_wall, ms_wall = s.timing_get(3)
+    n_cl, ms_cl = s.timing_get(4)
     s.timing(False)
     # the same number of steps without event timing (the headline figure)
     torch.cuda.synchronize()
@@ -71,13 +80,19 @@ def time_form(B, torch, p, Q, G, steps, warmup):
     s.sync()
     torch.cuda.synchronize()
     t3 = time.perf_counter()
+    frac = None
+    if p["precision"] == "closure":
+        ncl, _ = s.closure_cells()
+        frac = ncl / ((warmup + 2 * steps) * p["nx"] * p["ny"])
     s.close()
     return {"seconds": t3 - t2, "seconds_timed_run": t1 - t0,
             "micro_ms": ms_micro / max(n_micro, 1), "prep_ms": ms_prep / max(n_prep, 1),
-            "macro_ms": ms_macro / max(n_macro, 1), "wall_ms": ms_wall / max(n_wall, 1), "launches": n_micro}
+            "macro_ms": ms_macro / max(n_macro, 1), "wall_ms": ms_wall / max(n_wall, 1),
+            "closure_ms": ms_cl / max(n_cl, 1), "launches": n_micro,
+            "closure_fraction": frac}
 
 
-def oracle_error(B, p, eps, seed=0):
+def oracle_error(B, p, eps, seed=0, closure=None):
     """Macro rel-L1 after 100 steps against the oracle's stored result (sampled cells)."""
     if not os.path.exists(GOLDEN):
         return None
@@ -88,7 +103,7 @@ def oracle_error(B, p, eps, seed=0):
     st = int(ref["stride"])
     p0, Q0, G0 = W.cavity2d(seed=seed, eps=eps)
     p0["precision"] = p["precision"]
-    with B.Solver(p0, Q0, G0) as s:
+    with make_solver(B, p0, Q0, G0, closure) as s:
         s.step(int(ref["steps"]))
         Q = s.moments().reshape(p0["ny"], p0["nx"], 6)
     a = Q[::st, ::st, :]
@@ -134,7 +149,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--forms", default="fp64,mixed")
+    ap.add_argument("--forms", default="fp64,mixed,closure")
     ap.add_argument("--eps", type=float, default=1e-2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-error", action="store_true")
@@ -164,17 +179,27 @@ def main():
     p, Q, G = W.cavity2d(seed=0, eps=args.eps)
     pts = p["nx"] * p["ny"] * p["nv1"] * p["nv2"]
     forms = {}
+    closure = None
     for form in [f for f in args.forms.split(",") if f]:
         pf = dict(p)
         pf["precision"] = form
+        if form == "closure" and closure is None:
+            # the network, trained on the GPU by the library's kernels (not timed)
+            from paper_2509_21832_amd import closure as CL
+            t0 = time.perf_counter()
+            net, losses, nsamp = CL.trained_closure()
+            closure = {"net": net, "kn_max": CL.KN_MAX, "residual": CL.RESIDUAL,
+                       "train_seconds": time.perf_counter() - t0, "train_samples": nsamp,
+                       "final_loss": float(losses[-1])}
+            log(f"closure network: {nsamp} samples, {closure['train_seconds']:.1f} s, loss {losses[-1]:.4f}")
         try:
-            r = time_form(B, torch, pf, Q, G, args.steps, args.warmup)
+            r = time_form(B, torch, pf, Q, G, args.steps, args.warmup, closure)
         except B.MMError as e:
             log(f"form {form}: {e}")
             continue
         r["value"] = pts * args.steps / r["seconds"]
         r["ms_per_step"] = 1e3 * r["seconds"] / args.steps
-        r["err_vs_oracle"] = None if args.no_error else oracle_error(B, pf, args.eps)
+        r["err_vs_oracle"] = None if args.no_error else oracle_error(B, pf, args.eps, closure=closure)
         bpp = bytes_per_point(form)
         # dominant kernel: the fused phase-space pass (one launch per step, every point
         # read once and written once); its duration from HIP events on the solver's stream
@@ -183,9 +208,11 @@ def main():
                          "peak": HBM_PEAK_GBS, "unit": "GB/s"}
         r["roofline"]["frac"] = r["roofline"]["achieved"] / HBM_PEAK_GBS
         r["roofline"]["traffic"] = traffic_entry(form)
+        if form == "closure":
+            r["roofline"] = None      # the closure pass touches only the solved cells
         forms[form] = r
         log(f"{form}: {r['ms_per_step']:.3f} ms/step, {r['value']:.3e} updates/s, micro pass "
-            f"{r['micro_ms']:.3f} ms ({r['roofline']['frac']:.1%} of HBM peak), err {r['err_vs_oracle']}")
+            f"{r['micro_ms']:.3f} ms, err {r['err_vs_oracle']}")
 
     main_form = forms.get("fp64") or next(iter(forms.values()))
     out = {
@@ -209,11 +236,14 @@ def main():
         "forms": {k: {"value": v["value"], "ms_per_step": v["ms_per_step"], "err_vs_oracle": v["err_vs_oracle"],
                       "speedup_vs_fp64": v["value"] / forms["fp64"]["value"] if "fp64" in forms else None,
                       "micro_pass_ms": v["micro_ms"], "wall_cells_ms": v["wall_ms"], "prep_ms": v["prep_ms"],
-                      "macro_ms": v["macro_ms"],
-                      "roofline_frac": v["roofline"]["frac"]}
+                      "macro_ms": v["macro_ms"], "closure_kernels_ms": v["closure_ms"],
+                      "closure_fraction": v["closure_fraction"],
+                      "roofline_frac": v["roofline"]["frac"] if v["roofline"] else None}
                   for k, v in forms.items()},
         "kernel_hash": kernel_hash(),
     }
+    if closure is not None:
+        out["closure_training"] = {k: closure[k] for k in ("train_seconds", "train_samples", "final_loss")}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(p, Q, G)
     print(json.dumps(out), flush=True)
