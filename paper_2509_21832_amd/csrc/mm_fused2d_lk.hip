@@ -15,6 +15,8 @@
 //     recurrence r(m+1) = r(m) q(m), q(m+1) = q(m) kappa (FP64), or exp m1 of a
 //     directly evaluated delta (FP32), so there is no per-node exponential in
 //     the FP64 pass.
+#include <type_traits>
+
 #include "mm_fused_common.h"
 #include "mm_launch.h"
 
@@ -26,6 +28,9 @@ using namespace fused;
 
 template <typename TS, typename TC, int NPT, bool RC, bool CL>
 struct PassLK {
+    // FP64: cell records are loaded rows ahead into VGPRs (one wavefront per SIMD
+    // has the registers); FP32 keeps two wavefronts per SIMD and reads them in place
+    using Rec = typename std::conditional<sizeof(TC) == 8, RecV, RecP>::type;
     const uint8_t *__restrict__ cls;   // closure form: 1 where the micro part is solved
     const TS *__restrict__ G;
     TS *__restrict__ Gn;
@@ -43,7 +48,7 @@ struct PassLK {
 
     __device__ __forceinline__ const double *slot_tab(int slot) const { return tab + slot * 2 * MAXV; }
 
-    __device__ __forceinline__ void build_tables(int slot, const double *R) const
+    __device__ __forceinline__ void build_tables(int slot, const Rec &R) const
     {
         const double u1 = R[R_U1], u2 = R[R_U2], i2T = R[R_I2T], mpre = R[R_MPRE];
         double *t = tab + slot * 2 * MAXV;
@@ -72,20 +77,51 @@ struct PassLK {
         for (int m = 0; m < NPT; ++m) out[m] = (TC)g[64 * m];
     }
 
-    // x-sweep of row r: G*(i, r) into out; tables of cell (i, r) go to `slot`.
-    __device__ __forceinline__ void xsweep(int r, int slot, TC (&out)[NPT]) const
+    // FP64 (one wavefront per SIMD): the next x-sweep's three cells are loaded
+    // into registers while the current row is computed
+#ifndef MM_LK_PF
+#define MM_LK_PF 0
+#endif
+    static constexpr bool PF = MM_LK_PF && sizeof(TC) == 8 && !CL && !RC;
+    TC pfc[PF ? NPT : 1], pfm[PF ? NPT : 1], pfp[PF ? NPT : 1];
+
+    __device__ __forceinline__ void prefetch(int x)
+    {
+        if constexpr (PF) {
+            const size_t c = (size_t)x * P->nx + i;
+            load(c, pfc);
+            if (i > 0) load(c - 1, pfm);
+            else if (P->bc[0].kind == BC_PERIODIC) load(c + P->nx - 1, pfm);
+            if (i < P->nx - 1) load(c + 1, pfp);
+            else if (P->bc[1].kind == BC_PERIODIC) load(c - (P->nx - 1), pfp);
+        }
+    }
+
+    // x-sweep of row r: G*(i, r) into out; tables of cell (i, r) go to `slot`;
+    // R: the record of cell (i, r).  With the prefetch, the cells come from the
+    // prefetch registers and the loads of row `next` (>= 0) are issued after use.
+    __device__ __forceinline__ void xsweep(int r, int slot, TC (&out)[NPT], const Rec &R, bool pre = false,
+                                           int next = -1)
     {
         const size_t c = (size_t)r * P->nx + i;
-        const double *R = rec + c * REC;
         build_tables(slot, R);
         TC gc[NPT], Z[NPT];
         {
             TC gm[NPT], gp[NPT];
-            load(c, gc);
-            if (i > 0) load(c - 1, gm);
-            else if (P->bc[0].kind == BC_PERIODIC) load(c + P->nx - 1, gm);
-            if (i < P->nx - 1) load(c + 1, gp);
-            else if (P->bc[1].kind == BC_PERIODIC) load(c - (P->nx - 1), gp);
+            if (PF && pre) {
+#pragma unroll
+                for (int m = 0; m < NPT; ++m) {
+                    gc[m] = pfc[PF ? m : 0];
+                    gm[m] = pfm[PF ? m : 0];
+                    gp[m] = pfp[PF ? m : 0];
+                }
+            } else {
+                load(c, gc);
+                if (i > 0) load(c - 1, gm);
+                else if (P->bc[0].kind == BC_PERIODIC) load(c + P->nx - 1, gm);
+                if (i < P->nx - 1) load(c + 1, gp);
+                else if (P->bc[1].kind == BC_PERIODIC) load(c - (P->nx - 1), gp);
+            }
             if (i == 0 && P->bc[0].kind != BC_PERIODIC) {
                 const bool open = is_open(P->bc[0].kind);
 #pragma unroll
@@ -99,6 +135,7 @@ struct PassLK {
 #pragma unroll
             for (int m = 0; m < NPT; ++m) Z[m] = ax * (gp[m] - gc[m]) + bx * (gc[m] - gm[m]);
         }
+        if (PF && next >= 0) prefetch(next);
         double t0 = 0.0, t2 = 0.0, t22 = 0.0;
 #pragma unroll
         for (int m = 0; m < NPT; ++m) {
@@ -158,10 +195,9 @@ struct PassLK {
         for (int m = 0; m < CH; ++m) Z[m] = ax * (gp[m] - gc[m]) + bx * (gc[m] - gm[m]);
     }
 
-    __device__ __forceinline__ void xsweep_rc(int r, int slot, TC (&out)[NPT]) const
+    __device__ __forceinline__ void xsweep_rc(int r, int slot, TC (&out)[NPT], const Rec &R) const
     {
         const size_t c = (size_t)r * P->nx + i;
-        const double *R = rec + c * REC;
         build_tables(slot, R);
         double t0 = 0.0, t2 = 0.0, t22 = 0.0;
 #pragma unroll
@@ -202,9 +238,8 @@ struct PassLK {
     // y-sweep of a wall-adjacent cell: G** only.  The wall form of G-hat, the
     // relaxation and H of these cells are done by k_wall_relax2d afterwards.
     __device__ __forceinline__ void wall_row(size_t c, int slot, const TC (&lo)[NPT], const TC (&ce)[NPT],
-                                             const TC (&hi)[NPT]) const
+                                             const TC (&hi)[NPT], const Rec &R) const
     {
-        const double *R = rec + c * REC;
         Cell<TC> cl;
         load_cell(R, cl);
         const double *t = slot_tab(slot);
@@ -236,9 +271,8 @@ struct PassLK {
 
     // y-sweep, G-hat (eqn5-97), relaxation and H for interior row j with window (lo, ce, hi)
     __device__ __forceinline__ void finish_row(size_t c, int slot, const TC (&lo)[NPT], const TC (&ce)[NPT],
-                                               const TC (&hi)[NPT]) const
+                                               const TC (&hi)[NPT], const Rec &R) const
     {
-        const double *R = rec + c * REC;
         Cell<TC> cl;
         load_cell(R, cl);
         const bool discrete = P->proj_mode == PROJ_DISCRETE;
@@ -340,9 +374,8 @@ struct PassLK {
 
     // y-sweep, G-hat (eqn5-97), relaxation and H for interior row j with window (lo, ce, hi)
     __device__ __forceinline__ void finish_row_rc(size_t c, int slot, const TC (&lo)[NPT], const TC (&ce)[NPT],
-                                               const TC (&hi)[NPT]) const
+                                               const TC (&hi)[NPT], const Rec &R) const
     {
-        const double *R = rec + c * REC;
         Cell<TC> cl;
         load_cell(R, cl);
         const bool discrete = P->proj_mode == PROJ_DISCRETE;
@@ -490,28 +523,60 @@ struct PassLK {
 
     // (closure form: G* of row j+1 is made only if one of rows j, j+1, j+2 is
     // solved, and row j is finished only if it is solved)
+    // row of the x-sweep for window row r (beyond a periodic side: wrapped;
+    // beyond any other side: -1, a ghost row)
+    __device__ __forceinline__ int xrow(int r) const
+    {
+        if (r >= 0 && r < P->ny) return r;
+        if (P->bc[2].kind != BC_PERIODIC) return -1;
+        return r < 0 ? r + P->ny : r - P->ny;
+    }
+
+    static constexpr bool RING = std::is_same<Rec, RecV>::value;
+
+    // FP64: load the record of cell (i, xrow(r)) ahead of its use into a ring slot
+    __device__ __forceinline__ void fetch_rec(int r, Rec &dst) const
+    {
+        if constexpr (RING) {
+            const int x = xrow(r);
+            if (x >= 0) dst = load_rec(rec, (size_t)x * P->nx + i, lane);
+        }
+    }
+
+    // the record of cell (i, x) for its use: the ring slot (FP64) or the record in memory
+    __device__ __forceinline__ Rec rec_at(int x, const Rec &slot) const
+    {
+        if constexpr (RING) return slot;
+        else return Rec{rec + ((size_t)x * P->nx + i) * REC};
+    }
+
     template <int LO, int CE, int HI>
-    __device__ __forceinline__ void step(int j, int j1, TC (&win)[3][NPT])
+    __device__ __forceinline__ void step(int j, int j1, TC (&win)[3][NPT], Rec (&rv)[3])
     {
         refresh();
         __builtin_amdgcn_sched_barrier(0);
+        // records ride with the window: rv[CE] is row j, rv[HI] row j + 1; the
+        // record of row j + 2 (next step's x-sweep) is loaded now into rv[LO]
+        if (j + 2 <= j1) fetch_rec(j + 2, rv[LO]);
         bool solve = true;
         if constexpr (CL) {
             solve = micro_row(j);
             if (!solve && !micro_row(j + 1) && !micro_row(j + 2)) return;
         }
+        const int nxt = (PF && j + 2 <= j1) ? xrow(j + 2) : -1;
         if (j + 1 < P->ny) {
-            if constexpr (RC) xsweep_rc(j + 1, (j + 1) & 1, win[HI]);
-            else xsweep(j + 1, (j + 1) & 1, win[HI]);
+            if constexpr (RC) xsweep_rc(j + 1, (j + 1) & 1, win[HI], rec_at(j + 1, rv[HI]));
+            else xsweep(j + 1, (j + 1) & 1, win[HI], rec_at(j + 1, rv[HI]), PF, nxt);
         }
-        else if (P->bc[3].kind == BC_PERIODIC) xsweep(0, 2, win[HI]);
+        else if (P->bc[3].kind == BC_PERIODIC) xsweep(0, 2, win[HI], rec_at(0, rv[HI]), PF, nxt);
         else ghost(P->bc[3].kind, win[CE], win[HI]);
         __builtin_amdgcn_sched_barrier(0);
         if (CL && !solve) return;
         const size_t c = (size_t)j * P->nx + i;
-        if (rec[c * REC + R_WALL] != 0.0) wall_row(c, j & 1, win[LO], win[CE], win[HI]);
-        else if constexpr (RC) finish_row_rc(c, j & 1, win[LO], win[CE], win[HI]);
-        else finish_row(c, j & 1, win[LO], win[CE], win[HI]);
+        const Rec R = rec_at(j, rv[CE]);
+        if (R[R_WALL] != 0.0) wall_row(c, j & 1, win[LO], win[CE], win[HI], R);
+        else if constexpr (RC) finish_row_rc(c, j & 1, win[LO], win[CE], win[HI], R);
+        else finish_row(c, j & 1, win[LO], win[CE], win[HI], R);
         __builtin_amdgcn_sched_barrier(0);
     }
 };
@@ -521,9 +586,12 @@ struct PassLK {
 // in FP32 the x-sweep and the finish run in chunks that recompute per-node
 // temporaries, which keeps two wavefronts per SIMD (the faster choice for each
 // precision on gfx950).
+#ifndef MM_LK_BIG_BYTES
+#define MM_LK_BIG_BYTES 64
+#endif
 template <typename TC, int NPT>
 struct LKTraits {
-    static constexpr bool big = sizeof(TC) * NPT >= 64;
+    static constexpr bool big = sizeof(TC) * NPT >= MM_LK_BIG_BYTES;
     static constexpr bool recompute = big && sizeof(TC) == 4;
     static constexpr int occupancy = big && !recompute ? 1 : 2;
 };
@@ -574,23 +642,33 @@ __global__ __launch_bounds__(64 * WPG, (LKTraits<TC, NPT>::occupancy)) void k_fu
         if (ps.cmask == 0) return;
     }
     TC win[3][NPT];
+    // records of the window rows j0 - 1, j0, j0 + 1 (slots 0, 1, 2)
+    typename PassLK<TS, TC, NPT, RC, CL>::Rec rv[3] = {};
+    ps.fetch_rec(j0 - 1, rv[0]);
+    ps.fetch_rec(j0, rv[1]);
+    ps.fetch_rec(j0 + 1, rv[2]);
     // closure form: the prologue rows are needed only for solved rows of the segment
-    if (!CL || ps.micro_row(j0 - 1) || ps.micro_row(j0) || ps.micro_row(j0 + 1)) ps.xsweep(j0, j0 & 1, win[1]);
+    if (!CL || ps.micro_row(j0 - 1) || ps.micro_row(j0) || ps.micro_row(j0 + 1))
+        ps.xsweep(j0, j0 & 1, win[1], ps.rec_at(j0, rv[1]));
     if (!CL || ps.micro_row(j0)) {
-        if (j0 > 0) ps.xsweep(j0 - 1, 2, win[0]);
-        else if (P.bc[2].kind == BC_PERIODIC) ps.xsweep(P.ny - 1, 2, win[0]);
+        if (j0 > 0) ps.xsweep(j0 - 1, 2, win[0], ps.rec_at(j0 - 1, rv[0]));
+        else if (P.bc[2].kind == BC_PERIODIC) ps.xsweep(P.ny - 1, 2, win[0], ps.rec_at(P.ny - 1, rv[0]));
         else ps.ghost(P.bc[2].kind, win[1], win[0]);
+    }
+    if (ps.PF) {
+        const int x1 = ps.xrow(j0 + 1);
+        if (x1 >= 0) ps.prefetch(x1);
     }
     // full rounds of three rows rotate the window back to its start; the tail
     // (one or two rows) runs after the loop so the window is never merged
     int j = j0;
     for (; j + 3 <= j1; j += 3) {
-        ps.template step<0, 1, 2>(j, j1, win);
-        ps.template step<1, 2, 0>(j + 1, j1, win);
-        ps.template step<2, 0, 1>(j + 2, j1, win);
+        ps.template step<0, 1, 2>(j, j1, win, rv);
+        ps.template step<1, 2, 0>(j + 1, j1, win, rv);
+        ps.template step<2, 0, 1>(j + 2, j1, win, rv);
     }
-    if (j < j1) ps.template step<0, 1, 2>(j, j1, win);
-    if (j + 1 < j1) ps.template step<1, 2, 0>(j + 1, j1, win);
+    if (j < j1) ps.template step<0, 1, 2>(j, j1, win, rv);
+    if (j + 1 < j1) ps.template step<1, 2, 0>(j + 1, j1, win, rv);
 }
 
 template <typename TS, typename TC, bool CL>
@@ -631,7 +709,7 @@ bool launch_micro_lk2d(const void *G, void *Gn, double *H, const double *rec, co
 {
     if (!lk_supported(P)) return false;
     const int npt = P.nv / 64;
-    const bool one_wave = precision == 0 && 8 * npt >= 64;
+    const bool one_wave = precision == 0 && 8 * npt >= MM_LK_BIG_BYTES;
     const Geom geo = geometry(P, one_wave ? 1 : 2);
     if (cls) {   // closure form: g in FP32 only
         // the solved cells cluster along the walls: short row segments spread a

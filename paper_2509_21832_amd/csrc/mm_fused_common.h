@@ -118,8 +118,31 @@ struct Cell {
     double u1d, u2d, rsTd, i2Td, ra, rb;
 };
 
-template <typename TC>
-__device__ __forceinline__ void load_cell(const double *R, Cell<TC> &c)
+// A per-cell record held in a wavefront's VGPRs, one field per lane (lane q
+// holds field q < REC); a field is read as a wave-uniform value (v_readlane),
+// so a record loaded rows ahead costs no scalar-load round trip when used
+struct RecV {
+    double v;
+    __device__ __forceinline__ double operator[](int q) const { return bcast(v, q); }
+};
+
+// the same interface over the record in memory (scalar loads at each use)
+struct RecP {
+    const double *p;
+    __device__ __forceinline__ double operator[](int q) const { return p[q]; }
+};
+
+// one coalesced load of the record of `cell`
+__device__ __forceinline__ RecV load_rec(const double *rec, size_t cell, int lane)
+{
+    RecV r;
+    r.v = lane < REC ? rec[cell * REC + lane] : 0.0;
+    return r;
+}
+
+// R: a pointer to the record or a RecV
+template <typename TC, typename RT>
+__device__ __forceinline__ void load_cell(const RT &R, Cell<TC> &c)
 {
     c.u1d = R[R_U1];
     c.u2d = R[R_U2];
