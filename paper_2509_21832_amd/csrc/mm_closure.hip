@@ -527,9 +527,15 @@ __global__ void k_classify2d(const float *__restrict__ kn, const uint8_t *__rest
             H[4 * (size_t)c + 3] = 1.5 * q2;
         }
     }
-    // count of closure cells (one atomic per wavefront)
+    // count of closure cells: per-wavefront ballots, one atomic per workgroup
+    __shared__ int wcount[4];
     const unsigned long long b = __ballot(closure);
-    if ((threadIdx.x & 63) == 0 && b) atomicAdd(nclosure, (unsigned long long)__popcll(b));
+    if ((threadIdx.x & 63) == 0) wcount[threadIdx.x >> 6] = (int)__popcll(b);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int tot = wcount[0] + wcount[1] + wcount[2] + wcount[3];
+        if (tot) atomicAdd(nclosure, (unsigned long long)tot);
+    }
 }
 
 // Cells whose micro part a solved cell needs (its 3 x 3 block) but whose G^n is

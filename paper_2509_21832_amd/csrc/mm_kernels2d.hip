@@ -78,14 +78,23 @@ __device__ __forceinline__ void spd_inverse4(const double A[4][4], double scale,
         for (int b = a; b < 4; ++b) out[sym4(a, b)] = scale * 0.5 * (X[a][b] + X[b][a]);
 }
 
-__global__ void k_prep2d(const double *__restrict__ Q, double *__restrict__ rec, double *__restrict__ wrec,
-                         int *__restrict__ flag, int step, Params P)
+// One thread per cell.  The records of the block's cells are assembled in
+// LDS and written out together, so the stores are coalesced.
+constexpr int PREP_BLOCK = 64;
+
+__global__ __launch_bounds__(PREP_BLOCK) void k_prep2d(const double *__restrict__ Q, double *__restrict__ rec,
+                                                       double *__restrict__ wrec, int *__restrict__ flag, int step,
+                                                       Params P)
 {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= P.nx * P.ny) return;
+    __shared__ double s_rec[PREP_BLOCK * REC];
+    const int ncell = P.nx * P.ny;
+    const int c0 = blockIdx.x * PREP_BLOCK;
+    const int c = c0 + threadIdx.x;
+    double *R = s_rec + threadIdx.x * REC;
+    if (c < ncell) {
     const int i = c % P.nx, j = c / P.nx;
     const CellPrim s = prim_of(Q + 6 * (size_t)c);
-    double *R = rec + (size_t)c * REC;
+    for (int q = R_DC + 1; q < REC; ++q) R[q] = 0.0;     // unused tail of the record
 
     const double tau = tau_of(P, s.rho, s.p, s.T);
     const double S11 = (1.0 - P.nu) * s.T + P.nu * s.P11 / s.rho;
@@ -191,6 +200,11 @@ __global__ void k_prep2d(const double *__restrict__ Q, double *__restrict__ rec,
             Wr[4 * d + 3] = 1.0 / (2.0 * g[3]);
         }
     }
+    }
+    __syncthreads();
+    const int ncopy = (ncell - c0 < PREP_BLOCK ? ncell - c0 : PREP_BLOCK) * REC;
+    double *dst = rec + (size_t)c0 * REC;
+    for (int t = threadIdx.x; t < ncopy; t += PREP_BLOCK) dst[t] = s_rec[t];
 }
 
 // ---------------------------------------------------------------------------
@@ -406,35 +420,67 @@ __device__ __forceinline__ void load_q(const double *Q, int c, double q[6])
 }
 
 // dir 0: Q^n -> (collision half) Q* -> KFVS x -> Q**;  dir 1: Q** -> KFVS y -> Q*** -> (collision half) Q^{n+1}
+// Four lanes per cell, one half flux each (the erf / exp of the half-space
+// integrals dominate): lane 0 F+ of the low neighbour, lane 1 F- of the cell
+// (the low face), lane 2 F+ of the cell, lane 3 F- of the high neighbour (the
+// high face).  A boundary face is computed whole by lane 0 or 3 (the other
+// lane of the face adds zero).  Lane 1 combines the faces and writes the cell.
 template <int DIR>
-__global__ void k_macro2d(const double *__restrict__ Qin, const double *__restrict__ H, double *__restrict__ Qout,
-                          int *__restrict__ flag, int step, Params P)
+__global__ __launch_bounds__(256) void k_macro2d(const double *__restrict__ Qin, const double *__restrict__ H,
+                                                 double *__restrict__ Qout, int *__restrict__ flag, int step,
+                                                 Params P)
 {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= P.nx * P.ny) return;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = t >> 2, role = t & 3;
+    if (c >= P.nx * P.ny) return;     // whole groups of four
     const int i = c % P.nx, j = c / P.nx;
     const int n = DIR == 0 ? P.nx : P.ny, pos = DIR == 0 ? i : j;
     const int stride = DIR == 0 ? 1 : P.nx;
     const int slo = DIR == 0 ? 0 : 2, shi = DIR == 0 ? 1 : 3;
     const double h = DIR == 0 ? P.dx : P.dy;
     const int hoff = DIR == 0 ? 0 : 1;
-    double qc[6], ql[6], qr[6];
-    load_q(Qin, c, qc);
-    if (DIR == 0) collide(P, qc);
     const int cl = pos > 0 ? c - stride : c + (n - 1) * stride;      // periodic wrap when at the low edge
     const int cr = pos < n - 1 ? c + stride : c - (n - 1) * stride;
-    load_q(Qin, cl, ql);
-    load_q(Qin, cr, qr);
-    if (DIR == 0) {
-        collide(P, ql);
-        collide(P, qr);
+    const bool low_face = role < 2;
+    const int side = low_face ? slo : shi;
+    const bool at_bc = low_face ? pos == 0 : pos == n - 1;
+    const bool whole = at_bc && P.bc[side].kind != BC_PERIODIC;      // a boundary face, not a wrap
+    double r[6];
+    if (whole) {
+        if (role == 0 || role == 3) {
+            double qc[6], qw[6];
+            load_q(Qin, c, qc);
+            load_q(Qin, role == 0 ? cl : cr, qw);
+            if (DIR == 0) collide(P, qc);
+            boundary_face(P, side, qc, qw, DIR, r);
+        } else {
+#pragma unroll
+            for (int m = 0; m < 6; ++m) r[m] = 0.0;
+        }
+    } else {
+        double q[6];
+        load_q(Qin, role == 0 ? cl : role == 3 ? cr : c, q);
+        if (DIR == 0) collide(P, q);
+        kfvs_half(q, DIR, (role == 0 || role == 2) ? 1.0 : -1.0, r);
     }
-    double FL[6], FR[6], HL[3], HR[3];
+    // faces: F_low = r(lane 0) + r(lane 1), F_high = r(lane 2) + r(lane 3)
+    const int g0 = threadIdx.x & ~3;
+    double FL[6], FR[6];
+#pragma unroll
+    for (int m = 0; m < 6; ++m) {
+        const double a0 = __shfl(r[m], g0, 64), a1 = __shfl(r[m], g0 + 1, 64);
+        const double a2 = __shfl(r[m], g0 + 2, 64), a3 = __shfl(r[m], g0 + 3, 64);
+        FL[m] = a0 + a1;
+        FR[m] = a2 + a3;
+    }
+    if (role != 1) return;
+    double qc[6];
+    load_q(Qin, c, qc);
+    if (DIR == 0) collide(P, qc);
+    double HL[3], HR[3];
     if (pos > 0) {
-        interior_face(ql, qc, DIR, FL);
         for (int a = 0; a < 3; ++a) HL[a] = 0.5 * (H[4 * (size_t)c + hoff + a] + H[4 * (size_t)cl + hoff + a]);
     } else {
-        boundary_face(P, slo, qc, ql, DIR, FL);
         const int kind = P.bc[slo].kind;
         for (int a = 0; a < 3; ++a) {
             const double hc = H[4 * (size_t)c + hoff + a];
@@ -442,10 +488,8 @@ __global__ void k_macro2d(const double *__restrict__ Qin, const double *__restri
         }
     }
     if (pos < n - 1) {
-        interior_face(qc, qr, DIR, FR);
         for (int a = 0; a < 3; ++a) HR[a] = 0.5 * (H[4 * (size_t)cr + hoff + a] + H[4 * (size_t)c + hoff + a]);
     } else {
-        boundary_face(P, shi, qc, qr, DIR, FR);
         const int kind = P.bc[shi].kind;
         for (int a = 0; a < 3; ++a) {
             const double hc = H[4 * (size_t)c + hoff + a];
@@ -512,12 +556,21 @@ __device__ __forceinline__ void ring_cell(const Params &P, int r, int &i, int &j
     j = r + 1;
 }
 
+// One workgroup per wall-adjacent cell.  The cell's Maxwellian and the four
+// neighbour (ghost) Maxwellians are separable: 1D factors of each go to LDS
+// tables (5 (nv1 + nv2) exponentials per cell instead of 5 nv).  The first
+// pass keeps the upwind term and the ES term of every node in LDS for the second.
+constexpr int WALL_MAXV = 64;      // nv1, nv2 of the fused pass
+constexpr int WALL_MAXNV = 2304;   // nv of the fused pass
+
 template <typename TS>
 __global__ __launch_bounds__(256) void k_wall_relax2d(TS *__restrict__ Gn, double *__restrict__ H,
                                                       const double *__restrict__ rec,
                                                       const double *__restrict__ wrec, Params P)
 {
     __shared__ double lds[4 * 8];
+    __shared__ double e1[5][WALL_MAXV], e2[5][WALL_MAXV];   // 0: the cell; 1..4: x-, x+, y-, y+ neighbours
+    __shared__ double s_mup[WALL_MAXNV], s_es[WALL_MAXNV];
     int i, j;
     ring_cell(P, blockIdx.x, i, j);
     const size_t c = (size_t)j * P.nx + i;
@@ -526,49 +579,64 @@ __global__ __launch_bounds__(256) void k_wall_relax2d(TS *__restrict__ Gn, doubl
     const double u1 = R[R_U1], u2 = R[R_U2], rsT = R[R_RST], i2T = R[R_I2T], mpre = R[R_MPRE];
     const double dA = R[R_DA], dB = R[R_QB], dC = R[R_DC], lg = R[R_LG], ieps = R[R_IEPS], itau = R[R_ITAU];
     const bool es_on = P.wall_es_term != 0, discrete = P.proj_mode == PROJ_DISCRETE;
-    double nb[16];
-    for (int t = 0; t < 16; ++t) nb[t] = wrec[c * WREC + t];
-    TS *g = Gn + c * (size_t)P.nv;
-    auto point = [&](int p, double &M, double &es, double &mup, double &w1, double &w2) {
-        const int k = p % P.nv1, l = p / P.nv1;
-        const double v1 = P.v1_lo + (k + 0.5) * P.dv1, v2 = P.v2_lo + (l + 0.5) * P.dv2;
-        w1 = v1 - u1;
-        w2 = v2 - u2;
-        M = mpre * exp(-(w1 * w1 + w2 * w2) * i2T);
-        es = es_on ? M * expm1(lg - (dA * w1 * w1 + 2.0 * dB * w1 * w2 + dC * w2 * w2)) * ieps : 0.0;
-        double Mn[4];
-        for (int d = 0; d < 4; ++d) {
-            const double a1 = v1 - nb[4 * d + 1], a2 = v2 - nb[4 * d + 2];
-            Mn[d] = nb[4 * d] * exp(-(a1 * a1 + a2 * a2) * nb[4 * d + 3]);
-        }
-        mup = (fmin(v1, 0.0) * (Mn[1] - M) + fmax(v1, 0.0) * (M - Mn[0])) / P.dx +
-              (fmin(v2, 0.0) * (Mn[3] - M) + fmax(v2, 0.0) * (M - Mn[2])) / P.dy;
-    };
-    double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int p = threadIdx.x; p < P.nv; p += 256) {
-        double M, es, mup, w1, w2;
-        point(p, M, es, mup, w1, w2);
-        const double f[4] = {1.0, w1 * rsT, w2 * rsT, (w1 * w1 + w2 * w2) * i2T - 1.0};
-        for (int a = 0; a < 4; ++a) {
-            s[a] += f[a] * mup;
-            s[4 + a] += f[a] * es;
+    const double *nb = wrec + c * WREC;     // per neighbour: (rho / (2 pi T), u1, u2, 1 / (2T))
+    const int n12 = P.nv1 + P.nv2;
+    for (int t = threadIdx.x; t < 5 * n12; t += 256) {
+        const int d = t / n12, q = t - d * n12;
+        const double cu1 = d ? nb[4 * (d - 1) + 1] : u1, cu2 = d ? nb[4 * (d - 1) + 2] : u2;
+        const double ci2T = d ? nb[4 * (d - 1) + 3] : i2T;
+        if (q < P.nv1) {
+            const double a = P.v1_lo + (q + 0.5) * P.dv1 - cu1;
+            e1[d][q] = exp(-a * a * ci2T);
+        } else {
+            const double a = P.v2_lo + (q - P.nv1 + 0.5) * P.dv2 - cu2;
+            e2[d][q - P.nv1] = exp(-a * a * ci2T);
         }
     }
-    block_sum<8, 4>(s, lds);
+    __syncthreads();
+    const double pre0 = nb[0], pre1 = nb[4], pre2 = nb[8], pre3 = nb[12];
+    double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll 1
+    for (int p = threadIdx.x; p < P.nv; p += 256) {
+        const int k = p % P.nv1, l = p / P.nv1;
+        const double v1 = P.v1_lo + (k + 0.5) * P.dv1, v2 = P.v2_lo + (l + 0.5) * P.dv2;
+        const double w1 = v1 - u1, w2 = v2 - u2;
+        const double M = mpre * e1[0][k] * e2[0][l];
+        const double es = es_on ? M * expm1(lg - (dA * w1 * w1 + 2.0 * dB * w1 * w2 + dC * w2 * w2)) * ieps : 0.0;
+        const double M0 = pre0 * e1[1][k] * e2[1][l], M1 = pre1 * e1[2][k] * e2[2][l];
+        const double M2 = pre2 * e1[3][k] * e2[3][l], M3 = pre3 * e1[4][k] * e2[4][l];
+        const double mup = (fmin(v1, 0.0) * (M1 - M) + fmax(v1, 0.0) * (M - M0)) / P.dx +
+                           (fmin(v2, 0.0) * (M3 - M) + fmax(v2, 0.0) * (M - M2)) / P.dy;
+        s_mup[p] = mup;
+        s_es[p] = es;
+        const double f1 = w1 * rsT, f2 = w2 * rsT, f3 = (w1 * w1 + w2 * w2) * i2T - 1.0;
+        s[0] += mup;
+        s[1] += f1 * mup;
+        s[2] += f2 * mup;
+        s[3] += f3 * mup;
+        s[4] += es;
+        s[5] += f1 * es;
+        s[6] += f2 * es;
+        s[7] += f3 * es;
+    }
+    block_sum<8, 4>(s, lds);     // its barriers also publish s_mup, s_es
     double AM[4], AE[4];
     proj_coef(R, s, AM);
     proj_coef(R, s + 4, AE);
     if (!discrete)
         for (int a = 0; a < 4; ++a) AE[a] = 0.0;
     const double ra = R[R_A], rb = R[R_B];
+    TS *g = Gn + c * (size_t)P.nv;
     double h[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 1
     for (int p = threadIdx.x; p < P.nv; p += 256) {
-        double M, es, mup, w1, w2;
-        point(p, M, es, mup, w1, w2);
+        const int k = p % P.nv1, l = p / P.nv1;
+        const double w1 = P.v1_lo + (k + 0.5) * P.dv1 - u1, w2 = P.v2_lo + (l + 0.5) * P.dv2 - u2;
+        const double M = mpre * e1[0][k] * e2[0][l];
         const double f1 = w1 * rsT, f2 = w2 * rsT, f3 = (w1 * w1 + w2 * w2) * i2T - 1.0;
         const double PM = (AM[0] + AM[1] * f1 + AM[2] * f2 + AM[3] * f3) * M;
         const double PE = (AE[0] + AE[1] * f1 + AE[2] * f2 + AE[3] * f3) * M;
-        const double gh = -itau * (mup - PM) + (es - PE);
+        const double gh = -itau * (s_mup[p] - PM) + (s_es[p] - PE);
         const TS gn = (TS)(ra * (double)g[p] + rb * gh);
         g[p] = gn;
         const double gv = (double)gn;
@@ -590,7 +658,8 @@ __global__ __launch_bounds__(256) void k_wall_relax2d(TS *__restrict__ Gn, doubl
 void launch_prep2d(const double *Q, double *rec, double *wrec, int *flag, int step, const Params &P, hipStream_t st)
 {
     const int n = P.nx * P.ny;
-    hipLaunchKernelGGL(k_prep2d, dim3((n + 127) / 128), dim3(128), 0, st, Q, rec, wrec, flag, step, P);
+    hipLaunchKernelGGL(k_prep2d, dim3((n + PREP_BLOCK - 1) / PREP_BLOCK), dim3(PREP_BLOCK), 0, st, Q, rec, wrec, flag,
+                       step, P);
 }
 
 void launch_micro_ref2d(const double *G, double *Gs, double *Gn, double *H, const double *rec, const double *wrec,
@@ -604,8 +673,9 @@ void launch_micro_ref2d(const double *G, double *Gs, double *Gn, double *H, cons
 void launch_macro2d(double *Q, double *Qs, const double *H, int *flag, int step, const Params &P, hipStream_t st)
 {
     const int n = P.nx * P.ny;
-    hipLaunchKernelGGL(k_macro2d<0>, dim3((n + 127) / 128), dim3(128), 0, st, Q, H, Qs, flag, step, P);
-    hipLaunchKernelGGL(k_macro2d<1>, dim3((n + 127) / 128), dim3(128), 0, st, Qs, H, Q, flag, step, P);
+    // four lanes per cell
+    hipLaunchKernelGGL(k_macro2d<0>, dim3((4 * n + 255) / 256), dim3(256), 0, st, Q, H, Qs, flag, step, P);
+    hipLaunchKernelGGL(k_macro2d<1>, dim3((4 * n + 255) / 256), dim3(256), 0, st, Qs, H, Q, flag, step, P);
 }
 
 void launch_wall_relax2d(void *Gn, int g_bytes, double *H, const double *rec, const double *wrec, const Params &P,
@@ -615,6 +685,7 @@ void launch_wall_relax2d(void *Gn, int g_bytes, double *H, const double *rec, co
     for (int s = 0; s < 4; ++s) any = any || is_open(P.bc[s].kind);
     if (!any) return;
     const int n = 2 * P.nx + 2 * (P.ny - 2);
+    if (P.nv1 > WALL_MAXV || P.nv2 > WALL_MAXV || P.nv > WALL_MAXNV) return;   // not a fused-pass shape
     if (g_bytes == 8)
         hipLaunchKernelGGL(k_wall_relax2d<double>, dim3(n), dim3(256), 0, st, (double *)Gn, H, rec, wrec, P);
     else
