@@ -14,18 +14,26 @@ constexpr int NO = 5;       // outputs: (q1, q2, S11, S12, S22) / eps
 constexpr int NPARAM = NH * NF + NH + NH * NH + NH + NO * NH + NO;   // 5893
 constexpr int NNORM = 2 * NF + 2 * NO;   // in_mean, in_std, out_mean, out_std
 
-// bf16 weights in matrix-core order (W1 [64][32], W2 [64][64], W3 [32][64],
-// zero padded), FP32 biases and normalisation
+// bf16 weights (W1 [64][32], W2 [64][64], W3 [32][64], zero padded, row-major:
+// the training kernel), the same weights packed per lane in the operand order
+// of the matrix instruction (Wp, 16 blocks of 64 lanes x 8: the inference
+// path), FP32 biases and normalisation
+constexpr int NWP = 16 * 64 * 8;
 struct MlpDev {
-    const __bf16 *W1, *W2, *W3;
+    const __bf16 *W1, *W2, *W3, *Wp;
     const float *b1, *b2, *b3, *norm;
 };
 struct MlpDevMut {
-    __bf16 *W1, *W2, *W3;
+    __bf16 *W1, *W2, *W3, *Wp;
     float *b1, *b2, *b3, *norm;
 };
 
 void launch_features2d(const double *Q, const Params &P, float *feat, float *kn, uint8_t *edge, hipStream_t st);
+// the closure part of a step in one kernel: features, indicator, classes, the
+// closure values out = (q, S) / eps (NSF, network, or NSF plus scale x network
+// with residual) and H of the closure cells; empties the rebuild list
+void launch_cells2d(const double *Q, const Params &P, const MlpDev *w, int residual, float kn_max, uint8_t *cls,
+                    float *out, double *H, unsigned long long *nclosure, int *nrebuild, hipStream_t st);
 // Y = MLP(X), or Y += scale MLP(X) with accumulate
 void launch_mlp_forward(const float *X, int n, const MlpDev &w, float *Y, bool accumulate, float scale,
                         hipStream_t st);

@@ -171,30 +171,103 @@ __device__ void forward_tile(const SmemW &W, SmemFwd &F, SmemBwd *Bw, const floa
 
 // ------------------------------------------------------------- inference
 
+// The network's weights in VGPRs, in the per-lane operand order (Wp)
+struct MlpRegs {
+    bf16x8 w1[4], w2[8], w3[4];
+};
+
+__device__ __forceinline__ void mlp_regs(const __bf16 *__restrict__ Wp, int lane, MlpRegs &R)
+{
+    const bf16x8 *p = (const bf16x8 *)Wp;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) R.w1[b] = p[b * 64 + lane];
+#pragma unroll
+    for (int b = 0; b < 8; ++b) R.w2[b] = p[(4 + b) * 64 + lane];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) R.w3[b] = p[(12 + b) * 64 + lane];
+}
+
+// Forward pass of the 32 samples of a wavefront with no LDS traffic: lane
+// (r, g) holds sample r's normalised inputs x; every layer's accumulator slots
+// are the next layer's B operand (the packed weights carry the matching
+// column order).  Returns the normalised outputs o = 4 g + v (v < 4, o < 5).
+__device__ __forceinline__ void mlp_eval(const MlpRegs &R, const float *b1, const float *b2, const float *b3,
+                                         const float (&x)[NF], int lane, float (&yh)[4])
+{
+    const int g = lane >> 5;
+    bf16x8 B1[2];
+#pragma unroll
+    for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int f0 = 16 * kb + q, f1 = 16 * kb + 8 + q;
+            const float v0 = f0 < NF ? x[f0 < NF ? f0 : 0] : 0.0f, v1 = f1 < NF ? x[f1 < NF ? f1 : 0] : 0.0f;
+            B1[kb][q] = (__bf16)(g ? v1 : v0);
+        }
+    bf16x8 B2[4];
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt) {
+        f32x16 acc = zero16();
+#pragma unroll
+        for (int kb = 0; kb < 2; ++kb) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(R.w1[2 * mt + kb], B1[kb], acc, 0, 0, 0);
+#pragma unroll
+        for (int v = 0; v < 16; ++v)
+            B2[2 * mt + (v >> 3)][v & 7] = (__bf16)gelu(acc[v] + b1[32 * mt + acc_row(v, lane)]);
+    }
+    bf16x8 B3[4];
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt) {
+        f32x16 acc = zero16();
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(R.w2[4 * mt + kb], B2[kb], acc, 0, 0, 0);
+#pragma unroll
+        for (int v = 0; v < 16; ++v)
+            B3[2 * mt + (v >> 3)][v & 7] = (__bf16)gelu(acc[v] + b2[32 * mt + acc_row(v, lane)]);
+    }
+    f32x16 acc = zero16();
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(R.w3[kb], B3[kb], acc, 0, 0, 0);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int o = 4 * g + v;
+        yh[v] = o < NO ? acc[v] + b3[o < NO ? o : 0] : 0.0f;
+    }
+}
+
 // Y = MLP(X) (accumulate = 0) or Y += scale MLP(X) (accumulate = 1)
 __global__ __launch_bounds__(256) void k_mlp_forward(const float *__restrict__ X, int n, MlpDev w,
                                                      float *__restrict__ Y, int accumulate, float scale)
 {
-    __shared__ SmemW W;
-    __shared__ SmemFwd F[4];
-    load_weights(W, w);
+    __shared__ float sb[NH + NH + 16 + NNORM];
+    for (int t = threadIdx.x; t < NH; t += blockDim.x) {
+        sb[t] = w.b1[t];
+        sb[NH + t] = w.b2[t];
+    }
+    for (int t = threadIdx.x; t < 16; t += blockDim.x) sb[2 * NH + t] = t < NO ? w.b3[t] : 0.0f;
+    for (int t = threadIdx.x; t < NNORM; t += blockDim.x) sb[2 * NH + 16 + t] = w.norm[t];
+    __syncthreads();
+    const float *b1 = sb, *b2 = sb + NH, *b3 = sb + 2 * NH, *nrm = sb + 2 * NH + 16;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    MlpRegs R;
+    mlp_regs(w.Wp, lane, R);
     const int ntile = (n + 31) / 32;
     for (int tile = blockIdx.x * 4 + wv; tile < ntile; tile += gridDim.x * 4) {
-        float yh[4];
-        forward_tile<false>(W, F[wv], nullptr, X, nullptr, tile * 32, n, lane, yh);
         const int s = tile * 32 + (lane & 31);
+        float x[NF];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) x[f] = s < n ? (X[(size_t)s * NF + f] - nrm[f]) / nrm[NF + f] : 0.0f;
+        float yh[4];
+        mlp_eval(R, b1, b2, b3, x, lane, yh);
         if (s < n) {
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int o = 4 * (lane >> 5) + v;
                 if (o < NO) {
-                    const float y = yh[v] * W.nrm[2 * NF + NO + o] + W.nrm[2 * NF + o];
+                    const float y = yh[v] * nrm[2 * NF + NO + o] + nrm[2 * NF + o];
                     Y[(size_t)s * NO + o] = accumulate ? Y[(size_t)s * NO + o] + scale * y : y;
                 }
             }
         }
-        wave_sync();
     }
 }
 
@@ -369,13 +442,37 @@ __global__ void k_mlp_adam(float *__restrict__ master, float *__restrict__ m1, f
     master[p] -= lr * (a / c1) / (sqrtf(b / c2) + epsa);
 }
 
+// hidden unit carried by K index 8 g + t of K-block kb when the next layer's B
+// operand is taken straight from this layer's accumulator slots: the slot
+// v = 8 (kb % 2) + t of tile kb / 2 in lane group g holds row 8 (v / 4) + 4 g + v % 4
+__device__ __forceinline__ int hidden_of(int kb, int g, int t)
+{
+    return 32 * (kb >> 1) + 16 * (kb & 1) + 8 * (t >> 2) + 4 * g + (t & 3);
+}
+
 __global__ void k_mlp_pack(const float *__restrict__ master, __bf16 *__restrict__ W1, __bf16 *__restrict__ W2,
-                           __bf16 *__restrict__ W3, float *__restrict__ b1, float *__restrict__ b2,
-                           float *__restrict__ b3)
+                           __bf16 *__restrict__ W3, __bf16 *__restrict__ Wp, float *__restrict__ b1,
+                           float *__restrict__ b2, float *__restrict__ b3)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     const float *w1 = master, *pb1 = w1 + NH * NF, *w2 = pb1 + NH, *pb2 = w2 + NH * NH, *w3 = pb2 + NH,
                 *pb3 = w3 + NO * NH;
+    if (t < NWP) {
+        // per-lane operand order: block b, lane (r, g), slot q
+        const int b = t >> 9, lane = (t >> 3) & 63, q = t & 7, r = lane & 31, g = lane >> 5;
+        float v;
+        if (b < 4) {             // layer 1: tile mt, K-block kb (inputs in natural order)
+            const int mt = b >> 1, kb = b & 1, f = 16 * kb + 8 * g + q;
+            v = f < NF ? w1[(32 * mt + r) * NF + f] : 0.0f;
+        } else if (b < 12) {     // layer 2: tile mt, K-block kb (inputs in accumulator order)
+            const int mt = (b - 4) >> 2, kb = (b - 4) & 3;
+            v = w2[(32 * mt + r) * NH + hidden_of(kb, g, q)];
+        } else {                 // layer 3: K-block kb
+            const int kb = b - 12;
+            v = r < NO ? w3[r * NH + hidden_of(kb, g, q)] : 0.0f;
+        }
+        Wp[t] = (__bf16)v;
+    }
     if (t < NH * 32) {
         const int h = t / 32, f = t % 32;
         W1[t] = (__bf16)(f < NF ? w1[h * NF + f] : 0.0f);
@@ -437,12 +534,11 @@ __device__ __forceinline__ void prim(const double *q, double *w)
     w[4] = P11; w[5] = P12; w[6] = P22;
 }
 
-// features (FP32), local Knudsen indicator and the always-micro mask per cell
-__global__ void k_features2d(const double *__restrict__ Q, Params P, float *__restrict__ feat,
-                             float *__restrict__ kn, uint8_t *__restrict__ edge)
+// features of cell c rounded to FP32 (as stored for training), local Knudsen
+// indicator (FP64 from the FP64 features) and the next-to-a-non-periodic-side flag
+__device__ __forceinline__ void cell_features(const double *__restrict__ Q, const Params &P, int c, float (&fo)[NF],
+                                              double &kn, bool &edge)
 {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= P.nx * P.ny) return;
     const int i = c % P.nx, j = c / P.nx;
     const bool px = P.bc[0].kind == BC_PERIODIC, py = P.bc[2].kind == BC_PERIODIC;
     int im = i - 1, ip = i + 1, jm = j - 1, jp = j + 1;
@@ -471,14 +567,30 @@ __global__ void k_features2d(const double *__restrict__ Q, Params P, float *__re
                                 : 0.0;
     }
 #pragma unroll
-    for (int a = 0; a < NF; ++a) feat[(size_t)c * NF + a] = (float)f[a];
+    for (int a = 0; a < NF; ++a) fo[a] = (float)f[a];
     const double rho = w0[0], T = w0[3];
     const double gr = sqrt(f[7] * f[7] + f[14] * f[14]) / rho;
     const double gT = sqrt(f[10] * f[10] + f[17] * f[17]) / T;
     const double gu = sqrt(f[8] * f[8] + f[15] * f[15] + f[9] * f[9] + f[16] * f[16]) / sqrt(T);
     const double m = fmax(gr, fmax(gT, gu));
-    kn[c] = (float)(P.eps * sqrt(T) / tau_of(P, rho, rho * T, T) * m);
-    edge[c] = (!px && (i == 0 || i == P.nx - 1)) || (!py && (j == 0 || j == P.ny - 1));
+    kn = P.eps * sqrt(T) / tau_of(P, rho, rho * T, T) * m;
+    edge = (!px && (i == 0 || i == P.nx - 1)) || (!py && (j == 0 || j == P.ny - 1));
+}
+
+// features (FP32), local Knudsen indicator and the always-micro mask per cell
+__global__ void k_features2d(const double *__restrict__ Q, Params P, float *__restrict__ feat,
+                             float *__restrict__ kn, uint8_t *__restrict__ edge)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= P.nx * P.ny) return;
+    float f[NF];
+    double k;
+    bool e;
+    cell_features(Q, P, c, f, k, e);
+#pragma unroll
+    for (int a = 0; a < NF; ++a) feat[(size_t)c * NF + a] = f[a];
+    kn[c] = (float)k;
+    edge[c] = e;
 }
 
 // Navier-Stokes-Fourier values of (q, S) / eps from the features of a cell:
@@ -531,6 +643,100 @@ __global__ void k_classify2d(const float *__restrict__ kn, const uint8_t *__rest
     __shared__ int wcount[4];
     const unsigned long long b = __ballot(closure);
     if ((threadIdx.x & 63) == 0) wcount[threadIdx.x >> 6] = (int)__popcll(b);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int tot = wcount[0] + wcount[1] + wcount[2] + wcount[3];
+        if (tot) atomicAdd(nclosure, (unsigned long long)tot);
+    }
+}
+
+// The closure part of a step for 32 cells per wavefront: features and
+// indicator (both lane halves of a cell compute them), classes, the closure
+// values out = (q, S) / eps (NSF; the network; or NSF plus scale x network)
+// and H of the closure cells.  Lane half g holds outputs o = 4 g + v.
+template <bool NET>
+__global__ __launch_bounds__(256) void k_cells2d(const double *__restrict__ Q, Params P, MlpDev w, int residual,
+                                                 float kn_max, uint8_t *__restrict__ cls, float *__restrict__ out,
+                                                 double *__restrict__ H, unsigned long long *__restrict__ nclosure,
+                                                 int *__restrict__ nrebuild)
+{
+    __shared__ float sb[NH + NH + 16 + NNORM];
+    __shared__ int wcount[4];
+    if (blockIdx.x == 0 && threadIdx.x == 0) *nrebuild = 0;     // the list of k_need2d starts empty
+    const int n = P.nx * P.ny;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, g = lane >> 5;
+    if constexpr (NET) {
+        for (int t = threadIdx.x; t < NH; t += blockDim.x) {
+            sb[t] = w.b1[t];
+            sb[NH + t] = w.b2[t];
+        }
+        for (int t = threadIdx.x; t < 16; t += blockDim.x) sb[2 * NH + t] = t < NO ? w.b3[t] : 0.0f;
+        for (int t = threadIdx.x; t < NNORM; t += blockDim.x) sb[2 * NH + 16 + t] = w.norm[t];
+        __syncthreads();
+    }
+    const float *b1 = sb, *b2 = sb + NH, *b3 = sb + 2 * NH, *nrm = sb + 2 * NH + 16;
+    const int c = (blockIdx.x * 4 + wv) * 32 + (lane & 31);
+    const bool valid = c < n;
+    float f[NF];
+    double kn = 0.0;
+    bool edge = true;
+    if (valid) cell_features(Q, P, c, f, kn, edge);
+    else
+        for (int a = 0; a < NF; ++a) f[a] = 1.0f;
+    const bool micro = edge || !((float)kn <= kn_max);     // the decision in FP32, as for stored indicators
+    // closure values of this lane's outputs o = 4 g + v
+    double o4[4] = {0.0, 0.0, 0.0, 0.0};
+    if (!NET || residual) {
+        double b[NO];
+        nsf5(f, P, b);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int o = 4 * g + v;
+            o4[v] = o < NO ? b[o < NO ? o : 0] : 0.0;
+        }
+    }
+    if constexpr (NET) {
+        MlpRegs R;
+        mlp_regs(w.Wp, lane, R);
+        float x[NF];
+#pragma unroll
+        for (int a = 0; a < NF; ++a) x[a] = (f[a] - nrm[a]) / nrm[NF + a];
+        float yh[4];
+        mlp_eval(R, b1, b2, b3, x, lane, yh);
+        const float scale = residual == 2 ? (float)P.eps : 1.0f;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int o = 4 * g + v;
+            if (o < NO) {
+                const float y = yh[v] * nrm[2 * NF + NO + o] + nrm[2 * NF + o];
+                // the same FP32 arithmetic as the separate forward kernel
+                o4[v] = residual ? (double)((float)o4[v] + scale * y) : (double)y;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) o4[v] = (double)(float)o4[v];
+    }
+    if (valid) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int o = 4 * g + v;
+            if (o < NO) out[(size_t)c * NO + o] = (float)o4[v];
+        }
+        if (g == 0) {
+            cls[c] = micro ? 1 : 0;
+            if (!micro) {
+                const double q1 = P.eps * (double)(float)o4[0], q2 = P.eps * (double)(float)o4[1];
+                H[4 * (size_t)c + 0] = 1.5 * q1;
+                H[4 * (size_t)c + 1] = 0.5 * q2;
+                H[4 * (size_t)c + 2] = 0.5 * q1;
+                H[4 * (size_t)c + 3] = 1.5 * q2;
+            }
+        }
+    }
+    // closure cells of the workgroup (lane half 0 of each wavefront), one atomic
+    const unsigned long long bal = __ballot(valid && g == 0 && !micro);
+    if (lane == 0) wcount[wv] = (int)__popcll(bal);
     __syncthreads();
     if (threadIdx.x == 0) {
         const int tot = wcount[0] + wcount[1] + wcount[2] + wcount[3];
@@ -692,6 +898,19 @@ void launch_features2d(const double *Q, const Params &P, float *feat, float *kn,
     hipLaunchKernelGGL(k_features2d, dim3((n + 255) / 256), dim3(256), 0, st, Q, P, feat, kn, edge);
 }
 
+void launch_cells2d(const double *Q, const Params &P, const MlpDev *w, int residual, float kn_max, uint8_t *cls,
+                    float *out, double *H, unsigned long long *nclosure, int *nrebuild, hipStream_t st)
+{
+    const int n = P.nx * P.ny;
+    const dim3 grid((n + 127) / 128), block(256);     // 4 wavefronts x 32 cells
+    if (w)
+        hipLaunchKernelGGL(k_cells2d<true>, grid, block, 0, st, Q, P, *w, residual, kn_max, cls, out, H, nclosure,
+                           nrebuild);
+    else
+        hipLaunchKernelGGL(k_cells2d<false>, grid, block, 0, st, Q, P, MlpDev{}, 0, kn_max, cls, out, H, nclosure,
+                           nrebuild);
+}
+
 void launch_mlp_forward(const float *X, int n, const MlpDev &w, float *Y, bool accumulate, float scale,
                         hipStream_t st)
 {
@@ -724,7 +943,7 @@ void launch_mlp_adam(float *master, float *m1, float *m2, const float *grad, flo
 
 void launch_mlp_pack(const float *master, const MlpDevMut &w, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_mlp_pack, dim3((NH * NH + 255) / 256), dim3(256), 0, st, master, w.W1, w.W2, w.W3, w.b1,
+    hipLaunchKernelGGL(k_mlp_pack, dim3((NWP + 255) / 256), dim3(256), 0, st, master, w.W1, w.W2, w.W3, w.Wp, w.b1,
                        w.b2, w.b3);
 }
 

@@ -277,14 +277,9 @@ int enqueue_steps(mm_ctx *c, int nsteps)
             if (c->closure) {
                 {
                     Timer t(c, 4);
-                    const int n = c->ncell;
-                    mm::closure::launch_features2d(c->Q, P, c->cl_feat, c->cl_kn, c->cl_edge, c->st);
-                    if (!c->net || c->residual) mm::closure::launch_nsf2d(c->cl_feat, n, P, c->cl_out, c->st);
-                    if (c->net)
-                        mm::closure::launch_mlp_forward(c->cl_feat, n, c->net->view(), c->cl_out, c->residual != 0,
-                                                        c->residual == 2 ? (float)P.eps : 1.0f, c->st);
-                    mm::closure::launch_classify2d(c->cl_kn, c->cl_edge, c->cl_out, n, c->kn_max, P.eps, c->cl_cls,
-                                                   c->H, c->cl_ncl, c->cl_nlist, c->st);
+                    const mm::closure::MlpDev wv = c->net ? c->net->view() : mm::closure::MlpDev{};
+                    mm::closure::launch_cells2d(c->Q, P, c->net ? &wv : nullptr, c->residual, c->kn_max, c->cl_cls,
+                                                c->cl_out, c->H, c->cl_ncl, c->cl_nlist, c->st);
                     mm::closure::launch_rebuild2d(c->G[c->cur], c->gbytes, c->rec, c->cl_out, c->cl_cls,
                                                   c->cl_valid[c->cl_vcur], c->cl_valid[1 - c->cl_vcur], c->cl_list,
                                                   c->cl_nlist, P, c->st);

@@ -43,7 +43,7 @@ void release(mm_mlp *n)
 {
     if (!n) return;
     if (n->st) hipStreamSynchronize(n->st);
-    void *bufs[] = {n->master, n->m1, n->m2, n->grad, n->W1, n->W2, n->W3, n->b1, n->b2, n->b3, n->norm,
+    void *bufs[] = {n->master, n->m1, n->m2, n->grad, n->W1, n->W2, n->W3, n->Wp, n->b1, n->b2, n->b3, n->norm,
                     n->part, n->loss_part, n->loss_acc, n->perm};
     for (void *b : bufs)
         if (b) hipFree(b);
@@ -89,8 +89,8 @@ int waves_for(int count)
 
 } // namespace
 
-mm::closure::MlpDev mm_mlp::view() const { return {W1, W2, W3, b1, b2, b3, norm}; }
-mm::closure::MlpDevMut mm_mlp::mut() const { return {W1, W2, W3, b1, b2, b3, norm}; }
+mm::closure::MlpDev mm_mlp::view() const { return {W1, W2, W3, Wp, b1, b2, b3, norm}; }
+mm::closure::MlpDevMut mm_mlp::mut() const { return {W1, W2, W3, Wp, b1, b2, b3, norm}; }
 
 extern "C" {
 
@@ -118,6 +118,7 @@ int mm_mlp_create(int device, void *stream, unsigned long long seed, mm_mlp **ou
               hipMalloc(&n->W1, sizeof(__bf16) * NH * 32) == hipSuccess &&
               hipMalloc(&n->W2, sizeof(__bf16) * NH * NH) == hipSuccess &&
               hipMalloc(&n->W3, sizeof(__bf16) * 32 * NH) == hipSuccess &&
+              hipMalloc(&n->Wp, sizeof(__bf16) * NWP) == hipSuccess &&
               hipMalloc(&n->b1, sizeof(float) * NH) == hipSuccess &&
               hipMalloc(&n->b2, sizeof(float) * NH) == hipSuccess &&
               hipMalloc(&n->b3, sizeof(float) * NO) == hipSuccess &&

@@ -10,7 +10,7 @@ struct mm_mlp {
     hipStream_t st = nullptr;
     bool own_stream = false;
     float *master = nullptr, *m1 = nullptr, *m2 = nullptr, *grad = nullptr;   // FP32, NPARAM each
-    __bf16 *W1 = nullptr, *W2 = nullptr, *W3 = nullptr;                      // matrix-core copies
+    __bf16 *W1 = nullptr, *W2 = nullptr, *W3 = nullptr, *Wp = nullptr;      // matrix-core copies
     float *b1 = nullptr, *b2 = nullptr, *b3 = nullptr, *norm = nullptr;
     float *part = nullptr, *loss_part = nullptr;   // per-wavefront partial gradients
     int nwaves_cap = 0;
