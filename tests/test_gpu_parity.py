@@ -61,7 +61,15 @@ LANE_K = {
                                         V1=9.0, V2=7.0),
     "lk_32x16_paper_proj": lambda: _velocity(
         lambda: W.smooth2d(seed=26, nx=10, ny=18, eps=0.1, proj_mode="paper"), 32, 16),
+    # an asymmetric v2 box: the y-upwind direction is decided per node at run time
+    "lk_32x32_asym_v2": lambda: _asym_v2(),
 }
+
+
+def _asym_v2():
+    p, Q, G = W.cavity2d(seed=27, nx=9, ny=21, nv=32, eps=0.05, amp=0.2)
+    p["v2"] = (-6.0, 8.0)
+    return p, Q, W.zero_g(p)
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
