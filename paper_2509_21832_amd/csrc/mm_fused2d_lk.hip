@@ -40,8 +40,10 @@ struct PassLK {
     const Params *P;
     double *tab;            // this wavefront's Maxwellian tables: 3 slots x 2 x MAXV
     int lane, i, k, l0, L;
+    int row_bytes;          // bytes of one row of cells of g
+    int off_c, off_u;       // byte offsets in its row of this lane's value of cell i and of its upwind cell
     double v1d, v2bd, hd;   // v1 of this lane; v2(m) = v2b + m h
-    TC v1, ax, bx, v2b, h, idy;
+    TC v1, cx, v2b, h, idy;
 
     __device__ __forceinline__ TC v2(int m) const { return v2b + (TC)m * h; }
     __device__ __forceinline__ double v2d(int m) const { return v2bd + (double)m * hd; }
@@ -70,72 +72,45 @@ struct PassLK {
         return E1 * (TC)t[MAXV + l0 + L * m];
     }
 
-    __device__ __forceinline__ void load(size_t cell, TC (&out)[NPT]) const
+    // g of row r of cells (of G or Gn) as a buffer
+    __device__ __forceinline__ __amdgpu_buffer_rsrc_t row(const TS *base, int r) const
     {
-        const TS *g = G + cell * (size_t)(64 * NPT) + lane;
+        return buf_rsrc(base + (size_t)r * P->nx * (64 * NPT), row_bytes);
+    }
+    static constexpr int NB = 64 * (int)sizeof(TS);   // byte stride of node m
+
+    __device__ __forceinline__ void load(__amdgpu_buffer_rsrc_t rs, int off, TC (&out)[NPT]) const
+    {
 #pragma unroll
-        for (int m = 0; m < NPT; ++m) out[m] = (TC)g[64 * m];
+        for (int m = 0; m < NPT; ++m) out[m] = (TC)buf_load(rs, off, NB * m, (TS *)nullptr);
     }
 
-    // FP64 (one wavefront per SIMD): the next x-sweep's three cells are loaded
-    // into registers while the current row is computed
-#ifndef MM_LK_PF
-#define MM_LK_PF 0
-#endif
-    static constexpr bool PF = MM_LK_PF && sizeof(TC) == 8 && !CL && !RC;
-    TC pfc[PF ? NPT : 1], pfm[PF ? NPT : 1], pfp[PF ? NPT : 1];
-
-    __device__ __forceinline__ void prefetch(int x)
-    {
-        if constexpr (PF) {
-            const size_t c = (size_t)x * P->nx + i;
-            load(c, pfc);
-            if (i > 0) load(c - 1, pfm);
-            else if (P->bc[0].kind == BC_PERIODIC) load(c + P->nx - 1, pfm);
-            if (i < P->nx - 1) load(c + 1, pfp);
-            else if (P->bc[1].kind == BC_PERIODIC) load(c - (P->nx - 1), pfp);
-        }
-    }
+    // x-transport of one cell: the upwind difference of this lane's velocity
+    // needs only the upwind x-neighbour (i - 1 for v1 > 0, i + 1 otherwise), so
+    // Z = |v1| / dx (g(i) - g(upwind)).  Beyond a non-periodic side the upwind
+    // cell is the cell itself (the ghost takes its value: off_u = off_c), and
+    // beyond an open side (wall, inflow) the ghost value is 0 instead (zero_nb).
+    bool zero_nb;
+    bool edge_col;   // wave-uniform: some lane of this column has zero_nb
 
     // x-sweep of row r: G*(i, r) into out; tables of cell (i, r) go to `slot`;
-    // R: the record of cell (i, r).  With the prefetch, the cells come from the
-    // prefetch registers and the loads of row `next` (>= 0) are issued after use.
-    __device__ __forceinline__ void xsweep(int r, int slot, TC (&out)[NPT], const Rec &R, bool pre = false,
-                                           int next = -1)
+    // R: the record of cell (i, r)
+    __device__ __forceinline__ void xsweep(int r, int slot, TC (&out)[NPT], const Rec &R)
     {
-        const size_t c = (size_t)r * P->nx + i;
         build_tables(slot, R);
         TC gc[NPT], Z[NPT];
         {
-            TC gm[NPT], gp[NPT];
-            if (PF && pre) {
+            const auto rs = row(G, r);
+            TC gn[NPT];
+            load(rs, off_c, gc);
+            load(rs, off_u, gn);
+            if (edge_col) {
 #pragma unroll
-                for (int m = 0; m < NPT; ++m) {
-                    gc[m] = pfc[PF ? m : 0];
-                    gm[m] = pfm[PF ? m : 0];
-                    gp[m] = pfp[PF ? m : 0];
-                }
-            } else {
-                load(c, gc);
-                if (i > 0) load(c - 1, gm);
-                else if (P->bc[0].kind == BC_PERIODIC) load(c + P->nx - 1, gm);
-                if (i < P->nx - 1) load(c + 1, gp);
-                else if (P->bc[1].kind == BC_PERIODIC) load(c - (P->nx - 1), gp);
-            }
-            if (i == 0 && P->bc[0].kind != BC_PERIODIC) {
-                const bool open = is_open(P->bc[0].kind);
-#pragma unroll
-                for (int m = 0; m < NPT; ++m) gm[m] = open ? (TC)0 : gc[m];
-            }
-            if (i == P->nx - 1 && P->bc[1].kind != BC_PERIODIC) {
-                const bool open = is_open(P->bc[1].kind);
-#pragma unroll
-                for (int m = 0; m < NPT; ++m) gp[m] = open ? (TC)0 : gc[m];
+                for (int m = 0; m < NPT; ++m) gn[m] = zero_nb ? (TC)0 : gn[m];
             }
 #pragma unroll
-            for (int m = 0; m < NPT; ++m) Z[m] = ax * (gp[m] - gc[m]) + bx * (gc[m] - gm[m]);
+            for (int m = 0; m < NPT; ++m) Z[m] = cx * (gc[m] - gn[m]);
         }
-        if (PF && next >= 0) prefetch(next);
         double t0 = 0.0, t2 = 0.0, t22 = 0.0;
 #pragma unroll
         for (int m = 0; m < NPT; ++m) {
@@ -166,44 +141,34 @@ struct PassLK {
     // cell: the second pass reloads the chunk (L1/L2 hits) and recomputes Z.
     static constexpr int CH = NPT < 8 ? NPT : 8;
 
-    __device__ __forceinline__ void load_chunk(size_t cell, int m0, TC (&out)[CH]) const
+    __device__ __forceinline__ void load_chunk(__amdgpu_buffer_rsrc_t rs, int off, int m0, TC (&out)[CH]) const
     {
-        const TS *g = G + cell * (size_t)(64 * NPT) + lane + 64 * m0;
 #pragma unroll
-        for (int m = 0; m < CH; ++m) out[m] = (TC)g[64 * m];
+        for (int m = 0; m < CH; ++m) out[m] = (TC)buf_load(rs, off, NB * (m0 + m), (TS *)nullptr);
     }
 
-    __device__ __forceinline__ void zx_chunk(size_t c, int m0, TC (&gc)[CH], TC (&Z)[CH]) const
+    __device__ __forceinline__ void zx_chunk(__amdgpu_buffer_rsrc_t rs, int m0, TC (&gc)[CH], TC (&Z)[CH]) const
     {
-        TC gm[CH], gp[CH];
-        load_chunk(c, m0, gc);
-        if (i > 0) load_chunk(c - 1, m0, gm);
-        else if (P->bc[0].kind == BC_PERIODIC) load_chunk(c + P->nx - 1, m0, gm);
-        else {
-            const bool open = is_open(P->bc[0].kind);
+        TC gn[CH];
+        load_chunk(rs, off_c, m0, gc);
+        load_chunk(rs, off_u, m0, gn);
+        if (edge_col) {
 #pragma unroll
-            for (int m = 0; m < CH; ++m) gm[m] = open ? (TC)0 : gc[m];
-        }
-        if (i < P->nx - 1) load_chunk(c + 1, m0, gp);
-        else if (P->bc[1].kind == BC_PERIODIC) load_chunk(c - (P->nx - 1), m0, gp);
-        else {
-            const bool open = is_open(P->bc[1].kind);
-#pragma unroll
-            for (int m = 0; m < CH; ++m) gp[m] = open ? (TC)0 : gc[m];
+            for (int m = 0; m < CH; ++m) gn[m] = zero_nb ? (TC)0 : gn[m];
         }
 #pragma unroll
-        for (int m = 0; m < CH; ++m) Z[m] = ax * (gp[m] - gc[m]) + bx * (gc[m] - gm[m]);
+        for (int m = 0; m < CH; ++m) Z[m] = cx * (gc[m] - gn[m]);
     }
 
     __device__ __forceinline__ void xsweep_rc(int r, int slot, TC (&out)[NPT], const Rec &R) const
     {
-        const size_t c = (size_t)r * P->nx + i;
+        const auto rs = row(G, r);
         build_tables(slot, R);
         double t0 = 0.0, t2 = 0.0, t22 = 0.0;
 #pragma unroll
         for (int m0 = 0; m0 < NPT; m0 += CH) {
             TC gc[CH], Z[CH];
-            zx_chunk(c, m0, gc, Z);
+            zx_chunk(rs, m0, gc, Z);
 #pragma unroll
             for (int m = 0; m < CH; ++m) {
                 const double z = (double)Z[m], w = v2d(m0 + m), u = w * z;
@@ -225,7 +190,7 @@ struct PassLK {
 #pragma unroll
         for (int m0 = 0; m0 < NPT; m0 += CH) {
             TC gc[CH], Z[CH];
-            zx_chunk(c, m0, gc, Z);
+            zx_chunk(rs, m0, gc, Z);
 #pragma unroll
             for (int m = 0; m < CH; ++m) {
                 const TC w = v2(m0 + m);
@@ -237,8 +202,8 @@ struct PassLK {
 
     // y-sweep of a wall-adjacent cell: G** only.  The wall form of G-hat, the
     // relaxation and H of these cells are done by k_wall_relax2d afterwards.
-    __device__ __forceinline__ void wall_row(size_t c, int slot, const TC (&lo)[NPT], const TC (&ce)[NPT],
-                                             const TC (&hi)[NPT], const Rec &R) const
+    __device__ __forceinline__ void wall_row(size_t c, int jr, int slot, const TC (&lo)[NPT], const TC (&ce)[NPT],
+                                             const TC (&hi)[NPT], const Rec &R)
     {
         Cell<TC> cl;
         load_cell(R, cl);
@@ -260,18 +225,18 @@ struct PassLK {
         TC cz[4];
         proj_poly(cl, s, cz);
         const TC Kz = cz[0] + cz[1] * v1 + cz[3] * v1 * v1, dt = (TC)P->dt;
-        TS *gout = Gn + c * (size_t)(64 * NPT) + lane;
+        const auto ws = row(Gn, jr);
 #pragma unroll
         for (int m = 0; m < NPT; ++m) {
             const TC w = v2(m);
             const TC pz = (cz[3] * w + cz[2]) * w + Kz;
-            gout[64 * m] = (TS)(ce[m] + dt * (pz * maxw(t, E1, m) - Zy[m]));
+            buf_store((TS)(ce[m] + dt * (pz * maxw(t, E1, m) - Zy[m])), ws, off_c, NB * m);
         }
     }
 
     // y-sweep, G-hat (eqn5-97), relaxation and H for interior row j with window (lo, ce, hi)
-    __device__ __forceinline__ void finish_row(size_t c, int slot, const TC (&lo)[NPT], const TC (&ce)[NPT],
-                                               const TC (&hi)[NPT], const Rec &R) const
+    __device__ __forceinline__ void finish_row(size_t c, int jr, int slot, const TC (&lo)[NPT], const TC (&ce)[NPT],
+                                               const TC (&hi)[NPT], const Rec &R)
     {
         Cell<TC> cl;
         load_cell(R, cl);
@@ -344,7 +309,9 @@ struct PassLK {
         const TC Kz = cz[0] + cz[1] * v1 + cz[3] * vv;
         const TC Kb = cb[0] + cb[1] * v1 + cb[3] * vv;
         const TC dt = (TC)P->dt, ra = (TC)cl.ra, rb = (TC)cl.rb;
-        TS *gout = Gn + c * (size_t)(64 * NPT) + lane;
+        const auto ws = row(Gn, jr);
+        // recompute the node values below rather than hold all NPT of them from the first loop
+        refresh();
         double h0 = 0.0, h1 = 0.0, h2 = 0.0, h3 = 0.0;
         const double u2d = cl.u2d;
 #pragma unroll
@@ -356,7 +323,7 @@ struct PassLK {
             const TC gss = ce[m] + dt * (pz * M - Zy[m]);
             const TC gh = base[m] - pb * M;
             const TS gn = (TS)(ra * gss + rb * gh);
-            gout[64 * m] = gn;
+            buf_store(gn, ws, off_c, NB * m);
             const double g = (double)gn, w2 = v2d(m) - u2d;
             const double ug = g * w2, ug2 = ug * w2;
             h0 += g;
@@ -373,8 +340,8 @@ struct PassLK {
     }
 
     // y-sweep, G-hat (eqn5-97), relaxation and H for interior row j with window (lo, ce, hi)
-    __device__ __forceinline__ void finish_row_rc(size_t c, int slot, const TC (&lo)[NPT], const TC (&ce)[NPT],
-                                               const TC (&hi)[NPT], const Rec &R) const
+    __device__ __forceinline__ void finish_row_rc(size_t c, int jr, int slot, const TC (&lo)[NPT], const TC (&ce)[NPT],
+                                               const TC (&hi)[NPT], const Rec &R)
     {
         Cell<TC> cl;
         load_cell(R, cl);
@@ -447,7 +414,7 @@ struct PassLK {
         const TC Kz = cz[0] + cz[1] * v1 + cz[3] * vv;
         const TC Kb = cb[0] + cb[1] * v1 + cb[3] * vv;
         const TC dt = (TC)P->dt, ra = (TC)cl.ra, rb = (TC)cl.rb;
-        TS *gout = Gn + c * (size_t)(64 * NPT) + lane;
+        const auto ws = row(Gn, jr);
         double h0 = 0.0, h1 = 0.0, h2 = 0.0, h3 = 0.0;
         const double u2d = cl.u2d;
         r = r0;
@@ -471,7 +438,7 @@ struct PassLK {
             const TC gss = ce[m] + dt * (pz * M - zyv);
             const TC gh = basev - pb * M;
             const TS gn = (TS)(ra * gss + rb * gh);
-            gout[64 * m] = gn;
+            buf_store(gn, ws, off_c, NB * m);
             const double g = (double)gn, w2 = v2d(m) - u2d;
             const double ug = g * w2, ug2 = ug * w2;
             h0 += g;
@@ -502,8 +469,9 @@ struct PassLK {
     // row-variant: the node constants are recomputed (one FMA each) instead.
     __device__ __forceinline__ void refresh()
     {
-        asm volatile("" : "+v"(v2bd), "+v"(l0));
+        asm volatile("" : "+v"(v2bd), "+v"(l0), "+v"(hd));
         v2b = (TC)v2bd;
+        h = (TC)hd;
     }
 
     // closure form: is the micro part of cell (i, r) solved?  Rows beyond a
@@ -563,20 +531,20 @@ struct PassLK {
             solve = micro_row(j);
             if (!solve && !micro_row(j + 1) && !micro_row(j + 2)) return;
         }
-        const int nxt = (PF && j + 2 <= j1) ? xrow(j + 2) : -1;
         if (j + 1 < P->ny) {
             if constexpr (RC) xsweep_rc(j + 1, (j + 1) & 1, win[HI], rec_at(j + 1, rv[HI]));
-            else xsweep(j + 1, (j + 1) & 1, win[HI], rec_at(j + 1, rv[HI]), PF, nxt);
+            else xsweep(j + 1, (j + 1) & 1, win[HI], rec_at(j + 1, rv[HI]));
         }
-        else if (P->bc[3].kind == BC_PERIODIC) xsweep(0, 2, win[HI], rec_at(0, rv[HI]), PF, nxt);
+        else if (P->bc[3].kind == BC_PERIODIC) xsweep(0, 2, win[HI], rec_at(0, rv[HI]));
         else ghost(P->bc[3].kind, win[CE], win[HI]);
         __builtin_amdgcn_sched_barrier(0);
         if (CL && !solve) return;
+        refresh();
         const size_t c = (size_t)j * P->nx + i;
         const Rec R = rec_at(j, rv[CE]);
-        if (R[R_WALL] != 0.0) wall_row(c, j & 1, win[LO], win[CE], win[HI], R);
-        else if constexpr (RC) finish_row_rc(c, j & 1, win[LO], win[CE], win[HI], R);
-        else finish_row(c, j & 1, win[LO], win[CE], win[HI], R);
+        if (R[R_WALL] != 0.0) wall_row(c, j, j & 1, win[LO], win[CE], win[HI], R);
+        else if constexpr (RC) finish_row_rc(c, j, j & 1, win[LO], win[CE], win[HI], R);
+        else finish_row(c, j, j & 1, win[LO], win[CE], win[HI], R);
         __builtin_amdgcn_sched_barrier(0);
     }
 };
@@ -589,11 +557,14 @@ struct PassLK {
 #ifndef MM_LK_BIG_BYTES
 #define MM_LK_BIG_BYTES 64
 #endif
+#ifndef MM_LK_OCC64
+#define MM_LK_OCC64 1
+#endif
 template <typename TC, int NPT>
 struct LKTraits {
     static constexpr bool big = sizeof(TC) * NPT >= MM_LK_BIG_BYTES;
     static constexpr bool recompute = big && sizeof(TC) == 4;
-    static constexpr int occupancy = big && !recompute ? 1 : 2;
+    static constexpr int occupancy = big && !recompute ? MM_LK_OCC64 : 2;
 };
 
 template <typename TS, typename TC, int NPT, bool CL>
@@ -624,8 +595,25 @@ __global__ __launch_bounds__(64 * WPG, (LKTraits<TC, NPT>::occupancy)) void k_fu
     ps.v2bd = P.v2_lo + (ps.l0 + 0.5) * P.dv2;
     ps.hd = ps.L * P.dv2;
     ps.v1 = (TC)ps.v1d;
-    ps.ax = (TC)(fmin(ps.v1d, 0.0) / P.dx);
-    ps.bx = (TC)(fmax(ps.v1d, 0.0) / P.dx);
+    ps.cx = (TC)(fabs(ps.v1d) / P.dx);
+    {
+        const bool pos = ps.v1d > 0.0;
+        const int side = pos ? 0 : 1;
+        int iu = pos ? ps.i - 1 : ps.i + 1;
+        bool ghost = false;
+        if (iu < 0 || iu >= P.nx) {
+            if (P.bc[side].kind == BC_PERIODIC) iu = iu < 0 ? P.nx - 1 : 0;
+            else {
+                ghost = true;
+                iu = ps.i;
+            }
+        }
+        ps.row_bytes = P.nx * 64 * NPT * (int)sizeof(TS);
+        ps.off_c = (ps.i * 64 * NPT + ps.lane) * (int)sizeof(TS);
+        ps.off_u = (iu * 64 * NPT + ps.lane) * (int)sizeof(TS);
+        ps.zero_nb = ghost && is_open(P.bc[side].kind);
+        ps.edge_col = __ballot(ps.zero_nb) != 0;
+    }
     ps.v2b = (TC)ps.v2bd;
     ps.h = (TC)ps.hd;
     ps.idy = (TC)(1.0 / P.dy);
@@ -654,10 +642,6 @@ __global__ __launch_bounds__(64 * WPG, (LKTraits<TC, NPT>::occupancy)) void k_fu
         if (j0 > 0) ps.xsweep(j0 - 1, 2, win[0], ps.rec_at(j0 - 1, rv[0]));
         else if (P.bc[2].kind == BC_PERIODIC) ps.xsweep(P.ny - 1, 2, win[0], ps.rec_at(P.ny - 1, rv[0]));
         else ps.ghost(P.bc[2].kind, win[1], win[0]);
-    }
-    if (ps.PF) {
-        const int x1 = ps.xrow(j0 + 1);
-        if (x1 >= 0) ps.prefetch(x1);
     }
     // full rounds of three rows rotate the window back to its start; the tail
     // (one or two rows) runs after the loop so the window is never merged
@@ -701,6 +685,8 @@ bool lk_supported(const Params &P)
     const int L = 64 / P.nv1;
     if (P.nv2 % L != 0 || P.nv2 > MAXV) return false;
     const int npt = P.nv / 64;
+    // a row of cells of g is addressed with 32-bit byte offsets
+    if ((long long)P.nx * P.nv * 8 >= (1LL << 31)) return false;
     return npt == 1 || npt == 2 || npt == 4 || npt == 8 || npt == 16;
 }
 
@@ -709,7 +695,7 @@ bool launch_micro_lk2d(const void *G, void *Gn, double *H, const double *rec, co
 {
     if (!lk_supported(P)) return false;
     const int npt = P.nv / 64;
-    const bool one_wave = precision == 0 && 8 * npt >= MM_LK_BIG_BYTES;
+    const bool one_wave = precision == 0 && 8 * npt >= MM_LK_BIG_BYTES && MM_LK_OCC64 == 1;
     const Geom geo = geometry(P, one_wave ? 1 : 2);
     if (cls) {   // closure form: g in FP32 only
         // the solved cells cluster along the walls: short row segments spread a

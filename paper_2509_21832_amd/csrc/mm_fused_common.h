@@ -109,6 +109,31 @@ __device__ __forceinline__ double t_exp(double x) { return exp(x); }
 __device__ __forceinline__ float t_expm1(float x) { return expm1f(x); }
 __device__ __forceinline__ double t_expm1(double x) { return expm1(x); }
 
+// Raw buffer access: a wave-uniform base and extent (one row of cells) in
+// SGPRs, the lane's byte offset in one VGPR and the node's byte offset as an
+// SGPR or immediate.  Accesses beyond the extent read 0 and write nothing.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void *base, int bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, bytes, 0x00020000);
+}
+__device__ __forceinline__ double buf_load(__amdgpu_buffer_rsrc_t r, int voff, int soff, double *)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+__device__ __forceinline__ float buf_load(__amdgpu_buffer_rsrc_t r, int voff, int soff, float *)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+__device__ __forceinline__ void buf_store(double v, __amdgpu_buffer_rsrc_t r, int voff, int soff)
+{
+    typedef unsigned u2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, voff, soff, 0);
+}
+__device__ __forceinline__ void buf_store(float v, __amdgpu_buffer_rsrc_t r, int voff, int soff)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
+}
+
 // Per-cell coefficients (wave-uniform), converted to the compute type
 template <typename TC>
 struct Cell {
