@@ -45,7 +45,9 @@ enum mm_status {
     MM_EINVAL = 1,     /* invalid configuration or argument                    */
     MM_ENOMEM = 2,     /* device or host allocation failed                     */
     MM_EDEVICE = 3,    /* a HIP runtime call failed                            */
-    MM_ENONPHYS = 4,   /* rho <= 0, T <= 0, det(calT) <= 0 or a non-finite value */
+    MM_ENONPHYS = 4,   /* rho <= 0, T <= 0, det(calT) <= 0 or a non-finite value; in 2D also a
+                          Maxwellian or ES Gaussian whose exponent exceeds 600 at a node of the
+                          velocity grid (a gas too cold for the grid to resolve) */
     MM_ESTATE = 5      /* the context is unusable (an earlier device error)     */
 };
 

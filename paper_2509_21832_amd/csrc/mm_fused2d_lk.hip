@@ -72,6 +72,35 @@ struct PassLK {
         return E1 * (TC)t[MAXV + l0 + L * m];
     }
 
+    // FP64 has no tables: a Gaussian of the cell along this lane's nodes,
+    // e(m) = exp(quadratic in m), follows the exact recurrence
+    // e(m+1) = e(m) r(m), r(m+1) = r(m) k (the range rule of the 2D solver keeps
+    // e(0) and r(0) inside the range of exp)
+    static constexpr bool Q8 = sizeof(TC) == 8;
+    struct Gq {
+        double e, r, k;
+        __device__ __forceinline__ double next()
+        {
+            const double v = e;
+            e *= r;
+            r *= k;
+            return v;
+        }
+    };
+    // the Maxwellian of record R: mpre exp(-(w1^2 + w2(m)^2) / 2T)
+    __device__ __forceinline__ Gq maxw_q(const Rec &R) const
+    {
+        const double i2T = R[R_I2T], a = v1d - R[R_U1], w = v2bd - R[R_U2];
+        return Gq{R[R_MPRE] * exp(-(a * a + w * w) * i2T), exp(-(2.0 * w + hd) * hd * i2T), R[R_KM]};
+    }
+    // the ES Gaussian of record R: gpre exp(-(QA w1^2 + 2 QB w1 w2(m) + QC w2(m)^2))
+    __device__ __forceinline__ Gq es_q(const Rec &R) const
+    {
+        const double qa = R[R_QA], qb = R[R_QB], qc = R[R_QC], a = v1d - R[R_U1], w = v2bd - R[R_U2];
+        return Gq{R[R_GPRE] * exp(-((qa * a + 2.0 * qb * w) * a + qc * w * w)),
+                  exp(-(2.0 * qb * a + qc * (2.0 * w + hd)) * hd), R[R_KG]};
+    }
+
     // g of row r of cells (of G or Gn) as a buffer
     __device__ __forceinline__ __amdgpu_buffer_rsrc_t row(const TS *base, int r) const
     {
@@ -97,11 +126,11 @@ struct PassLK {
     // R: the record of cell (i, r)
     __device__ __forceinline__ void xsweep(int r, int slot, TC (&out)[NPT], const Rec &R)
     {
-        build_tables(slot, R);
+        if constexpr (!Q8) build_tables(slot, R);
         TC gc[NPT], Z[NPT];
         {
-            const auto rs = row(G, r);
             TC gn[NPT];
+            const auto rs = row(G, r);
             load(rs, off_c, gc);
             load(rs, off_u, gn);
             if (edge_col) {
@@ -126,14 +155,24 @@ struct PassLK {
         TC cp[4];
         proj_poly(cl, s, cp);
         const TC K = cp[0] + cp[1] * v1 + cp[3] * v1 * v1;
-        const double *t = slot_tab(slot);
-        const TC E1 = (TC)t[k];
         const TC dt = (TC)P->dt;
+        if constexpr (Q8) {
+            Gq mq = maxw_q(R);
 #pragma unroll
-        for (int m = 0; m < NPT; ++m) {
-            const TC w = v2(m);
-            const TC pm = (cp[3] * w + cp[2]) * w + K;
-            out[m] = gc[m] + dt * (pm * maxw(t, E1, m) - Z[m]);
+            for (int m = 0; m < NPT; ++m) {
+                const TC w = v2(m);
+                const TC pm = (cp[3] * w + cp[2]) * w + K;
+                out[m] = gc[m] + dt * (pm * mq.next() - Z[m]);
+            }
+        } else {
+            const double *t = slot_tab(slot);
+            const TC E1 = (TC)t[k];
+#pragma unroll
+            for (int m = 0; m < NPT; ++m) {
+                const TC w = v2(m);
+                const TC pm = (cp[3] * w + cp[2]) * w + K;
+                out[m] = gc[m] + dt * (pm * maxw(t, E1, m) - Z[m]);
+            }
         }
     }
 
@@ -200,6 +239,14 @@ struct PassLK {
         }
     }
 
+    // y-transport of node m: v2 (G(j) - G(j -/+ 1)) / dy upwind, written as
+    // |v2| / dy (G(j) - G(upwind)) (the same value)
+    __device__ __forceinline__ TC zy(int m, const TC (&lo)[NPT], const TC (&ce)[NPT], const TC (&hi)[NPT]) const
+    {
+        const TC w = v2(m);
+        return (fabs(w) * idy) * (ce[m] - (w < (TC)0 ? hi[m] : lo[m]));
+    }
+
     // y-sweep of a wall-adjacent cell: G** only.  The wall form of G-hat, the
     // relaxation and H of these cells are done by k_wall_relax2d afterwards.
     __device__ __forceinline__ void wall_row(size_t c, int jr, int slot, const TC (&lo)[NPT], const TC (&ce)[NPT],
@@ -207,14 +254,11 @@ struct PassLK {
     {
         Cell<TC> cl;
         load_cell(R, cl);
-        const double *t = slot_tab(slot);
-        const TC E1 = (TC)t[k];
         TC Zy[NPT];
         double t0 = 0.0, t2 = 0.0, t22 = 0.0;
 #pragma unroll
         for (int m = 0; m < NPT; ++m) {
-            const TC w = v2(m);
-            Zy[m] = w * idy * (w < (TC)0 ? hi[m] - ce[m] : ce[m] - lo[m]);
+            Zy[m] = zy(m, lo, ce, hi);
             const double z = (double)Zy[m], vd = v2d(m), u = vd * z;
             t0 += z;
             t2 += u;
@@ -226,11 +270,23 @@ struct PassLK {
         proj_poly(cl, s, cz);
         const TC Kz = cz[0] + cz[1] * v1 + cz[3] * v1 * v1, dt = (TC)P->dt;
         const auto ws = row(Gn, jr);
+        if constexpr (Q8) {
+            Gq mq = maxw_q(R);
 #pragma unroll
-        for (int m = 0; m < NPT; ++m) {
-            const TC w = v2(m);
-            const TC pz = (cz[3] * w + cz[2]) * w + Kz;
-            buf_store((TS)(ce[m] + dt * (pz * maxw(t, E1, m) - Zy[m])), ws, off_c, NB * m);
+            for (int m = 0; m < NPT; ++m) {
+                const TC w = v2(m);
+                const TC pz = (cz[3] * w + cz[2]) * w + Kz;
+                buf_store((TS)(ce[m] + dt * (pz * mq.next() - Zy[m])), ws, off_c, NB * m);
+            }
+        } else {
+            const double *t = slot_tab(slot);
+            const TC E1 = (TC)t[k];
+#pragma unroll
+            for (int m = 0; m < NPT; ++m) {
+                const TC w = v2(m);
+                const TC pz = (cz[3] * w + cz[2]) * w + Kz;
+                buf_store((TS)(ce[m] + dt * (pz * maxw(t, E1, m) - Zy[m])), ws, off_c, NB * m);
+            }
         }
     }
 
@@ -241,10 +297,7 @@ struct PassLK {
         Cell<TC> cl;
         load_cell(R, cl);
         const bool discrete = P->proj_mode == PROJ_DISCRETE;
-        const double *t = slot_tab(slot);
-        const TC E1 = (TC)t[k];
         const double a = v1d - cl.u1d;              // w1 of this lane
-        const double w2b = v2bd - cl.u2d;           // w2 at m = 0
         // closed form of G-hat (eqn5-97) as a cubic in w2, times -1/tau
         TC C0, C1, C2, C3;
         {
@@ -256,17 +309,19 @@ struct PassLK {
             C2 = (TC)(-itau * (-s11 * i2T + iT * i2T * a * dTx));
             C3 = (TC)(-itau * (iT * i2T * dTy));
         }
-        // ES term: delta(m) = lg - (dA w1^2 + 2 dB w1 w2(m) + dC w2(m)^2)
-        const double dA = R[R_DA], dB = R[R_QB], dC = R[R_DC], lg = R[R_LG];
-        double r = 0.0, q = 0.0, kq = 0.0;
-        TC A0 = (TC)0, Bq = (TC)0, Cq = (TC)0;
-        if constexpr (sizeof(TC) == 8) {
-            const double d0 = lg - (dA * a * a + 2.0 * dB * a * w2b + dC * w2b * w2b);
-            const double d1 = -(2.0 * dB * a * hd + dC * (2.0 * w2b * hd + hd * hd));
-            r = exp(d0);
-            q = exp(d1);
-            kq = exp(-2.0 * dC * hd * hd);
+        // Maxwellian M and ES term (calG - M) / eps: FP64 follows M and the ES
+        // Gaussian calG along the nodes; FP32 reads M from the tables and takes
+        // calG / M - 1 = expm1(delta), delta = lg - (dA w1^2 + 2 dB w1 w2 + dC w2^2)
+        [[maybe_unused]] Gq mq0, gq;
+        [[maybe_unused]] const double *t = nullptr;
+        [[maybe_unused]] TC E1 = (TC)0, A0 = (TC)0, Bq = (TC)0, Cq = (TC)0;
+        if constexpr (Q8) {
+            mq0 = maxw_q(R);
+            gq = es_q(R);
         } else {
+            t = slot_tab(slot);
+            E1 = (TC)t[k];
+            const double dA = R[R_DA], dB = R[R_QB], dC = R[R_DC], lg = R[R_LG];
             A0 = (TC)(lg - dA * a * a);
             Bq = (TC)(-2.0 * dB * a);
             Cq = (TC)(-dC);
@@ -274,29 +329,31 @@ struct PassLK {
         const TC u2 = cl.u2, ieps = cl.ieps;
         TC Zy[NPT], base[NPT];
         double acc[6] = {0, 0, 0, 0, 0, 0};
+        {
+            [[maybe_unused]] Gq mq = mq0;
 #pragma unroll
-        for (int m = 0; m < NPT; ++m) {
-            const TC w = v2(m), w2 = w - u2;
-            Zy[m] = w * idy * (w < (TC)0 ? hi[m] - ce[m] : ce[m] - lo[m]);
-            const TC M = maxw(t, E1, m);
-            TC es;
-            if constexpr (sizeof(TC) == 8) {
-                es = (TC)(r - 1.0) * M * ieps;
-                r *= q;
-                q *= kq;
-            } else {
-                es = M * expm1f(A0 + (Bq + Cq * w2) * w2) * ieps;
+            for (int m = 0; m < NPT; ++m) {
+                const TC w = v2(m), w2 = w - u2;
+                Zy[m] = zy(m, lo, ce, hi);
+                TC M, es;
+                if constexpr (Q8) {
+                    M = mq.next();
+                    es = (gq.next() - M) * ieps;
+                } else {
+                    M = maxw(t, E1, m);
+                    es = M * expm1f(A0 + (Bq + Cq * w2) * w2) * ieps;
+                }
+                base[m] = M * (((C3 * w2 + C2) * w2 + C1) * w2 + C0) + es;
+                const double vd = v2d(m);
+                const double z = (double)Zy[m], b = (double)base[m];
+                const double uz = vd * z, ub = vd * b;
+                acc[0] += z;
+                acc[1] += uz;
+                acc[2] += vd * uz;
+                acc[3] += b;
+                acc[4] += ub;
+                acc[5] += vd * ub;
             }
-            base[m] = M * (((C3 * w2 + C2) * w2 + C1) * w2 + C0) + es;
-            const double vd = v2d(m);
-            const double z = (double)Zy[m], b = (double)base[m];
-            const double uz = vd * z, ub = vd * b;
-            acc[0] += z;
-            acc[1] += uz;
-            acc[2] += vd * uz;
-            acc[3] += b;
-            acc[4] += ub;
-            acc[5] += vd * ub;
         }
         const double v1s = v1d * v1d;
         double s[8] = {acc[0], v1d * acc[0], acc[1], v1s * acc[0] + acc[2],
@@ -314,10 +371,13 @@ struct PassLK {
         refresh();
         double h0 = 0.0, h1 = 0.0, h2 = 0.0, h3 = 0.0;
         const double u2d = cl.u2d;
+        [[maybe_unused]] Gq mq = mq0;
 #pragma unroll
         for (int m = 0; m < NPT; ++m) {
             const TC w = v2(m);
-            const TC M = maxw(t, E1, m);
+            TC M;
+            if constexpr (Q8) M = mq.next();
+            else M = maxw(t, E1, m);
             const TC pz = (cz[3] * w + cz[2]) * w + Kz;
             const TC pb = (cb[3] * w + cb[2]) * w + Kb;
             const TC gss = ce[m] + dt * (pz * M - Zy[m]);
@@ -382,7 +442,7 @@ struct PassLK {
 #pragma unroll
         for (int m = 0; m < NPT; ++m) {
             const TC w = v2(m), w2 = w - u2;
-            const TC zyv = w * idy * (w < (TC)0 ? hi[m] - ce[m] : ce[m] - lo[m]);
+            const TC zyv = zy(m, lo, ce, hi);
             const TC M = maxw(t, E1, m);
             TC es;
             if constexpr (sizeof(TC) == 8) {
@@ -423,7 +483,7 @@ struct PassLK {
         for (int m = 0; m < NPT; ++m) {
             const TC w = v2(m), wc = w - u2;
             const TC M = maxw(t, E1, m);
-            const TC zyv = w * idy * (w < (TC)0 ? hi[m] - ce[m] : ce[m] - lo[m]);
+            const TC zyv = zy(m, lo, ce, hi);
             TC es;
             if constexpr (sizeof(TC) == 8) {
                 es = (TC)(r - 1.0) * M * ieps;

@@ -124,14 +124,17 @@ __device__ __forceinline__ float buf_load(__amdgpu_buffer_rsrc_t r, int voff, in
 {
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
 }
+// Stores are non-temporal (cache policy bit NT): g of the next time level is
+// not read again by the kernel that writes it
+constexpr int STORE_NT = 2;
 __device__ __forceinline__ void buf_store(double v, __amdgpu_buffer_rsrc_t r, int voff, int soff)
 {
     typedef unsigned u2 __attribute__((ext_vector_type(2)));
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, voff, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, voff, soff, STORE_NT);
 }
 __device__ __forceinline__ void buf_store(float v, __amdgpu_buffer_rsrc_t r, int voff, int soff)
 {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, STORE_NT);
 }
 
 // Per-cell coefficients (wave-uniform), converted to the compute type

@@ -120,8 +120,13 @@ bool state_ok(const mm_config *c, const double *q, int ncell)
             const double T = 0.5 * (P11 + P22) / rho;
             const double S11 = (1.0 - c->nu) * T + c->nu * P11 / rho, S22 = (1.0 - c->nu) * T + c->nu * P22 / rho;
             const double S12 = c->nu * P12 / rho;
-            if (!(rho > 0.0) || !(T > 0.0) || !(P11 > 0.0) || !(P22 > 0.0) || !(S11 * S22 - S12 * S12 > 0.0) ||
+            const double det = S11 * S22 - S12 * S12;
+            if (!(rho > 0.0) || !(T > 0.0) || !(P11 > 0.0) || !(P22 > 0.0) || !(det > 0.0) ||
                 !std::isfinite(u1) || !std::isfinite(u2) || !std::isfinite(P12))
+                return false;
+            const double dv1 = (c->v1_hi - c->v1_lo) / c->nv1, dv2 = (c->v2_hi - c->v2_lo) / c->nv2;
+            if (!mm::exp_range_ok(c->v1_lo, dv1, c->nv1, c->v2_lo, dv2, c->nv2, u1, u2, 1.0 / (2.0 * T),
+                                  S22 / (2.0 * det), -S12 / (2.0 * det), S11 / (2.0 * det)))
                 return false;
         }
     }
@@ -567,7 +572,9 @@ const char *mm_strerror(int status)
     case MM_EINVAL: return "invalid configuration or argument";
     case MM_ENOMEM: return "out of memory";
     case MM_EDEVICE: return "HIP runtime error";
-    case MM_ENONPHYS: return "non-physical macro state (rho, T or det of the ES temperature tensor not positive, or not finite)";
+    case MM_ENONPHYS:
+        return "non-physical macro state (rho, T or det of the ES temperature tensor not positive, or not finite; "
+               "or, in 2D, a Maxwellian exponent beyond 600 on the velocity grid)";
     case MM_ESTATE: return "context unusable after an earlier device error";
     default: return "unknown status";
     }

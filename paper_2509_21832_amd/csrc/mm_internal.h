@@ -57,11 +57,45 @@ enum {
     R_IT,                 // 1 / T
     R_LG,                 // log(GPRE / MPRE) = log(T / sqrt(det calT))
     R_DA, R_DC,           // QA - 1/(2T), QC - 1/(2T): ES exponent minus Maxwellian exponent
+    R_KM, R_KG,           // exp(-2 h^2 / 2T), exp(-2 QC h^2) with h = (64 / nv1) dv2 (lane-k node step
+                          // in v2): second-difference factors of the Maxwellian and ES exponents
     REC = 40
 };
 // wall cells: the four neighbour Maxwellians (x-, x+, y-, y+), each as
 // (rho / (2 pi T), u1, u2, 1 / (2T))
 enum { WREC = 16 };
+
+// Step in v2 between consecutive nodes of one lane in the lane-k phase-space
+// pass (nv1 divides 64; lane k + nv1 l0 owns the nodes (k, l0 + (64 / nv1) m)),
+// or 0 where that layout does not apply
+__host__ __device__ inline double lk_step(int nv1, int nv2, double dv2)
+{
+    if (nv1 > 64 || 64 % nv1 != 0) return 0.0;
+    const int L = 64 / nv1;
+    if (nv2 % L != 0 || nv1 * nv2 < 64) return 0.0;
+    return L * dv2;
+}
+
+// Range rule of the 2D solver: the Maxwellian and ES Gaussian exponents, and the
+// exponent steps between lane-k nodes (h = (64 / nv1) dv2 apart in v2), stay
+// within EXP_RANGE at every node of the velocity grid, so that each Gaussian can
+// be followed along a lane's nodes from its first node without leaving the
+// range of exp.  A state outside it (a gas too cold for the velocity grid) is
+// reported as non-physical.  qa, qb, qc: the ES quadratic form; i2T = 1 / (2T).
+constexpr double EXP_RANGE = 600.0;
+__host__ __device__ inline bool exp_range_ok(double v1_lo, double dv1, int nv1, double v2_lo, double dv2, int nv2,
+                                             double u1, double u2, double i2T, double qa, double qb, double qc)
+{
+    const double a0 = v1_lo + 0.5 * dv1 - u1, a1 = v1_lo + (nv1 - 0.5) * dv1 - u1;
+    const double w0 = v2_lo + 0.5 * dv2 - u2, w1 = v2_lo + (nv2 - 0.5) * dv2 - u2;
+    const double A = fmax(fabs(a0), fabs(a1)), W = fmax(fabs(w0), fabs(w1));
+    const double h = lk_step(nv1, nv2, dv2);
+    const double em = (A * A + W * W) * i2T;
+    const double rm = (2.0 * W + h) * h * i2T;
+    const double eg = qa * A * A + 2.0 * fabs(qb) * A * W + qc * W * W;
+    const double rg = (2.0 * fabs(qb) * A + qc * (2.0 * W + h)) * h;
+    return em <= EXP_RANGE && rm <= EXP_RANGE && eg <= EXP_RANGE && rg <= EXP_RANGE;
+}
 
 // index of the symmetric 4x4 entry (a, b) in the packed R_P0 block
 __host__ __device__ constexpr int sym4(int a, int b)

@@ -94,7 +94,7 @@ __global__ __launch_bounds__(PREP_BLOCK) void k_prep2d(const double *__restrict_
     if (c < ncell) {
     const int i = c % P.nx, j = c / P.nx;
     const CellPrim s = prim_of(Q + 6 * (size_t)c);
-    for (int q = R_DC + 1; q < REC; ++q) R[q] = 0.0;     // unused tail of the record
+    for (int q = R_KG + 1; q < REC; ++q) R[q] = 0.0;     // unused tail of the record
 
     const double tau = tau_of(P, s.rho, s.p, s.T);
     const double S11 = (1.0 - P.nu) * s.T + P.nu * s.P11 / s.rho;
@@ -125,6 +125,14 @@ __global__ __launch_bounds__(PREP_BLOCK) void k_prep2d(const double *__restrict_
     R[R_LG] = log(s.T / sqrt(det));
     R[R_DA] = R[R_QA] - R[R_I2T];
     R[R_DC] = R[R_QC] - R[R_I2T];
+    {
+        const double h = lk_step(P.nv1, P.nv2, P.dv2);
+        R[R_KM] = exp(-2.0 * h * h * R[R_I2T]);
+        R[R_KG] = exp(-2.0 * R[R_QC] * h * h);
+    }
+    if (!exp_range_ok(P.v1_lo, P.dv1, P.nv1, P.v2_lo, P.dv2, P.nv2, s.u1, s.u2, R[R_I2T], R[R_QA], R[R_QB],
+                      R[R_QC]))
+        atomicMin(flag, step);
 
     // projection coefficients
     const double dA = P.dv1 * P.dv2;

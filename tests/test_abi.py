@@ -69,7 +69,7 @@ def test_unpaired_periodic_and_1d_walls_rejected():
     assert e.value.code == B.MM_EINVAL
 
 
-@pytest.mark.parametrize("what", ["rho", "T", "es_det"])
+@pytest.mark.parametrize("what", ["rho", "T", "es_det", "cold"])
 def test_nonphysical_initial_state_rejected(what):
     from paper_2509_21832_amd import binding as B
     p, Q, G = W.quadrant2d(nx=4, ny=4, nv=4, nu=-1.0)
@@ -79,6 +79,14 @@ def test_nonphysical_initial_state_rejected(what):
     elif what == "T":
         Q[0, 0, 3] = Q[0, 0, 1] ** 2 / Q[0, 0, 0] - 0.5
         Q[0, 0, 5] = Q[0, 0, 2] ** 2 / Q[0, 0, 0] - 0.5
+    elif what == "cold":
+        # T = 1e-3 on a velocity grid of half-width 8: the Maxwellian's exponent
+        # reaches about 6e4 at the grid corners, beyond the solver's range rule
+        rho = Q[1, 1, 0]
+        u1, u2 = Q[1, 1, 1] / rho, Q[1, 1, 2] / rho
+        Q[1, 1, 3] = rho * u1 * u1 + rho * 1e-3
+        Q[1, 1, 5] = rho * u2 * u2 + rho * 1e-3
+        Q[1, 1, 4] = rho * u1 * u2
     else:
         # P11 > 0 and P22 > 0 but nu = -1 makes calT = 2 T I - TT singular when P12^2 >= ...
         rho = Q[2, 2, 0]
