@@ -11,10 +11,9 @@
 //     short Horner form in v2 whose coefficients a lane computes once per cell;
 //   - the moment sums factor: a lane accumulates sum F, sum v2 F, sum v2^2 F
 //     and multiplies by its own v1 powers once;
-//   - the ES ratio G/M = exp(delta) with delta quadratic in m follows the
-//     recurrence r(m+1) = r(m) q(m), q(m+1) = q(m) kappa (FP64), or exp m1 of a
-//     directly evaluated delta (FP32), so there is no per-node exponential in
-//     the FP64 pass.
+//   - the Maxwellian and the ES Gaussian have exponents quadratic in m, so
+//     each follows an exact two-factor recurrence along a lane's nodes (in
+//     FP64 for both compute types): no tables and no per-node exponential.
 #include <type_traits>
 
 #include "mm_fused_common.h"
@@ -38,7 +37,13 @@ struct PassLK {
     const double *__restrict__ rec;
     const double *__restrict__ wrec;
     const Params *P;
-    double *tab;            // this wavefront's Maxwellian tables: 3 slots x 2 x MAXV
+    // Large FP64 instances park Zy and G-hat of the row being finished in this
+    // wavefront's LDS slice between the two node loops instead of in registers
+#ifndef MM_LK_STASH
+#define MM_LK_STASH 1
+#endif
+    static constexpr bool STASH = MM_LK_STASH && sizeof(TC) == 8 && NPT >= 16 && !RC;
+    TC *st;                 // this wavefront's slice: [2][NPT][64]
     int lane, i, k, l0, L;
     int row_bytes;          // bytes of one row of cells of g
     int off_c, off_u;       // byte offsets in its row of this lane's value of cell i and of its upwind cell
@@ -48,35 +53,10 @@ struct PassLK {
     __device__ __forceinline__ TC v2(int m) const { return v2b + (TC)m * h; }
     __device__ __forceinline__ double v2d(int m) const { return v2bd + (double)m * hd; }
 
-    __device__ __forceinline__ const double *slot_tab(int slot) const { return tab + slot * 2 * MAXV; }
-
-    __device__ __forceinline__ void build_tables(int slot, const Rec &R) const
-    {
-        const double u1 = R[R_U1], u2 = R[R_U2], i2T = R[R_I2T], mpre = R[R_MPRE];
-        double *t = tab + slot * 2 * MAXV;
-        if (lane < P->nv1) {
-            const double w = P->v1_lo + (lane + 0.5) * P->dv1 - u1;
-            t[lane] = mpre * exp(-w * w * i2T);
-        }
-        if (lane < P->nv2) {
-            const double w = P->v2_lo + (lane + 0.5) * P->dv2 - u2;
-            t[MAXV + lane] = exp(-w * w * i2T);
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    }
-
-    __device__ __forceinline__ TC maxw(const double *t, TC E1, int m) const
-    {
-        return E1 * (TC)t[MAXV + l0 + L * m];
-    }
-
-    // FP64 has no tables: a Gaussian of the cell along this lane's nodes,
-    // e(m) = exp(quadratic in m), follows the exact recurrence
-    // e(m+1) = e(m) r(m), r(m+1) = r(m) k (the range rule of the 2D solver keeps
-    // e(0) and r(0) inside the range of exp)
-    static constexpr bool Q8 = sizeof(TC) == 8;
+    // A Gaussian of the cell along this lane's nodes, e(m) = exp(quadratic in m),
+    // follows the exact recurrence e(m+1) = e(m) r(m), r(m+1) = r(m) k, in FP64
+    // for both compute types (the range rule of the 2D solver keeps e(0) and
+    // r(0) inside the range of exp): no tables, no per-node exponential
     struct Gq {
         double e, r, k;
         __device__ __forceinline__ double next()
@@ -122,11 +102,9 @@ struct PassLK {
     bool zero_nb;
     bool edge_col;   // wave-uniform: some lane of this column has zero_nb
 
-    // x-sweep of row r: G*(i, r) into out; tables of cell (i, r) go to `slot`;
-    // R: the record of cell (i, r)
-    __device__ __forceinline__ void xsweep(int r, int slot, TC (&out)[NPT], const Rec &R)
+    // x-sweep of row r: G*(i, r) into out; R: the record of cell (i, r)
+    __device__ __forceinline__ void xsweep(int r, TC (&out)[NPT], const Rec &R)
     {
-        if constexpr (!Q8) build_tables(slot, R);
         TC gc[NPT], Z[NPT];
         {
             TC gn[NPT];
@@ -156,23 +134,12 @@ struct PassLK {
         proj_poly(cl, s, cp);
         const TC K = cp[0] + cp[1] * v1 + cp[3] * v1 * v1;
         const TC dt = (TC)P->dt;
-        if constexpr (Q8) {
-            Gq mq = maxw_q(R);
+        Gq mq = maxw_q(R);
 #pragma unroll
-            for (int m = 0; m < NPT; ++m) {
-                const TC w = v2(m);
-                const TC pm = (cp[3] * w + cp[2]) * w + K;
-                out[m] = gc[m] + dt * (pm * mq.next() - Z[m]);
-            }
-        } else {
-            const double *t = slot_tab(slot);
-            const TC E1 = (TC)t[k];
-#pragma unroll
-            for (int m = 0; m < NPT; ++m) {
-                const TC w = v2(m);
-                const TC pm = (cp[3] * w + cp[2]) * w + K;
-                out[m] = gc[m] + dt * (pm * maxw(t, E1, m) - Z[m]);
-            }
+        for (int m = 0; m < NPT; ++m) {
+            const TC w = v2(m);
+            const TC pm = (cp[3] * w + cp[2]) * w + K;
+            out[m] = gc[m] + dt * (pm * (TC)mq.next() - Z[m]);
         }
     }
 
@@ -199,10 +166,9 @@ struct PassLK {
         for (int m = 0; m < CH; ++m) Z[m] = cx * (gc[m] - gn[m]);
     }
 
-    __device__ __forceinline__ void xsweep_rc(int r, int slot, TC (&out)[NPT], const Rec &R) const
+    __device__ __forceinline__ void xsweep_rc(int r, TC (&out)[NPT], const Rec &R) const
     {
         const auto rs = row(G, r);
-        build_tables(slot, R);
         double t0 = 0.0, t2 = 0.0, t22 = 0.0;
 #pragma unroll
         for (int m0 = 0; m0 < NPT; m0 += CH) {
@@ -223,9 +189,8 @@ struct PassLK {
         TC cp[4];
         proj_poly(cl, s, cp);
         const TC K = cp[0] + cp[1] * v1 + cp[3] * v1 * v1;
-        const double *t = slot_tab(slot);
-        const TC E1 = (TC)t[k];
         const TC dt = (TC)P->dt;
+        Gq mq = maxw_q(R);
 #pragma unroll
         for (int m0 = 0; m0 < NPT; m0 += CH) {
             TC gc[CH], Z[CH];
@@ -234,7 +199,7 @@ struct PassLK {
             for (int m = 0; m < CH; ++m) {
                 const TC w = v2(m0 + m);
                 const TC pm = (cp[3] * w + cp[2]) * w + K;
-                out[m0 + m] = gc[m] + dt * (pm * maxw(t, E1, m0 + m) - Z[m]);
+                out[m0 + m] = gc[m] + dt * (pm * (TC)mq.next() - Z[m]);
             }
         }
     }
@@ -249,8 +214,8 @@ struct PassLK {
 
     // y-sweep of a wall-adjacent cell: G** only.  The wall form of G-hat, the
     // relaxation and H of these cells are done by k_wall_relax2d afterwards.
-    __device__ __forceinline__ void wall_row(size_t c, int jr, int slot, const TC (&lo)[NPT], const TC (&ce)[NPT],
-                                             const TC (&hi)[NPT], const Rec &R)
+    __device__ __forceinline__ void wall_row(int jr, const TC (&lo)[NPT], const TC (&ce)[NPT], const TC (&hi)[NPT],
+                                             const Rec &R)
     {
         Cell<TC> cl;
         load_cell(R, cl);
@@ -270,82 +235,63 @@ struct PassLK {
         proj_poly(cl, s, cz);
         const TC Kz = cz[0] + cz[1] * v1 + cz[3] * v1 * v1, dt = (TC)P->dt;
         const auto ws = row(Gn, jr);
-        if constexpr (Q8) {
-            Gq mq = maxw_q(R);
+        Gq mq = maxw_q(R);
 #pragma unroll
-            for (int m = 0; m < NPT; ++m) {
-                const TC w = v2(m);
-                const TC pz = (cz[3] * w + cz[2]) * w + Kz;
-                buf_store((TS)(ce[m] + dt * (pz * mq.next() - Zy[m])), ws, off_c, NB * m);
-            }
-        } else {
-            const double *t = slot_tab(slot);
-            const TC E1 = (TC)t[k];
-#pragma unroll
-            for (int m = 0; m < NPT; ++m) {
-                const TC w = v2(m);
-                const TC pz = (cz[3] * w + cz[2]) * w + Kz;
-                buf_store((TS)(ce[m] + dt * (pz * maxw(t, E1, m) - Zy[m])), ws, off_c, NB * m);
-            }
+        for (int m = 0; m < NPT; ++m) {
+            const TC w = v2(m);
+            const TC pz = (cz[3] * w + cz[2]) * w + Kz;
+            buf_store((TS)(ce[m] + dt * (pz * (TC)mq.next() - Zy[m])), ws, off_c, NB * m);
         }
     }
 
-    // y-sweep, G-hat (eqn5-97), relaxation and H for interior row j with window (lo, ce, hi)
-    __device__ __forceinline__ void finish_row(size_t c, int jr, int slot, const TC (&lo)[NPT], const TC (&ce)[NPT],
+    // closed form of G-hat (eqn5-97) at this lane's w1 = a as a cubic in w2, times -1/tau
+    __device__ __forceinline__ void ghat_cubic(const Rec &R, double a, TC (&C)[4]) const
+    {
+        const double i2T = R[R_I2T], iT = R[R_IT], itau = R[R_ITAU];
+        const double s11 = R[R_S11], s12 = R[R_S12], dTx = R[R_DTX], dTy = R[R_DTY];
+        const double q = a * a * i2T - 2.0;
+        C[0] = (TC)(-itau * (s11 * a * a * i2T + iT * q * a * dTx));
+        C[1] = (TC)(-itau * (2.0 * s12 * a * i2T + iT * q * dTy));
+        C[2] = (TC)(-itau * (-s11 * i2T + iT * i2T * a * dTx));
+        C[3] = (TC)(-itau * (iT * i2T * dTy));
+    }
+
+    // y-sweep, G-hat (eqn5-97), relaxation and H for interior row j with window
+    // (lo, ce, hi).  The ES term (calG - M) / eps is formed in FP64 from the two
+    // Gaussians, then converted to the compute type.
+    __device__ __forceinline__ void finish_row(size_t c, int jr, const TC (&lo)[NPT], const TC (&ce)[NPT],
                                                const TC (&hi)[NPT], const Rec &R)
     {
         Cell<TC> cl;
         load_cell(R, cl);
         const bool discrete = P->proj_mode == PROJ_DISCRETE;
         const double a = v1d - cl.u1d;              // w1 of this lane
-        // closed form of G-hat (eqn5-97) as a cubic in w2, times -1/tau
-        TC C0, C1, C2, C3;
-        {
-            const double i2T = R[R_I2T], iT = R[R_IT], itau = R[R_ITAU];
-            const double s11 = R[R_S11], s12 = R[R_S12], dTx = R[R_DTX], dTy = R[R_DTY];
-            const double q = a * a * i2T - 2.0;
-            C0 = (TC)(-itau * (s11 * a * a * i2T + iT * q * a * dTx));
-            C1 = (TC)(-itau * (2.0 * s12 * a * i2T + iT * q * dTy));
-            C2 = (TC)(-itau * (-s11 * i2T + iT * i2T * a * dTx));
-            C3 = (TC)(-itau * (iT * i2T * dTy));
-        }
-        // Maxwellian M and ES term (calG - M) / eps: FP64 follows M and the ES
-        // Gaussian calG along the nodes; FP32 reads M from the tables and takes
-        // calG / M - 1 = expm1(delta), delta = lg - (dA w1^2 + 2 dB w1 w2 + dC w2^2)
-        [[maybe_unused]] Gq mq0, gq;
-        [[maybe_unused]] const double *t = nullptr;
-        [[maybe_unused]] TC E1 = (TC)0, A0 = (TC)0, Bq = (TC)0, Cq = (TC)0;
-        if constexpr (Q8) {
-            mq0 = maxw_q(R);
-            gq = es_q(R);
-        } else {
-            t = slot_tab(slot);
-            E1 = (TC)t[k];
-            const double dA = R[R_DA], dB = R[R_QB], dC = R[R_DC], lg = R[R_LG];
-            A0 = (TC)(lg - dA * a * a);
-            Bq = (TC)(-2.0 * dB * a);
-            Cq = (TC)(-dC);
-        }
-        const TC u2 = cl.u2, ieps = cl.ieps;
-        TC Zy[NPT], base[NPT];
+        TC C[4];
+        ghat_cubic(R, a, C);
+        const Gq mq0 = maxw_q(R);
+        Gq gq = es_q(R);
+        const double iepsd = R[R_IEPS];
+        const TC u2 = cl.u2;
+        TC Zy[STASH ? 1 : NPT], base[STASH ? 1 : NPT];
         double acc[6] = {0, 0, 0, 0, 0, 0};
         {
-            [[maybe_unused]] Gq mq = mq0;
+            Gq mq = mq0;
 #pragma unroll
             for (int m = 0; m < NPT; ++m) {
                 const TC w = v2(m), w2 = w - u2;
-                Zy[m] = zy(m, lo, ce, hi);
-                TC M, es;
-                if constexpr (Q8) {
-                    M = mq.next();
-                    es = (gq.next() - M) * ieps;
+                const TC zv = zy(m, lo, ce, hi);
+                const double Md = mq.next();
+                const TC M = (TC)Md, es = (TC)((gq.next() - Md) * iepsd);
+                const TC bv = M * (((C[3] * w2 + C[2]) * w2 + C[1]) * w2 + C[0]) + es;
+                if constexpr (STASH) {
+                    st[m * 64 + lane] = zv;
+                    st[(NPT + m) * 64 + lane] = bv;
                 } else {
-                    M = maxw(t, E1, m);
-                    es = M * expm1f(A0 + (Bq + Cq * w2) * w2) * ieps;
+                    Zy[m] = zv;
+                    base[m] = bv;
                 }
-                base[m] = M * (((C3 * w2 + C2) * w2 + C1) * w2 + C0) + es;
                 const double vd = v2d(m);
-                const double z = (double)Zy[m], b = (double)base[m];
+                const double z = (double)zv, b = (double)bv;
                 const double uz = vd * z, ub = vd * b;
                 acc[0] += z;
                 acc[1] += uz;
@@ -371,17 +317,17 @@ struct PassLK {
         refresh();
         double h0 = 0.0, h1 = 0.0, h2 = 0.0, h3 = 0.0;
         const double u2d = cl.u2d;
-        [[maybe_unused]] Gq mq = mq0;
+        Gq mq = mq0;
 #pragma unroll
         for (int m = 0; m < NPT; ++m) {
             const TC w = v2(m);
-            TC M;
-            if constexpr (Q8) M = mq.next();
-            else M = maxw(t, E1, m);
+            const TC M = (TC)mq.next();
             const TC pz = (cz[3] * w + cz[2]) * w + Kz;
             const TC pb = (cb[3] * w + cb[2]) * w + Kb;
-            const TC gss = ce[m] + dt * (pz * M - Zy[m]);
-            const TC gh = base[m] - pb * M;
+            const TC zv = STASH ? st[m * 64 + lane] : Zy[STASH ? 0 : m];
+            const TC bv = STASH ? st[(NPT + m) * 64 + lane] : base[STASH ? 0 : m];
+            const TC gss = ce[m] + dt * (pz * M - zv);
+            const TC gh = bv - pb * M;
             const TS gn = (TS)(ra * gss + rb * gh);
             buf_store(gn, ws, off_c, NB * m);
             const double g = (double)gn, w2 = v2d(m) - u2d;
@@ -399,69 +345,40 @@ struct PassLK {
         }
     }
 
-    // y-sweep, G-hat (eqn5-97), relaxation and H for interior row j with window (lo, ce, hi)
-    __device__ __forceinline__ void finish_row_rc(size_t c, int jr, int slot, const TC (&lo)[NPT], const TC (&ce)[NPT],
-                                               const TC (&hi)[NPT], const Rec &R)
+    // The same with Zy and G-hat recomputed in the second loop instead of held
+    // (the register budget of the large FP32 instances)
+    __device__ __forceinline__ void finish_row_rc(size_t c, int jr, const TC (&lo)[NPT], const TC (&ce)[NPT],
+                                                  const TC (&hi)[NPT], const Rec &R)
     {
         Cell<TC> cl;
         load_cell(R, cl);
         const bool discrete = P->proj_mode == PROJ_DISCRETE;
-        const double *t = slot_tab(slot);
-        const TC E1 = (TC)t[k];
         const double a = v1d - cl.u1d;              // w1 of this lane
-        const double w2b = v2bd - cl.u2d;           // w2 at m = 0
-        // closed form of G-hat (eqn5-97) as a cubic in w2, times -1/tau
-        TC C0, C1, C2, C3;
-        {
-            const double i2T = R[R_I2T], iT = R[R_IT], itau = R[R_ITAU];
-            const double s11 = R[R_S11], s12 = R[R_S12], dTx = R[R_DTX], dTy = R[R_DTY];
-            const double q = a * a * i2T - 2.0;
-            C0 = (TC)(-itau * (s11 * a * a * i2T + iT * q * a * dTx));
-            C1 = (TC)(-itau * (2.0 * s12 * a * i2T + iT * q * dTy));
-            C2 = (TC)(-itau * (-s11 * i2T + iT * i2T * a * dTx));
-            C3 = (TC)(-itau * (iT * i2T * dTy));
-        }
-        // ES term: delta(m) = lg - (dA w1^2 + 2 dB w1 w2(m) + dC w2(m)^2)
-        const double dA = R[R_DA], dB = R[R_QB], dC = R[R_DC], lg = R[R_LG];
-        double r = 0.0, q = 0.0, kq = 0.0;
-        TC A0 = (TC)0, Bq = (TC)0, Cq = (TC)0;
-        if constexpr (sizeof(TC) == 8) {
-            const double d0 = lg - (dA * a * a + 2.0 * dB * a * w2b + dC * w2b * w2b);
-            const double d1 = -(2.0 * dB * a * hd + dC * (2.0 * w2b * hd + hd * hd));
-            r = exp(d0);
-            q = exp(d1);
-            kq = exp(-2.0 * dC * hd * hd);
-        } else {
-            A0 = (TC)(lg - dA * a * a);
-            Bq = (TC)(-2.0 * dB * a);
-            Cq = (TC)(-dC);
-        }
-        const TC u2 = cl.u2, ieps = cl.ieps;
-        const double r0 = r, q0 = q;
+        TC C[4];
+        ghat_cubic(R, a, C);
+        const Gq mq0 = maxw_q(R), gq0 = es_q(R);
+        const double iepsd = R[R_IEPS];
+        const TC u2 = cl.u2;
         double acc[6] = {0, 0, 0, 0, 0, 0};
+        {
+            Gq mq = mq0, gq = gq0;
 #pragma unroll
-        for (int m = 0; m < NPT; ++m) {
-            const TC w = v2(m), w2 = w - u2;
-            const TC zyv = zy(m, lo, ce, hi);
-            const TC M = maxw(t, E1, m);
-            TC es;
-            if constexpr (sizeof(TC) == 8) {
-                es = (TC)(r - 1.0) * M * ieps;
-                r *= q;
-                q *= kq;
-            } else {
-                es = M * expm1f(A0 + (Bq + Cq * w2) * w2) * ieps;
+            for (int m = 0; m < NPT; ++m) {
+                const TC w = v2(m), w2 = w - u2;
+                const TC zyv = zy(m, lo, ce, hi);
+                const double Md = mq.next();
+                const TC M = (TC)Md, es = (TC)((gq.next() - Md) * iepsd);
+                const TC basev = M * (((C[3] * w2 + C[2]) * w2 + C[1]) * w2 + C[0]) + es;
+                const double vd = v2d(m);
+                const double z = (double)zyv, b = (double)basev;
+                const double uz = vd * z, ub = vd * b;
+                acc[0] += z;
+                acc[1] += uz;
+                acc[2] += vd * uz;
+                acc[3] += b;
+                acc[4] += ub;
+                acc[5] += vd * ub;
             }
-            const TC basev = M * (((C3 * w2 + C2) * w2 + C1) * w2 + C0) + es;
-            const double vd = v2d(m);
-            const double z = (double)zyv, b = (double)basev;
-            const double uz = vd * z, ub = vd * b;
-            acc[0] += z;
-            acc[1] += uz;
-            acc[2] += vd * uz;
-            acc[3] += b;
-            acc[4] += ub;
-            acc[5] += vd * ub;
         }
         const double v1s = v1d * v1d;
         double s[8] = {acc[0], v1d * acc[0], acc[1], v1s * acc[0] + acc[2],
@@ -477,22 +394,14 @@ struct PassLK {
         const auto ws = row(Gn, jr);
         double h0 = 0.0, h1 = 0.0, h2 = 0.0, h3 = 0.0;
         const double u2d = cl.u2d;
-        r = r0;
-        q = q0;
+        Gq mq = mq0, gq = gq0;
 #pragma unroll
         for (int m = 0; m < NPT; ++m) {
             const TC w = v2(m), wc = w - u2;
-            const TC M = maxw(t, E1, m);
+            const double Md = mq.next();
+            const TC M = (TC)Md, es = (TC)((gq.next() - Md) * iepsd);
             const TC zyv = zy(m, lo, ce, hi);
-            TC es;
-            if constexpr (sizeof(TC) == 8) {
-                es = (TC)(r - 1.0) * M * ieps;
-                r *= q;
-                q *= kq;
-            } else {
-                es = M * expm1f(A0 + (Bq + Cq * wc) * wc) * ieps;
-            }
-            const TC basev = M * (((C3 * wc + C2) * wc + C1) * wc + C0) + es;
+            const TC basev = M * (((C[3] * wc + C[2]) * wc + C[1]) * wc + C[0]) + es;
             const TC pz = (cz[3] * w + cz[2]) * w + Kz;
             const TC pb = (cb[3] * w + cb[2]) * w + Kb;
             const TC gss = ce[m] + dt * (pz * M - zyv);
@@ -592,19 +501,19 @@ struct PassLK {
             if (!solve && !micro_row(j + 1) && !micro_row(j + 2)) return;
         }
         if (j + 1 < P->ny) {
-            if constexpr (RC) xsweep_rc(j + 1, (j + 1) & 1, win[HI], rec_at(j + 1, rv[HI]));
-            else xsweep(j + 1, (j + 1) & 1, win[HI], rec_at(j + 1, rv[HI]));
+            if constexpr (RC) xsweep_rc(j + 1, win[HI], rec_at(j + 1, rv[HI]));
+            else xsweep(j + 1, win[HI], rec_at(j + 1, rv[HI]));
         }
-        else if (P->bc[3].kind == BC_PERIODIC) xsweep(0, 2, win[HI], rec_at(0, rv[HI]));
+        else if (P->bc[3].kind == BC_PERIODIC) xsweep(0, win[HI], rec_at(0, rv[HI]));
         else ghost(P->bc[3].kind, win[CE], win[HI]);
         __builtin_amdgcn_sched_barrier(0);
         if (CL && !solve) return;
         refresh();
         const size_t c = (size_t)j * P->nx + i;
         const Rec R = rec_at(j, rv[CE]);
-        if (R[R_WALL] != 0.0) wall_row(c, j, j & 1, win[LO], win[CE], win[HI], R);
-        else if constexpr (RC) finish_row_rc(c, j, j & 1, win[LO], win[CE], win[HI], R);
-        else finish_row(c, j, j & 1, win[LO], win[CE], win[HI], R);
+        if (R[R_WALL] != 0.0) wall_row(j, win[LO], win[CE], win[HI], R);
+        else if constexpr (RC) finish_row_rc(c, j, win[LO], win[CE], win[HI], R);
+        else finish_row(c, j, win[LO], win[CE], win[HI], R);
         __builtin_amdgcn_sched_barrier(0);
     }
 };
@@ -635,16 +544,16 @@ __global__ __launch_bounds__(64 * WPG, (LKTraits<TC, NPT>::occupancy)) void k_fu
                                                             const uint8_t *__restrict__ cls)
 {
     const Params &P = *Pd;
-    __shared__ double s_tab[WPG][3 * 2 * MAXV];
     const int t = tile_of(blockIdx.x, geo.ntiles);
     if (t >= geo.ntiles) return;
     const int cg = t % geo.ncg, sg = t / geo.ncg;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform: cell indices live in SGPRs
     constexpr bool RC = LKTraits<TC, NPT>::recompute;
     PassLK<TS, TC, NPT, RC, CL> ps;
+    __shared__ TC s_st[PassLK<TS, TC, NPT, RC, CL>::STASH ? WPG * 2 * NPT * 64 : 1];
+    ps.st = s_st + (PassLK<TS, TC, NPT, RC, CL>::STASH ? wv * 2 * NPT * 64 : 0);
     ps.cls = cls;
     ps.G = G; ps.Gn = Gn; ps.H = H; ps.rec = rec; ps.wrec = wrec; ps.P = Pd;
-    ps.tab = s_tab[wv];
     ps.lane = threadIdx.x & 63;
     ps.i = cg * WPG + wv;
     if (ps.i >= P.nx) return;
@@ -697,10 +606,10 @@ __global__ __launch_bounds__(64 * WPG, (LKTraits<TC, NPT>::occupancy)) void k_fu
     ps.fetch_rec(j0 + 1, rv[2]);
     // closure form: the prologue rows are needed only for solved rows of the segment
     if (!CL || ps.micro_row(j0 - 1) || ps.micro_row(j0) || ps.micro_row(j0 + 1))
-        ps.xsweep(j0, j0 & 1, win[1], ps.rec_at(j0, rv[1]));
+        ps.xsweep(j0, win[1], ps.rec_at(j0, rv[1]));
     if (!CL || ps.micro_row(j0)) {
-        if (j0 > 0) ps.xsweep(j0 - 1, 2, win[0], ps.rec_at(j0 - 1, rv[0]));
-        else if (P.bc[2].kind == BC_PERIODIC) ps.xsweep(P.ny - 1, 2, win[0], ps.rec_at(P.ny - 1, rv[0]));
+        if (j0 > 0) ps.xsweep(j0 - 1, win[0], ps.rec_at(j0 - 1, rv[0]));
+        else if (P.bc[2].kind == BC_PERIODIC) ps.xsweep(P.ny - 1, win[0], ps.rec_at(P.ny - 1, rv[0]));
         else ps.ghost(P.bc[2].kind, win[1], win[0]);
     }
     // full rounds of three rows rotate the window back to its start; the tail

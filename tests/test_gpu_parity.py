@@ -82,6 +82,24 @@ def test_lane_k_2d(name, precision):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("name", ["lk_32x32_cavity", "lk_32x32_asym_v2"])
+def test_lane_k_2d_bitwise_repeatable(name, precision):
+    """Two runs of the same case give the same bits (every reduction in the
+    step has a fixed order, so any difference is a defect of the kernel)."""
+    from paper_2509_21832_amd import binding as B
+    p, Q, G = LANE_K[name]()
+    p["precision"] = precision
+    out = []
+    for _ in range(2):
+        with B.Solver(p, Q, G) as s:
+            s.step(25)
+            out.append((s.moments(), s.get_g()))
+    log(f"repeat {name} {precision}")
+    assert np.array_equal(out[0][0], out[1][0])
+    assert np.array_equal(out[0][1], out[1][1])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
 @pytest.mark.parametrize("name", ["lk_32x32_cavity", "lk_16x8_walls", "lk_4x64_inflow"])
 def test_generic_fused_on_lane_k_shapes(name, precision):
     """The generic fused kernel, forced where the lane-k kernel would run."""
