@@ -30,6 +30,20 @@ __device__ __forceinline__ void block_sum(double (&v)[N], double *lds)
     __syncthreads();
 }
 
+// Cell (i, j) of the r-th wall-adjacent cell of the ring: bottom row, top
+// row, then the left and right columns without their corners
+__device__ __forceinline__ void ring_cell(const Params &P, int r, int &i, int &j)
+{
+    if (r < P.nx) { i = r; j = 0; return; }
+    r -= P.nx;
+    if (r < P.nx) { i = r; j = P.ny - 1; return; }
+    r -= P.nx;
+    if (r < P.ny - 2) { i = 0; j = r + 1; return; }
+    r -= P.ny - 2;
+    i = P.nx - 1;
+    j = r + 1;
+}
+
 __device__ __forceinline__ double tau_of(const Params &P, double rho, double p, double T)
 {
     switch (P.tau_model) {

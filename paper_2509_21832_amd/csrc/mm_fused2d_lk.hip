@@ -646,6 +646,122 @@ bool launch_lk_t(int npt, const void *G, void *Gn, double *H, const double *rec,
 #undef MM_CASE
 }
 
+// Wall-adjacent cells in the lane-k layout (one wavefront per ring cell, the
+// node ownership of k_fused2d_lk).  The pass left G** of these cells in Gn; here
+// follow the wall form of G-hat (Sec. 6.3), -(1/tau)(I - Pi)[M_up] + (calG - M)/eps,
+// with M_up the upwind difference of the four neighbour (or ghost) Maxwellians,
+// then the relaxation (eqn5-98) and H (eqn5-99).  Every Gaussian follows the
+// exact recurrence of the pass along the lane's nodes; the sums are wavefront
+// sums, so there are no block barriers.
+struct GqW {
+    double e, r, k;
+    __device__ __forceinline__ double next()
+    {
+        const double v = e;
+        e *= r;
+        r *= k;
+        return v;
+    }
+};
+
+template <typename TS, int NPT>
+__global__ __launch_bounds__(256) void k_wall_lk(TS *__restrict__ Gn, double *__restrict__ H,
+                                                  const double *__restrict__ rec, const double *__restrict__ wrec,
+                                                  Params P, int nring)
+{
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int rr = blockIdx.x * 4 + wv;
+    if (rr >= nring) return;
+    int i, j;
+    ring_cell(P, rr, i, j);
+    const size_t c = (size_t)j * P.nx + i;
+    const double *R = rec + c * REC;
+    if (R[R_WALL] == 0.0) return;
+    const int lane = threadIdx.x & 63;
+    const int k = lane % P.nv1, L = 64 / P.nv1, l0 = lane / P.nv1;
+    const double v1 = P.v1_lo + (k + 0.5) * P.dv1, v2b = P.v2_lo + (l0 + 0.5) * P.dv2, h = L * P.dv2;
+    const double u1 = R[R_U1], u2 = R[R_U2], ieps = R[R_IEPS], itau = R[R_ITAU];
+    const bool es_on = P.wall_es_term != 0, discrete = P.proj_mode == PROJ_DISCRETE;
+    const double idx = 1.0 / P.dx, idy = 1.0 / P.dy;
+    auto maxw = [&](double pre, double cu1, double cu2, double ci2T, double kap) {
+        const double a = v1 - cu1, w = v2b - cu2;
+        return GqW{pre * exp(-(a * a + w * w) * ci2T), exp(-(2.0 * w + h) * h * ci2T), kap};
+    };
+    const GqW m0 = maxw(R[R_MPRE], u1, u2, R[R_I2T], R[R_KM]);
+    const double *nb = wrec + c * WREC;   // x-, x+, y-, y+: (rho / (2 pi T), u1, u2, 1 / (2T))
+    GqW mn[4];
+#pragma unroll
+    for (int d = 0; d < 4; ++d)
+        mn[d] = maxw(nb[4 * d], nb[4 * d + 1], nb[4 * d + 2], nb[4 * d + 3], exp(-2.0 * h * h * nb[4 * d + 3]));
+    GqW gq;
+    {
+        const double qa = R[R_QA], qb = R[R_QB], qc = R[R_QC], a = v1 - u1, w = v2b - u2;
+        gq = GqW{R[R_GPRE] * exp(-((qa * a + 2.0 * qb * w) * a + qc * w * w)),
+                 exp(-(2.0 * qb * a + qc * (2.0 * w + h)) * h), R[R_KG]};
+    }
+    const int bytes = P.nv * (int)sizeof(TS);
+    const auto rs = buf_rsrc(Gn + c * (size_t)P.nv, bytes);
+    const int off = lane * (int)sizeof(TS);
+    constexpr int NB = 64 * (int)sizeof(TS);
+    double g[NPT], mup[NPT], es[NPT];
+#pragma unroll
+    for (int m = 0; m < NPT; ++m) g[m] = (double)buf_load(rs, off, NB * m, (TS *)nullptr);
+    const double ax = fmin(v1, 0.0) * idx, bx = fmax(v1, 0.0) * idx;
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    {
+        GqW mq = m0;
+#pragma unroll
+        for (int m = 0; m < NPT; ++m) {
+            const double w = v2b + m * h;
+            const double M = mq.next(), M0 = mn[0].next(), M1 = mn[1].next(), M2 = mn[2].next(),
+                         M3 = mn[3].next();
+            mup[m] = (ax * (M1 - M) + bx * (M - M0)) + (fmin(w, 0.0) * (M3 - M) + fmax(w, 0.0) * (M - M2)) * idy;
+            es[m] = es_on ? (gq.next() - M) * ieps : 0.0;
+            const double uz = w * mup[m], ub = w * es[m];
+            acc[0] += mup[m];
+            acc[1] += uz;
+            acc[2] += w * uz;
+            acc[3] += es[m];
+            acc[4] += ub;
+            acc[5] += w * ub;
+        }
+    }
+    const double v1s = v1 * v1;
+    double s[8] = {acc[0], v1 * acc[0], acc[1], v1s * acc[0] + acc[2],
+                   acc[3], v1 * acc[3], acc[4], v1s * acc[3] + acc[5]};
+    wave_sum<8>(s, lane);
+    Cell<double> cl;
+    load_cell(RecP{R}, cl);
+    double cz[4], cb[4] = {0.0, 0.0, 0.0, 0.0};
+    proj_poly(cl, s, cz);
+    if (discrete) proj_poly(cl, s + 4, cb);
+    const double Kz = cz[0] + cz[1] * v1 + cz[3] * v1s, Kb = cb[0] + cb[1] * v1 + cb[3] * v1s;
+    const double ra = R[R_A], rb = R[R_B];
+    const double a = v1 - u1;
+    double h0 = 0.0, h1 = 0.0, h2 = 0.0, h3 = 0.0;
+    GqW mq = m0;
+#pragma unroll
+    for (int m = 0; m < NPT; ++m) {
+        const double w = v2b + m * h, M = mq.next();
+        const double pz = (cz[3] * w + cz[2]) * w + Kz, pb = (cb[3] * w + cb[2]) * w + Kb;
+        const double gh = -itau * (mup[m] - pz * M) + (es[m] - pb * M);
+        const TS gn = (TS)(ra * g[m] + rb * gh);
+        buf_store(gn, rs, off, NB * m);
+        const double gv = (double)gn, w2 = w - u2;
+        const double ug = gv * w2, ug2 = ug * w2;
+        h0 += gv;
+        h1 += ug;
+        h2 += ug2;
+        h3 += ug2 * w2;
+    }
+    double hs[4] = {a * a * a * h0, a * a * h1, a * h2, h3};
+    wave_sum<4>(hs, lane);
+    if (lane == 0) {
+        const double f = P.eps * P.dv1 * P.dv2;
+        for (int q = 0; q < 4; ++q) H[c * 4 + q] = f * hs[q];
+    }
+}
+
 } // namespace
 
 bool lk_supported(const Params &P)
@@ -657,6 +773,31 @@ bool lk_supported(const Params &P)
     // a row of cells of g is addressed with 32-bit byte offsets
     if ((long long)P.nx * P.nv * 8 >= (1LL << 31)) return false;
     return npt == 1 || npt == 2 || npt == 4 || npt == 8 || npt == 16;
+}
+
+bool launch_wall_lk2d(void *Gn, int g_bytes, double *H, const double *rec, const double *wrec, const Params &P,
+                      hipStream_t st)
+{
+    if (!lk_supported(P)) return false;
+    const int nring = 2 * P.nx + 2 * (P.ny - 2);
+    const dim3 grid((nring + 3) / 4), block(256);
+#define MM_CASE(N)                                                                                            \
+    case N:                                                                                                   \
+        if (g_bytes == 8)                                                                                     \
+            hipLaunchKernelGGL((k_wall_lk<double, N>), grid, block, 0, st, (double *)Gn, H, rec, wrec, P, nring); \
+        else                                                                                                  \
+            hipLaunchKernelGGL((k_wall_lk<float, N>), grid, block, 0, st, (float *)Gn, H, rec, wrec, P, nring);   \
+        return true;
+    switch (P.nv / 64) {
+        MM_CASE(1)
+        MM_CASE(2)
+        MM_CASE(4)
+        MM_CASE(8)
+        MM_CASE(16)
+    default:
+        return false;
+    }
+#undef MM_CASE
 }
 
 bool launch_micro_lk2d(const void *G, void *Gn, double *H, const double *rec, const double *wrec,

@@ -78,6 +78,27 @@ __device__ __forceinline__ void spd_inverse4(const double A[4][4], double scale,
         for (int b = a; b < 4; ++b) out[sym4(a, b)] = scale * 0.5 * (X[a][b] + X[b][a]);
 }
 
+// S[q] = sum_k w_k^q exp(-w_k^2 i2T), q = 0..4, over the nodes w_k = w0 + (k + 1/2) h,
+// k < n.  The Gaussian follows e(k+1) = e(k) r(k), r(k+1) = r(k) kappa (its
+// exponent is quadratic in k), restarted from a direct exponential every 8
+// nodes so the relative error stays within a few tens of ulps.
+__device__ inline void gauss_sums(double w0, double h, int n, double i2T, double S[5])
+{
+    const double kap = exp(-2.0 * h * h * i2T);
+    for (int k0 = 0; k0 < n; k0 += 8) {
+        const double wb = w0 + (k0 + 0.5) * h;
+        double e = exp(-wb * wb * i2T), r = exp(-(2.0 * wb + h) * h * i2T);
+        const int kn = n - k0 < 8 ? n - k0 : 8;
+        for (int k = 0; k < kn; ++k) {
+            const double w = wb + k * h;
+            double m = e;
+            for (int q = 0; q < 5; ++q) { S[q] += m; m *= w; }
+            e *= r;
+            r *= kap;
+        }
+    }
+}
+
 // One thread per cell.  The records of the block's cells are assembled in
 // LDS and written out together, so the stores are coalesced.
 constexpr int PREP_BLOCK = 64;
@@ -142,18 +163,8 @@ __global__ __launch_bounds__(PREP_BLOCK) void k_prep2d(const double *__restrict_
     } else {
         // Gram_ab = dA sum phi_a phi_b M from separable 1D sums: M = c0 e1(k) e2(l)
         double S1[5] = {0, 0, 0, 0, 0}, S2[5] = {0, 0, 0, 0, 0};
-        for (int k = 0; k < P.nv1; ++k) {
-            const double w = P.v1_lo + (k + 0.5) * P.dv1 - s.u1;
-            const double e = exp(-w * w / (2.0 * s.T));
-            double m = e;
-            for (int q = 0; q < 5; ++q) { S1[q] += m; m *= w; }
-        }
-        for (int l = 0; l < P.nv2; ++l) {
-            const double w = P.v2_lo + (l + 0.5) * P.dv2 - s.u2;
-            const double e = exp(-w * w / (2.0 * s.T));
-            double m = e;
-            for (int q = 0; q < 5; ++q) { S2[q] += m; m *= w; }
-        }
+        gauss_sums(P.v1_lo - s.u1, P.dv1, P.nv1, 1.0 / (2.0 * s.T), S1);
+        gauss_sums(P.v2_lo - s.u2, P.dv2, P.nv2, 1.0 / (2.0 * s.T), S2);
         auto mm = [&](int p, int q) { return S1[p] * S2[q]; };
         const double c0 = dA * s.rho / (2.0 * MM_PI * s.T);
         const double T = s.T, rT = sqrt(T);
@@ -206,6 +217,10 @@ __global__ __launch_bounds__(PREP_BLOCK) void k_prep2d(const double *__restrict_
             Wr[4 * d + 1] = g[1];
             Wr[4 * d + 2] = g[2];
             Wr[4 * d + 3] = 1.0 / (2.0 * g[3]);
+            // the wall kernel follows these Maxwellians along the velocity nodes too
+            if (!exp_range_ok(P.v1_lo, P.dv1, P.nv1, P.v2_lo, P.dv2, P.nv2, g[1], g[2], Wr[4 * d + 3],
+                              Wr[4 * d + 3], 0.0, Wr[4 * d + 3]))
+                atomicMin(flag, step);
         }
     }
     }
@@ -552,17 +567,6 @@ __global__ __launch_bounds__(256) void k_gmom2d(const TG *__restrict__ G, const 
 // (eqn5-99), in FP64 for both storage types.  One workgroup per cell of the
 // boundary ring; cells that are not wall cells return at once.
 
-__device__ __forceinline__ void ring_cell(const Params &P, int r, int &i, int &j)
-{
-    if (r < P.nx) { i = r; j = 0; return; }
-    r -= P.nx;
-    if (r < P.nx) { i = r; j = P.ny - 1; return; }
-    r -= P.nx;
-    if (r < P.ny - 2) { i = 0; j = r + 1; return; }
-    r -= P.ny - 2;
-    i = P.nx - 1;
-    j = r + 1;
-}
 
 // One workgroup per wall-adjacent cell.  The cell's Maxwellian and the four
 // neighbour (ghost) Maxwellians are separable: 1D factors of each go to LDS
@@ -692,6 +696,7 @@ void launch_wall_relax2d(void *Gn, int g_bytes, double *H, const double *rec, co
     bool any = false;
     for (int s = 0; s < 4; ++s) any = any || is_open(P.bc[s].kind);
     if (!any) return;
+    if (launch_wall_lk2d(Gn, g_bytes, H, rec, wrec, P, st)) return;
     const int n = 2 * P.nx + 2 * (P.ny - 2);
     if (P.nv1 > WALL_MAXV || P.nv2 > WALL_MAXV || P.nv > WALL_MAXNV) return;   // not a fused-pass shape
     if (g_bytes == 8)

@@ -14,6 +14,9 @@ void launch_gmom2d(const void *G, int g_bytes, const double *rec, double *out, c
 // wall-adjacent cells after a fused pass (Gn holds G** there)
 void launch_wall_relax2d(void *Gn, int g_bytes, double *H, const double *rec, const double *wrec, const Params &P,
                          hipStream_t st);
+// the same for velocity grids of the lane-k layout; false (nothing launched) otherwise
+bool launch_wall_lk2d(void *Gn, int g_bytes, double *H, const double *rec, const double *wrec, const Params &P,
+                      hipStream_t st);
 
 // fused phase-space pass; false when the shape is not supported.  Wall-adjacent
 // cells leave it holding G** and are finished by launch_wall_relax2d.
