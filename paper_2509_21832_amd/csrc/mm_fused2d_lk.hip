@@ -25,7 +25,7 @@ namespace {
 
 using namespace fused;
 
-template <typename TS, typename TC, int NPT, bool RC, bool CL>
+template <typename TS, typename TC, int NPT, bool CL>
 struct PassLK {
     // FP64: cell records are loaded rows ahead into VGPRs (one wavefront per SIMD
     // has the registers); FP32 keeps two wavefronts per SIMD and reads them in place
@@ -37,13 +37,14 @@ struct PassLK {
     const double *__restrict__ rec;
     const double *__restrict__ wrec;
     const Params *P;
-    // Large FP64 instances park Zy and G-hat of the row being finished in this
-    // wavefront's LDS slice between the two node loops instead of in registers
+    // Large FP64 instances park the local part of G^{n+1} of the row being
+    // finished in this wavefront's LDS slice between the two node loops instead
+    // of in registers
 #ifndef MM_LK_STASH
 #define MM_LK_STASH 1
 #endif
-    static constexpr bool STASH = MM_LK_STASH && sizeof(TC) == 8 && NPT >= 16 && !RC;
-    TC *st;                 // this wavefront's slice: [2][NPT][64]
+    static constexpr bool STASH = MM_LK_STASH && sizeof(TC) == 8 && NPT >= 16;
+    TC *st;                 // this wavefront's slice: [NPT][64]
     int lane, i, k, l0, L;
     int row_bytes;          // bytes of one row of cells of g
     int off_c, off_u;       // byte offsets in its row of this lane's value of cell i and of its upwind cell
@@ -143,67 +144,6 @@ struct PassLK {
         }
     }
 
-    // Same x-sweep in chunks of CH nodes without holding G and Z of the whole
-    // cell: the second pass reloads the chunk (L1/L2 hits) and recomputes Z.
-    static constexpr int CH = NPT < 8 ? NPT : 8;
-
-    __device__ __forceinline__ void load_chunk(__amdgpu_buffer_rsrc_t rs, int off, int m0, TC (&out)[CH]) const
-    {
-#pragma unroll
-        for (int m = 0; m < CH; ++m) out[m] = (TC)buf_load(rs, off, NB * (m0 + m), (TS *)nullptr);
-    }
-
-    __device__ __forceinline__ void zx_chunk(__amdgpu_buffer_rsrc_t rs, int m0, TC (&gc)[CH], TC (&Z)[CH]) const
-    {
-        TC gn[CH];
-        load_chunk(rs, off_c, m0, gc);
-        load_chunk(rs, off_u, m0, gn);
-        if (edge_col) {
-#pragma unroll
-            for (int m = 0; m < CH; ++m) gn[m] = zero_nb ? (TC)0 : gn[m];
-        }
-#pragma unroll
-        for (int m = 0; m < CH; ++m) Z[m] = cx * (gc[m] - gn[m]);
-    }
-
-    __device__ __forceinline__ void xsweep_rc(int r, TC (&out)[NPT], const Rec &R) const
-    {
-        const auto rs = row(G, r);
-        double t0 = 0.0, t2 = 0.0, t22 = 0.0;
-#pragma unroll
-        for (int m0 = 0; m0 < NPT; m0 += CH) {
-            TC gc[CH], Z[CH];
-            zx_chunk(rs, m0, gc, Z);
-#pragma unroll
-            for (int m = 0; m < CH; ++m) {
-                const double z = (double)Z[m], w = v2d(m0 + m), u = w * z;
-                t0 += z;
-                t2 += u;
-                t22 += w * u;
-            }
-        }
-        double s[4] = {t0, v1d * t0, t2, v1d * v1d * t0 + t22};
-        wave_sum<4>(s, lane);
-        Cell<TC> cl;
-        load_cell(R, cl);
-        TC cp[4];
-        proj_poly(cl, s, cp);
-        const TC K = cp[0] + cp[1] * v1 + cp[3] * v1 * v1;
-        const TC dt = (TC)P->dt;
-        Gq mq = maxw_q(R);
-#pragma unroll
-        for (int m0 = 0; m0 < NPT; m0 += CH) {
-            TC gc[CH], Z[CH];
-            zx_chunk(rs, m0, gc, Z);
-#pragma unroll
-            for (int m = 0; m < CH; ++m) {
-                const TC w = v2(m0 + m);
-                const TC pm = (cp[3] * w + cp[2]) * w + K;
-                out[m0 + m] = gc[m] + dt * (pm * (TC)mq.next() - Z[m]);
-            }
-        }
-    }
-
     // y-transport of node m: v2 (G(j) - G(j -/+ 1)) / dy upwind, written as
     // |v2| / dy (G(j) - G(upwind)) (the same value)
     __device__ __forceinline__ TC zy(int m, const TC (&lo)[NPT], const TC (&ce)[NPT], const TC (&hi)[NPT]) const
@@ -272,7 +212,11 @@ struct PassLK {
         Gq gq = es_q(R);
         const double iepsd = R[R_IEPS];
         const TC u2 = cl.u2;
-        TC Zy[STASH ? 1 : NPT], base[STASH ? 1 : NPT];
+        const TC dt = (TC)P->dt, ra = (TC)cl.ra, rb = (TC)cl.rb, radt = ra * dt;
+        // G^{n+1} = ra (ce + dt (pz M - Zy)) + rb (G-hat - pb M) regrouped as
+        // [ra ce - ra dt Zy + rb G-hat] + (ra dt pz - rb pb) M: the bracket is
+        // formed here, the projection part after the velocity sums
+        TC part[STASH ? 1 : NPT];
         double acc[6] = {0, 0, 0, 0, 0, 0};
         {
             Gq mq = mq0;
@@ -283,13 +227,9 @@ struct PassLK {
                 const double Md = mq.next();
                 const TC M = (TC)Md, es = (TC)((gq.next() - Md) * iepsd);
                 const TC bv = M * (((C[3] * w2 + C[2]) * w2 + C[1]) * w2 + C[0]) + es;
-                if constexpr (STASH) {
-                    st[m * 64 + lane] = zv;
-                    st[(NPT + m) * 64 + lane] = bv;
-                } else {
-                    Zy[m] = zv;
-                    base[m] = bv;
-                }
+                const TC pv = ra * ce[m] - radt * zv + rb * bv;
+                if constexpr (STASH) st[m * 64 + lane] = pv;
+                else part[m] = pv;
                 const double vd = v2d(m);
                 const double z = (double)zv, b = (double)bv;
                 const double uz = vd * z, ub = vd * b;
@@ -308,10 +248,10 @@ struct PassLK {
         TC cz[4], cb[4] = {(TC)0, (TC)0, (TC)0, (TC)0};
         proj_poly(cl, s, cz);
         if (discrete) proj_poly(cl, s + 4, cb);
+        // ra dt pz - rb pb as a quadratic in v2 at this lane's v1
         const TC vv = v1 * v1;
-        const TC Kz = cz[0] + cz[1] * v1 + cz[3] * vv;
-        const TC Kb = cb[0] + cb[1] * v1 + cb[3] * vv;
-        const TC dt = (TC)P->dt, ra = (TC)cl.ra, rb = (TC)cl.rb;
+        const TC q3 = radt * cz[3] - rb * cb[3], q2 = radt * cz[2] - rb * cb[2];
+        const TC q0 = radt * (cz[0] + cz[1] * v1 + cz[3] * vv) - rb * (cb[0] + cb[1] * v1 + cb[3] * vv);
         const auto ws = row(Gn, jr);
         // recompute the node values below rather than hold all NPT of them from the first loop
         refresh();
@@ -322,91 +262,8 @@ struct PassLK {
         for (int m = 0; m < NPT; ++m) {
             const TC w = v2(m);
             const TC M = (TC)mq.next();
-            const TC pz = (cz[3] * w + cz[2]) * w + Kz;
-            const TC pb = (cb[3] * w + cb[2]) * w + Kb;
-            const TC zv = STASH ? st[m * 64 + lane] : Zy[STASH ? 0 : m];
-            const TC bv = STASH ? st[(NPT + m) * 64 + lane] : base[STASH ? 0 : m];
-            const TC gss = ce[m] + dt * (pz * M - zv);
-            const TC gh = bv - pb * M;
-            const TS gn = (TS)(ra * gss + rb * gh);
-            buf_store(gn, ws, off_c, NB * m);
-            const double g = (double)gn, w2 = v2d(m) - u2d;
-            const double ug = g * w2, ug2 = ug * w2;
-            h0 += g;
-            h1 += ug;
-            h2 += ug2;
-            h3 += ug2 * w2;
-        }
-        double hs[4] = {a * a * a * h0, a * a * h1, a * h2, h3};
-        wave_sum<4>(hs, lane);
-        if (lane == 0) {
-            const double f = P->eps * P->dv1 * P->dv2;
-            for (int qq = 0; qq < 4; ++qq) H[c * 4 + qq] = f * hs[qq];
-        }
-    }
-
-    // The same with Zy and G-hat recomputed in the second loop instead of held
-    // (the register budget of the large FP32 instances)
-    __device__ __forceinline__ void finish_row_rc(size_t c, int jr, const TC (&lo)[NPT], const TC (&ce)[NPT],
-                                                  const TC (&hi)[NPT], const Rec &R)
-    {
-        Cell<TC> cl;
-        load_cell(R, cl);
-        const bool discrete = P->proj_mode == PROJ_DISCRETE;
-        const double a = v1d - cl.u1d;              // w1 of this lane
-        TC C[4];
-        ghat_cubic(R, a, C);
-        const Gq mq0 = maxw_q(R), gq0 = es_q(R);
-        const double iepsd = R[R_IEPS];
-        const TC u2 = cl.u2;
-        double acc[6] = {0, 0, 0, 0, 0, 0};
-        {
-            Gq mq = mq0, gq = gq0;
-#pragma unroll
-            for (int m = 0; m < NPT; ++m) {
-                const TC w = v2(m), w2 = w - u2;
-                const TC zyv = zy(m, lo, ce, hi);
-                const double Md = mq.next();
-                const TC M = (TC)Md, es = (TC)((gq.next() - Md) * iepsd);
-                const TC basev = M * (((C[3] * w2 + C[2]) * w2 + C[1]) * w2 + C[0]) + es;
-                const double vd = v2d(m);
-                const double z = (double)zyv, b = (double)basev;
-                const double uz = vd * z, ub = vd * b;
-                acc[0] += z;
-                acc[1] += uz;
-                acc[2] += vd * uz;
-                acc[3] += b;
-                acc[4] += ub;
-                acc[5] += vd * ub;
-            }
-        }
-        const double v1s = v1d * v1d;
-        double s[8] = {acc[0], v1d * acc[0], acc[1], v1s * acc[0] + acc[2],
-                       acc[3], v1d * acc[3], acc[4], v1s * acc[3] + acc[5]};
-        wave_sum<8>(s, lane);
-        TC cz[4], cb[4] = {(TC)0, (TC)0, (TC)0, (TC)0};
-        proj_poly(cl, s, cz);
-        if (discrete) proj_poly(cl, s + 4, cb);
-        const TC vv = v1 * v1;
-        const TC Kz = cz[0] + cz[1] * v1 + cz[3] * vv;
-        const TC Kb = cb[0] + cb[1] * v1 + cb[3] * vv;
-        const TC dt = (TC)P->dt, ra = (TC)cl.ra, rb = (TC)cl.rb;
-        const auto ws = row(Gn, jr);
-        double h0 = 0.0, h1 = 0.0, h2 = 0.0, h3 = 0.0;
-        const double u2d = cl.u2d;
-        Gq mq = mq0, gq = gq0;
-#pragma unroll
-        for (int m = 0; m < NPT; ++m) {
-            const TC w = v2(m), wc = w - u2;
-            const double Md = mq.next();
-            const TC M = (TC)Md, es = (TC)((gq.next() - Md) * iepsd);
-            const TC zyv = zy(m, lo, ce, hi);
-            const TC basev = M * (((C[3] * wc + C[2]) * wc + C[1]) * wc + C[0]) + es;
-            const TC pz = (cz[3] * w + cz[2]) * w + Kz;
-            const TC pb = (cb[3] * w + cb[2]) * w + Kb;
-            const TC gss = ce[m] + dt * (pz * M - zyv);
-            const TC gh = basev - pb * M;
-            const TS gn = (TS)(ra * gss + rb * gh);
+            const TC pv = STASH ? st[m * 64 + lane] : part[STASH ? 0 : m];
+            const TS gn = (TS)(((q3 * w + q2) * w + q0) * M + pv);
             buf_store(gn, ws, off_c, NB * m);
             const double g = (double)gn, w2 = v2d(m) - u2d;
             const double ug = g * w2, ug2 = ug * w2;
@@ -501,8 +358,7 @@ struct PassLK {
             if (!solve && !micro_row(j + 1) && !micro_row(j + 2)) return;
         }
         if (j + 1 < P->ny) {
-            if constexpr (RC) xsweep_rc(j + 1, win[HI], rec_at(j + 1, rv[HI]));
-            else xsweep(j + 1, win[HI], rec_at(j + 1, rv[HI]));
+            xsweep(j + 1, win[HI], rec_at(j + 1, rv[HI]));
         }
         else if (P->bc[3].kind == BC_PERIODIC) xsweep(0, win[HI], rec_at(0, rv[HI]));
         else ghost(P->bc[3].kind, win[CE], win[HI]);
@@ -512,28 +368,21 @@ struct PassLK {
         const size_t c = (size_t)j * P->nx + i;
         const Rec R = rec_at(j, rv[CE]);
         if (R[R_WALL] != 0.0) wall_row(j, win[LO], win[CE], win[HI], R);
-        else if constexpr (RC) finish_row_rc(c, j, win[LO], win[CE], win[HI], R);
         else finish_row(c, j, win[LO], win[CE], win[HI], R);
         __builtin_amdgcn_sched_barrier(0);
     }
 };
 
-// Register budget of the large instances (64 B or more of G per lane): in FP64
-// the per-node temporaries stay in registers and one wavefront runs per SIMD;
-// in FP32 the x-sweep and the finish run in chunks that recompute per-node
-// temporaries, which keeps two wavefronts per SIMD (the faster choice for each
-// precision on gfx950).
-#ifndef MM_LK_BIG_BYTES
-#define MM_LK_BIG_BYTES 64
-#endif
+// Occupancy: the FP64 instance with 16 nodes per lane (128 B of G per lane)
+// runs one wavefront per SIMD (measured faster than two); every other instance
+// fits two wavefronts per SIMD.
 #ifndef MM_LK_OCC64
 #define MM_LK_OCC64 1
 #endif
 template <typename TC, int NPT>
 struct LKTraits {
-    static constexpr bool big = sizeof(TC) * NPT >= MM_LK_BIG_BYTES;
-    static constexpr bool recompute = big && sizeof(TC) == 4;
-    static constexpr int occupancy = big && !recompute ? MM_LK_OCC64 : 2;
+    static constexpr bool big = sizeof(TC) * NPT >= 128;
+    static constexpr int occupancy = big ? MM_LK_OCC64 : 2;
 };
 
 template <typename TS, typename TC, int NPT, bool CL>
@@ -548,10 +397,10 @@ __global__ __launch_bounds__(64 * WPG, (LKTraits<TC, NPT>::occupancy)) void k_fu
     if (t >= geo.ntiles) return;
     const int cg = t % geo.ncg, sg = t / geo.ncg;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform: cell indices live in SGPRs
-    constexpr bool RC = LKTraits<TC, NPT>::recompute;
-    PassLK<TS, TC, NPT, RC, CL> ps;
-    __shared__ TC s_st[PassLK<TS, TC, NPT, RC, CL>::STASH ? WPG * 2 * NPT * 64 : 1];
-    ps.st = s_st + (PassLK<TS, TC, NPT, RC, CL>::STASH ? wv * 2 * NPT * 64 : 0);
+    using Pass = PassLK<TS, TC, NPT, CL>;
+    Pass ps;
+    __shared__ TC s_st[Pass::STASH ? WPG * NPT * 64 : 1];
+    ps.st = s_st + (Pass::STASH ? wv * NPT * 64 : 0);
     ps.cls = cls;
     ps.G = G; ps.Gn = Gn; ps.H = H; ps.rec = rec; ps.wrec = wrec; ps.P = Pd;
     ps.lane = threadIdx.x & 63;
@@ -600,7 +449,7 @@ __global__ __launch_bounds__(64 * WPG, (LKTraits<TC, NPT>::occupancy)) void k_fu
     }
     TC win[3][NPT];
     // records of the window rows j0 - 1, j0, j0 + 1 (slots 0, 1, 2)
-    typename PassLK<TS, TC, NPT, RC, CL>::Rec rv[3] = {};
+    typename Pass::Rec rv[3] = {};
     ps.fetch_rec(j0 - 1, rv[0]);
     ps.fetch_rec(j0, rv[1]);
     ps.fetch_rec(j0 + 1, rv[2]);
@@ -805,7 +654,7 @@ bool launch_micro_lk2d(const void *G, void *Gn, double *H, const double *rec, co
 {
     if (!lk_supported(P)) return false;
     const int npt = P.nv / 64;
-    const bool one_wave = precision == 0 && 8 * npt >= MM_LK_BIG_BYTES && MM_LK_OCC64 == 1;
+    const bool one_wave = precision == 0 && 8 * npt >= 128 && MM_LK_OCC64 == 1;
     const Geom geo = geometry(P, one_wave ? 1 : 2);
     if (cls) {   // closure form: g in FP32 only
         // the solved cells cluster along the walls: short row segments spread a
