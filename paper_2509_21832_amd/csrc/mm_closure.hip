@@ -753,6 +753,7 @@ __global__ void k_need2d(const uint8_t *__restrict__ cls, const uint8_t *__restr
 {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= P.nx * P.ny) return;
+    const int lane = threadIdx.x & 63;
     const int i = c % P.nx, j = c / P.nx;
     const bool px = P.bc[0].kind == BC_PERIODIC, py = P.bc[2].kind == BC_PERIODIC;
     bool need = false;
@@ -773,7 +774,17 @@ __global__ void k_need2d(const uint8_t *__restrict__ cls, const uint8_t *__restr
             if (in && cls[jj * P.nx + ii]) need = true;
         }
     valid_next[c] = cls[c];
-    if (need && !valid[c]) list[atomicAdd(nrebuild, 1)] = c;
+    // one atomic per wavefront: the first listed lane reserves the wavefront's
+    // slots, each lane takes its rank among the listed lanes
+    const bool add = need && !valid[c];
+    const uint64_t m = __ballot(add);
+    if (m) {
+        const int lead = __ffsll((unsigned long long)m) - 1;
+        int base = 0;
+        if (lane == lead) base = atomicAdd(nrebuild, __popcll(m));
+        base = __shfl(base, lead, 64);
+        if (add) list[base + __popcll(m & ((1ull << lane) - 1))] = c;
+    }
 }
 
 // Rebuild the listed cells from their (q, S) / eps:
@@ -800,8 +811,50 @@ __global__ __launch_bounds__(256) void k_rebuild2d(TS *__restrict__ G, const dou
         const double tr = 0.5 * ((double)o[2] + o[4]);
         const double a11 = o[2] - tr, a12 = o[3], a22 = o[4] - tr;
         const double pre = 1.0 / (2.0 * p * T);
-        // raw values and their (1, v1, v2, |v|^2) sums
         double s[4] = {0.0, 0.0, 0.0, 0.0};
+        if (lk_step(P.nv1, P.nv2, P.dv2) > 0.0) {
+            // lane-k layout: lane (k, l0) owns the nodes (k, l0 + L m); the Maxwellian
+            // follows e(m+1) = e(m) r(m), r(m+1) = r(m) kappa along them
+            const int L = 64 / P.nv1, k = lane % P.nv1, l0 = lane / P.nv1, npt = P.nv / 64;
+            const double i2T = R[R_I2T], h = L * P.dv2;
+            const double v1 = P.v1_lo + (k + 0.5) * P.dv1, v2b = P.v2_lo + (l0 + 0.5) * P.dv2;
+            const double w1 = v1 - cl.u1d, w2b = v2b - cl.u2d;
+            const double e0 = R[R_MPRE] * exp(-(w1 * w1 + w2b * w2b) * i2T);
+            const double r0 = exp(-(2.0 * w2b + h) * h * i2T), kap = R[R_KM];
+            const double b0 = pre * a11 * w1 * w1, b1 = pre * 2.0 * a12 * w1, b2 = pre * a22, bq = pre * q1 * w1;
+            auto gval = [&](double w2, double M) {
+                const double ww = w1 * w1 + w2 * w2;
+                return M * (b0 + (b1 + b2 * w2) * w2 + (bq + pre * q2 * w2) * (ww * i2T - 2.0));
+            };
+            double e = e0, r = r0;
+            for (int m = 0; m < npt; ++m) {
+                const double v2 = v2b + m * h, g = gval(v2 - cl.u2d, e);
+                e *= r;
+                r *= kap;
+                s[0] += g;
+                s[1] += v1 * g;
+                s[2] += v2 * g;
+                s[3] += (v1 * v1 + v2 * v2) * g;
+            }
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+                for (int a = 0; a < 4; ++a) s[a] += __shfl_xor(s[a], off, 64);
+            double cp[4];
+            fused::proj_poly(cl, s, cp);
+            TS *gout = G + (size_t)c * P.nv;
+            e = e0;
+            r = r0;
+            for (int m = 0; m < npt; ++m) {
+                const double v2 = v2b + m * h, g = gval(v2 - cl.u2d, e);
+                const double pg = (cp[0] + cp[1] * v1 + cp[2] * v2 + cp[3] * (v1 * v1 + v2 * v2)) * e;
+                e *= r;
+                r *= kap;
+                gout[lane + 64 * m] = (TS)(g - pg);
+            }
+            continue;
+        }
+        // raw values and their (1, v1, v2, |v|^2) sums
         for (int n = lane; n < P.nv; n += 64) {
             const int k = n % P.nv1, l = n / P.nv1;
             const double v1 = P.v1_lo + (k + 0.5) * P.dv1, v2 = P.v2_lo + (l + 0.5) * P.dv2;
