@@ -99,135 +99,163 @@ __device__ inline void gauss_sums(double w0, double h, int n, double i2T, double
     }
 }
 
-// One thread per cell.  The records of the block's cells are assembled in
-// LDS and written out together, so the stores are coalesced.
-constexpr int PREP_BLOCK = 64;
+// Four wavefronts per block of 64 cells, each assembling part of every cell's
+// record (one cell per lane; the per-cell work is a long chain of dependent FP64
+// operations: split four ways it is shorter, and four times as many wavefronts
+// hide each other's latency):
+//   wavefront 0: primitives, ES tensor and its Gaussian form, validity and range checks
+//   wavefront 1: tau, relaxation weights, Maxwellian scalars, v2 Gram sums
+//   wavefront 2: v1 Gram sums, the projection matrix (with wavefront 1's sums)
+//   wavefront 3: central differences from the four neighbours, wall neighbour Maxwellians
+// The records of the block's cells are assembled in LDS and written out together,
+// so the stores are coalesced.
+constexpr int PREP_CELLS = 64;
 
-__global__ __launch_bounds__(PREP_BLOCK) void k_prep2d(const double *__restrict__ Q, double *__restrict__ rec,
-                                                       double *__restrict__ wrec, int *__restrict__ flag, int step,
-                                                       Params P)
+__global__ __launch_bounds__(4 * PREP_CELLS) void k_prep2d(const double *__restrict__ Q, double *__restrict__ rec,
+                                                           double *__restrict__ wrec, int *__restrict__ flag,
+                                                           int step, Params P)
 {
-    __shared__ double s_rec[PREP_BLOCK * REC];
+    __shared__ double s_rec[PREP_CELLS * REC];
+    __shared__ double s_s2[5][PREP_CELLS];
     const int ncell = P.nx * P.ny;
-    const int c0 = blockIdx.x * PREP_BLOCK;
-    const int c = c0 + threadIdx.x;
-    double *R = s_rec + threadIdx.x * REC;
+    const int c0 = blockIdx.x * PREP_CELLS;
+    const int cl = threadIdx.x & 63;
+    const int role = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int c = c0 + cl;
+    double *R = s_rec + cl * REC;
+    const bool discrete = P.proj_mode != PROJ_PAPER;
     if (c < ncell) {
-    const int i = c % P.nx, j = c / P.nx;
-    const CellPrim s = prim_of(Q + 6 * (size_t)c);
-    for (int q = R_KG + 1; q < REC; ++q) R[q] = 0.0;     // unused tail of the record
-
-    const double tau = tau_of(P, s.rho, s.p, s.T);
-    const double S11 = (1.0 - P.nu) * s.T + P.nu * s.P11 / s.rho;
-    const double S12 = P.nu * s.P12 / s.rho;
-    const double S22 = (1.0 - P.nu) * s.T + P.nu * s.P22 / s.rho;
-    const double det = S11 * S22 - S12 * S12;
-    if (!(s.rho > 0.0) || !(s.T > 0.0) || !(det > 0.0) || !(s.P11 > 0.0) || !(s.P22 > 0.0) ||
-        !isfinite(s.u1) || !isfinite(s.u2) || !isfinite(s.P12))
-        atomicMin(flag, step);
-
-    R[R_RHO] = s.rho;
-    R[R_U1] = s.u1;
-    R[R_U2] = s.u2;
-    R[R_T] = s.T;
-    R[R_RST] = 1.0 / sqrt(s.T);
-    R[R_MPRE] = s.rho / (2.0 * MM_PI * s.T);
-    R[R_I2T] = 1.0 / (2.0 * s.T);
-    R[R_TAU] = tau;
-    R[R_ITAU] = 1.0 / tau;
-    R[R_IEPS] = 1.0 / P.eps;
-    R[R_A] = P.eps / (P.eps + P.dt * tau);
-    R[R_B] = P.dt * tau / (P.eps + P.dt * tau);
-    R[R_GPRE] = s.rho / (2.0 * MM_PI * sqrt(det));
-    R[R_QA] = S22 / (2.0 * det);
-    R[R_QB] = -S12 / (2.0 * det);
-    R[R_QC] = S11 / (2.0 * det);
-    R[R_IT] = 1.0 / s.T;
-    R[R_LG] = log(s.T / sqrt(det));
-    R[R_DA] = R[R_QA] - R[R_I2T];
-    R[R_DC] = R[R_QC] - R[R_I2T];
-    {
+        const int i = c % P.nx, j = c / P.nx;
+        const CellPrim s = prim_of(Q + 6 * (size_t)c);
+        const double i2T = 1.0 / (2.0 * s.T);
         const double h = lk_step(P.nv1, P.nv2, P.dv2);
-        R[R_KM] = exp(-2.0 * h * h * R[R_I2T]);
-        R[R_KG] = exp(-2.0 * R[R_QC] * h * h);
-    }
-    if (!exp_range_ok(P.v1_lo, P.dv1, P.nv1, P.v2_lo, P.dv2, P.nv2, s.u1, s.u2, R[R_I2T], R[R_QA], R[R_QB],
-                      R[R_QC]))
-        atomicMin(flag, step);
-
-    // projection coefficients
-    const double dA = P.dv1 * P.dv2;
-    if (P.proj_mode == PROJ_PAPER) {
-        for (int a = 0; a < 4; ++a)
-            for (int b = a; b < 4; ++b) R[R_P0 + sym4(a, b)] = a == b ? dA / s.rho : 0.0;
-    } else {
-        // Gram_ab = dA sum phi_a phi_b M from separable 1D sums: M = c0 e1(k) e2(l)
-        double S1[5] = {0, 0, 0, 0, 0}, S2[5] = {0, 0, 0, 0, 0};
-        gauss_sums(P.v1_lo - s.u1, P.dv1, P.nv1, 1.0 / (2.0 * s.T), S1);
-        gauss_sums(P.v2_lo - s.u2, P.dv2, P.nv2, 1.0 / (2.0 * s.T), S2);
-        auto mm = [&](int p, int q) { return S1[p] * S2[q]; };
-        const double c0 = dA * s.rho / (2.0 * MM_PI * s.T);
-        const double T = s.T, rT = sqrt(T);
-        double A[4][4];
-        A[0][0] = c0 * mm(0, 0);
-        A[0][1] = c0 * mm(1, 0) / rT;
-        A[0][2] = c0 * mm(0, 1) / rT;
-        A[0][3] = c0 * ((mm(2, 0) + mm(0, 2)) / (2.0 * T) - mm(0, 0));
-        A[1][1] = c0 * mm(2, 0) / T;
-        A[1][2] = c0 * mm(1, 1) / T;
-        A[1][3] = c0 * ((mm(3, 0) + mm(1, 2)) / (2.0 * T) - mm(1, 0)) / rT;
-        A[2][2] = c0 * mm(0, 2) / T;
-        A[2][3] = c0 * ((mm(2, 1) + mm(0, 3)) / (2.0 * T) - mm(0, 1)) / rT;
-        A[3][3] = c0 * ((mm(4, 0) + 2.0 * mm(2, 2) + mm(0, 4)) / (4.0 * T * T) - (mm(2, 0) + mm(0, 2)) / T + mm(0, 0));
-        for (int a = 0; a < 4; ++a)
-            for (int b = 0; b < a; ++b) A[a][b] = A[b][a];
-        spd_inverse4(A, dA, R + R_P0);
-    }
-
-    // central differences of u and T (eqn5-97, eqn5-97more) with boundary ghosts
-    const CellPrim xm = prim_of(Q + 6 * (size_t)nbr_cell(P, i, j, 0, 0));
-    const CellPrim xp = prim_of(Q + 6 * (size_t)nbr_cell(P, i, j, 0, 1));
-    const CellPrim ym = prim_of(Q + 6 * (size_t)nbr_cell(P, i, j, 1, 0));
-    const CellPrim yp = prim_of(Q + 6 * (size_t)nbr_cell(P, i, j, 1, 1));
-    const double Tip = 0.5 * (xp.T + s.T), Tim = 0.5 * (xm.T + s.T);
-    const double Tjp = 0.5 * (yp.T + s.T), Tjm = 0.5 * (ym.T + s.T);
-    R[R_DTX] = (Tip - Tim) / P.dx;
-    R[R_DTY] = (Tjp - Tjm) / P.dy;
-    const double Dxu1 = 0.5 * (xp.u1 - xm.u1), Dxu2 = 0.5 * (xp.u2 - xm.u2);
-    const double Dyu1 = 0.5 * (yp.u1 - ym.u1), Dyu2 = 0.5 * (yp.u2 - ym.u2);
-    R[R_S11] = Dxu1 / P.dx - Dyu2 / P.dy;
-    R[R_S12] = Dyu1 / P.dy + Dxu2 / P.dx;
-
-    const bool wall = wall_cell(P, i, j);
-    R[R_WALL] = wall ? 1.0 : 0.0;
-    if (wall) {
-        double *Wr = wrec + (size_t)c * WREC;
-        const CellPrim *nb[4] = {&xm, &xp, &ym, &yp};
-        for (int d = 0; d < 4; ++d) {
-            const int dir = d / 2, up = d % 2;
-            const bool inside = dir == 0 ? (up ? i < P.nx - 1 : i > 0) : (up ? j < P.ny - 1 : j > 0);
-            const int side = dir == 0 ? (up ? 1 : 0) : (up ? 3 : 2);
-            double g[4];
-            if (!inside && is_open(P.bc[side].kind)) {
-                side_ghost(P.bc[side], side, s.rho, s.u1, s.u2, side < 2 ? s.P11 / s.rho : s.P22 / s.rho, g);
-            } else {
-                g[0] = nb[d]->rho; g[1] = nb[d]->u1; g[2] = nb[d]->u2; g[3] = nb[d]->T;
-            }
-            Wr[4 * d + 0] = g[0] / (2.0 * MM_PI * g[3]);
-            Wr[4 * d + 1] = g[1];
-            Wr[4 * d + 2] = g[2];
-            Wr[4 * d + 3] = 1.0 / (2.0 * g[3]);
-            // the wall kernel follows these Maxwellians along the velocity nodes too
-            if (!exp_range_ok(P.v1_lo, P.dv1, P.nv1, P.v2_lo, P.dv2, P.nv2, g[1], g[2], Wr[4 * d + 3],
-                              Wr[4 * d + 3], 0.0, Wr[4 * d + 3]))
+        if (role == 0) {
+            const double S11 = (1.0 - P.nu) * s.T + P.nu * s.P11 / s.rho;
+            const double S12 = P.nu * s.P12 / s.rho;
+            const double S22 = (1.0 - P.nu) * s.T + P.nu * s.P22 / s.rho;
+            const double det = S11 * S22 - S12 * S12;
+            if (!(s.rho > 0.0) || !(s.T > 0.0) || !(det > 0.0) || !(s.P11 > 0.0) || !(s.P22 > 0.0) ||
+                !isfinite(s.u1) || !isfinite(s.u2) || !isfinite(s.P12))
                 atomicMin(flag, step);
+            R[R_RHO] = s.rho;
+            R[R_U1] = s.u1;
+            R[R_U2] = s.u2;
+            R[R_T] = s.T;
+            R[R_GPRE] = s.rho / (2.0 * MM_PI * sqrt(det));
+            const double qa = S22 / (2.0 * det), qb = -S12 / (2.0 * det), qc = S11 / (2.0 * det);
+            R[R_QA] = qa;
+            R[R_QB] = qb;
+            R[R_QC] = qc;
+            R[R_LG] = log(s.T / sqrt(det));
+            R[R_DA] = qa - i2T;
+            R[R_DC] = qc - i2T;
+            R[R_KG] = exp(-2.0 * qc * h * h);
+            if (!exp_range_ok(P.v1_lo, P.dv1, P.nv1, P.v2_lo, P.dv2, P.nv2, s.u1, s.u2, i2T, qa, qb, qc))
+                atomicMin(flag, step);
+        } else if (role == 1) {
+            for (int q = R_KG + 1; q < REC; ++q) R[q] = 0.0;     // unused tail of the record
+            const double tau = tau_of(P, s.rho, s.p, s.T);
+            R[R_RST] = 1.0 / sqrt(s.T);
+            R[R_MPRE] = s.rho / (2.0 * MM_PI * s.T);
+            R[R_I2T] = i2T;
+            R[R_TAU] = tau;
+            R[R_ITAU] = 1.0 / tau;
+            R[R_IEPS] = 1.0 / P.eps;
+            R[R_A] = P.eps / (P.eps + P.dt * tau);
+            R[R_B] = P.dt * tau / (P.eps + P.dt * tau);
+            R[R_IT] = 1.0 / s.T;
+            R[R_KM] = exp(-2.0 * h * h * i2T);
+            // Gram_ab = dA sum phi_a phi_b M from separable 1D sums: M = c0 e1(k) e2(l)
+            if (discrete) {
+                double S2[5] = {0, 0, 0, 0, 0};
+                gauss_sums(P.v2_lo - s.u2, P.dv2, P.nv2, i2T, S2);
+                for (int q = 0; q < 5; ++q) s_s2[q][cl] = S2[q];
+            }
+        } else if (role == 3) {
+            // central differences of u and T (eqn5-97, eqn5-97more) with boundary ghosts
+            const CellPrim xm = prim_of(Q + 6 * (size_t)nbr_cell(P, i, j, 0, 0));
+            const CellPrim xp = prim_of(Q + 6 * (size_t)nbr_cell(P, i, j, 0, 1));
+            const CellPrim ym = prim_of(Q + 6 * (size_t)nbr_cell(P, i, j, 1, 0));
+            const CellPrim yp = prim_of(Q + 6 * (size_t)nbr_cell(P, i, j, 1, 1));
+            const double Tip = 0.5 * (xp.T + s.T), Tim = 0.5 * (xm.T + s.T);
+            const double Tjp = 0.5 * (yp.T + s.T), Tjm = 0.5 * (ym.T + s.T);
+            R[R_DTX] = (Tip - Tim) / P.dx;
+            R[R_DTY] = (Tjp - Tjm) / P.dy;
+            const double Dxu1 = 0.5 * (xp.u1 - xm.u1), Dxu2 = 0.5 * (xp.u2 - xm.u2);
+            const double Dyu1 = 0.5 * (yp.u1 - ym.u1), Dyu2 = 0.5 * (yp.u2 - ym.u2);
+            R[R_S11] = Dxu1 / P.dx - Dyu2 / P.dy;
+            R[R_S12] = Dyu1 / P.dy + Dxu2 / P.dx;
+
+            const bool wall = wall_cell(P, i, j);
+            R[R_WALL] = wall ? 1.0 : 0.0;
+            if (wall) {
+                double *Wr = wrec + (size_t)c * WREC;
+                const CellPrim *nb[4] = {&xm, &xp, &ym, &yp};
+                for (int d = 0; d < 4; ++d) {
+                    const int dir = d / 2, up = d % 2;
+                    const bool inside = dir == 0 ? (up ? i < P.nx - 1 : i > 0) : (up ? j < P.ny - 1 : j > 0);
+                    const int side = dir == 0 ? (up ? 1 : 0) : (up ? 3 : 2);
+                    double g[4];
+                    if (!inside && is_open(P.bc[side].kind)) {
+                        side_ghost(P.bc[side], side, s.rho, s.u1, s.u2, side < 2 ? s.P11 / s.rho : s.P22 / s.rho, g);
+                    } else {
+                        g[0] = nb[d]->rho; g[1] = nb[d]->u1; g[2] = nb[d]->u2; g[3] = nb[d]->T;
+                    }
+                    Wr[4 * d + 0] = g[0] / (2.0 * MM_PI * g[3]);
+                    Wr[4 * d + 1] = g[1];
+                    Wr[4 * d + 2] = g[2];
+                    Wr[4 * d + 3] = 1.0 / (2.0 * g[3]);
+                    // the wall kernel follows these Maxwellians along the velocity nodes too
+                    if (!exp_range_ok(P.v1_lo, P.dv1, P.nv1, P.v2_lo, P.dv2, P.nv2, g[1], g[2], Wr[4 * d + 3],
+                                      Wr[4 * d + 3], 0.0, Wr[4 * d + 3]))
+                        atomicMin(flag, step);
+                }
+            }
         }
     }
+    // wavefront 2: the v1 sums, then (after wavefront 1's v2 sums are in LDS) the
+    // projection matrix
+    double S1[5] = {0, 0, 0, 0, 0};
+    if (role == 2 && c < ncell && discrete) {
+        const CellPrim s = prim_of(Q + 6 * (size_t)c);
+        gauss_sums(P.v1_lo - s.u1, P.dv1, P.nv1, 1.0 / (2.0 * s.T), S1);
     }
     __syncthreads();
-    const int ncopy = (ncell - c0 < PREP_BLOCK ? ncell - c0 : PREP_BLOCK) * REC;
+    if (role == 2 && c < ncell) {
+        const CellPrim s = prim_of(Q + 6 * (size_t)c);
+        {
+            // projection coefficients
+            const double dA = P.dv1 * P.dv2;
+            if (!discrete) {
+                for (int a = 0; a < 4; ++a)
+                    for (int b = a; b < 4; ++b) R[R_P0 + sym4(a, b)] = a == b ? dA / s.rho : 0.0;
+            } else {
+                double S2r[5];
+                for (int q = 0; q < 5; ++q) S2r[q] = s_s2[q][cl];
+                auto mm = [&](int p, int q) { return S1[p] * S2r[q]; };
+                const double c0 = dA * s.rho / (2.0 * MM_PI * s.T);
+                const double T = s.T, rT = sqrt(T);
+                double A[4][4];
+                A[0][0] = c0 * mm(0, 0);
+                A[0][1] = c0 * mm(1, 0) / rT;
+                A[0][2] = c0 * mm(0, 1) / rT;
+                A[0][3] = c0 * ((mm(2, 0) + mm(0, 2)) / (2.0 * T) - mm(0, 0));
+                A[1][1] = c0 * mm(2, 0) / T;
+                A[1][2] = c0 * mm(1, 1) / T;
+                A[1][3] = c0 * ((mm(3, 0) + mm(1, 2)) / (2.0 * T) - mm(1, 0)) / rT;
+                A[2][2] = c0 * mm(0, 2) / T;
+                A[2][3] = c0 * ((mm(2, 1) + mm(0, 3)) / (2.0 * T) - mm(0, 1)) / rT;
+                A[3][3] = c0 * ((mm(4, 0) + 2.0 * mm(2, 2) + mm(0, 4)) / (4.0 * T * T) - (mm(2, 0) + mm(0, 2)) / T + mm(0, 0));
+                for (int a = 0; a < 4; ++a)
+                    for (int b = 0; b < a; ++b) A[a][b] = A[b][a];
+                spd_inverse4(A, dA, R + R_P0);
+            }
+        }
+    }
+    __syncthreads();
+    const int ncopy = (ncell - c0 < PREP_CELLS ? ncell - c0 : PREP_CELLS) * REC;
     double *dst = rec + (size_t)c0 * REC;
-    for (int t = threadIdx.x; t < ncopy; t += PREP_BLOCK) dst[t] = s_rec[t];
+    for (int t = threadIdx.x; t < ncopy; t += 4 * PREP_CELLS) dst[t] = s_rec[t];
 }
 
 // ---------------------------------------------------------------------------
@@ -670,8 +698,8 @@ __global__ __launch_bounds__(256) void k_wall_relax2d(TS *__restrict__ Gn, doubl
 void launch_prep2d(const double *Q, double *rec, double *wrec, int *flag, int step, const Params &P, hipStream_t st)
 {
     const int n = P.nx * P.ny;
-    hipLaunchKernelGGL(k_prep2d, dim3((n + PREP_BLOCK - 1) / PREP_BLOCK), dim3(PREP_BLOCK), 0, st, Q, rec, wrec, flag,
-                       step, P);
+    hipLaunchKernelGGL(k_prep2d, dim3((n + PREP_CELLS - 1) / PREP_CELLS), dim3(4 * PREP_CELLS), 0, st, Q, rec, wrec,
+                       flag, step, P);
 }
 
 void launch_micro_ref2d(const double *G, double *Gs, double *Gn, double *H, const double *rec, const double *wrec,
