@@ -131,6 +131,28 @@ def cpu_baseline(p, Q, G, budget_s=20.0):
                       f"({per:.2f} s per step, {threads} OpenMP threads)"}
 
 
+def copy_bandwidth(torch, gib=1.0, reps=10):
+    """Device-to-device copy rate of this GPU (bytes read + written per second, GB/s):
+    the attainable bandwidth for a stream that reads and writes equal amounts, as
+    the phase-space pass does."""
+    n = int(gib * (1 << 30)) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2 * n * 8 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return gbs
+
+
 def traffic_entry(precision):
     """HBM bytes of the phase-space pass from committed rocprofv3 counter runs, if they
     were taken on the current kernel source."""
@@ -176,6 +198,9 @@ def main():
         log(f"copy probe: {args.copy_probe} MiB read, {args.copy_probe} MiB written")
         del a, b
 
+    copy_gbs = copy_bandwidth(torch)
+    log(f"device copy: {copy_gbs:.0f} GB/s (read + write)")
+
     p, Q, G = W.cavity2d(seed=0, eps=args.eps)
     pts = p["nx"] * p["ny"] * p["nv1"] * p["nv2"]
     forms = {}
@@ -207,6 +232,8 @@ def main():
                          "achieved": bpp * pts / (r["micro_ms"] * 1e-3) / 1e9,
                          "peak": HBM_PEAK_GBS, "unit": "GB/s"}
         r["roofline"]["frac"] = r["roofline"]["achieved"] / HBM_PEAK_GBS
+        r["roofline"]["copy_gbs"] = copy_gbs
+        r["roofline"]["frac_of_copy"] = r["roofline"]["achieved"] / copy_gbs
         r["roofline"]["traffic"] = traffic_entry(form)
         if form == "closure":
             r["roofline"] = None      # the closure pass touches only the solved cells
