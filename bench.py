@@ -126,9 +126,19 @@ def cpu_baseline(p, Q, G, budget_s=20.0):
         per = (time.perf_counter() - t0) / n
     steps = n if n else 1
     pts = p["nx"] * p["ny"] * p["nv1"] * p["nv2"]
+    # one more full step on a single thread
+    oracle.set_threads(1)
+    try:
+        t0 = time.perf_counter()
+        oracle.run(p, Qc, Gc, 1)
+        per1 = time.perf_counter() - t0
+    finally:
+        oracle.set_threads(threads)
     return {"value": pts / per, "unit": "phase-space cell-updates/s", "cores": threads, "kind": "oracle",
+            "value_1thread": pts / per1,
             "sample": f"{steps} full step(s) of the {p['nx']}x{p['ny']}x{p['nv1']}x{p['nv2']} workload "
-                      f"({per:.2f} s per step, {threads} OpenMP threads)"}
+                      f"({per:.2f} s per step, {threads} OpenMP threads), then 1 step on 1 thread "
+                      f"({per1:.2f} s)"}
 
 
 def copy_bandwidth(torch, gib=1.0, reps=10):
