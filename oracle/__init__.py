@@ -66,6 +66,7 @@ def lib():
         L.o_dt.restype = C.c_double
         L.o_run2d.argtypes = [cp, dp, dp, C.c_int, dp, ip]
         L.o_run1d.argtypes = [cp, dp, dp, C.c_int, dp, ip]
+        L.o_mms1d.argtypes = [cp, C.c_double, dp]
         L.o_micro2d.argtypes = [cp, dp, dp, dp]
         L.o_macro2d.argtypes = [cp, dp, dp]
         L.o_ghat2d.argtypes = [cp, dp, dp]
@@ -171,6 +172,16 @@ def run(p, Q, G, nsteps):
     if rc:
         raise ValueError(f"oracle returned {rc}")
     return Q, G, H
+
+
+def mms1d(p, t_final):
+    """The 1D manufactured-solution run of the convergence study (Sec. 3.4, tab5-2)
+    on the grid of p (periodic in x): (macro, micro) relative L2 errors at t_final."""
+    e = np.zeros(2)
+    rc = lib().o_mms1d(C.byref(cfg(p)), float(t_final), _dp(e))
+    if rc:
+        raise RuntimeError(f"o_mms1d failed ({rc})")
+    return float(e[0]), float(e[1])
 
 
 def micro2d(p, Q, G):

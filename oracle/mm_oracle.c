@@ -971,8 +971,31 @@ static void flux_full1d(const double *q, double *out)
     out[2] = 0.5 * rho * u * (3.0 * T + u * u);
 }
 
+/* Manufactured-solution source of the 1D convergence study (Sec. 3.4): the
+ * invented f = A(v) B(t, x), A = e^{-(v-1)^2} + 2 e^{-(v+1)^2},
+ * B = 2 + sin 2 pi (x - t), whose moments give rho = 3 sqrt(pi) B, u = -1/3,
+ * T = 25/18, and whose micro part is g = (A - 1.8 e^{-0.04 (3v+1)^2}) B / eps.
+ * Its residual S = f_t + v f_x - (tau / eps)(M - f) enters the micro update as
+ * (1/tau_i^n)(I - Pi)[S] added to G-hat, and the macro update as the moments of
+ * S, dt pi^{3/2} cos 2 pi (x_i - t^n) (-8, 11, -7). */
+typedef struct { double t; } o_mms1;
+
+static double mms1_A(double v) { return exp(-(v - 1.0) * (v - 1.0)) + 2.0 * exp(-(v + 1.0) * (v + 1.0)); }
+static double mms1_B(double t, double x) { return 2.0 + sin(2.0 * O_PI * (x - t)); }
+static double mms1_g(double eps, double t, double x, double v)
+{
+    return (mms1_A(v) - 1.8 * exp(-0.04 * (3.0 * v + 1.0) * (3.0 * v + 1.0))) * mms1_B(t, x) / eps;
+}
+/* S(t, x, v) with collision parameter tau: f_t + v f_x = 2 pi cos 2 pi (x - t) (v - 1) A(v),
+ * and -(tau/eps)(M - f) = tau g.  The section leaves open which tau enters S; it is
+ * taken as the cell's tau_i^n, the one that divides S in G-hat. */
+static double mms1_S(double eps, double tau, double t, double x, double v)
+{
+    return 2.0 * O_PI * cos(2.0 * O_PI * (x - t)) * (v - 1.0) * mms1_A(v) + tau * mms1_g(eps, t, x, v);
+}
+
 static int step1d(const o_cfg *c, const o_grid *g, double *Q, double *G, double *Gn,
-                  double *Hn, o_prim1 *P, double dt)
+                  double *Hn, o_prim1 *P, double dt, const o_mms1 *mms)
 {
     int nx = g->nx, nv = g->nv1;
     int per = c->bc[0].kind == O_BC_PERIODIC;
@@ -983,6 +1006,7 @@ static int step1d(const o_cfg *c, const o_grid *g, double *Q, double *G, double 
         double *Mx = malloc(sizeof(double) * nv), *Z = malloc(sizeof(double) * nv);
         double *PZ = malloc(sizeof(double) * nv), *Gh = malloc(sizeof(double) * nv);
         double *t1 = malloc(sizeof(double) * nv);
+        double *Sv = malloc(sizeof(double) * nv), *PS = malloc(sizeof(double) * nv);
         double *zero = calloc(nv, sizeof(double));
 #pragma omp for schedule(static)
         for (int i = 0; i < nx; ++i) {
@@ -1009,6 +1033,12 @@ static int step1d(const o_cfg *c, const o_grid *g, double *Q, double *G, double 
                 project1d(c, g, Pi, Mx, Gh, t1);
                 for (int k = 0; k < nv; ++k) Gh[k] -= t1[k];
             }
+            if (mms) {
+                const double xi = c->x_lo + (i + 0.5) * g->dx;
+                for (int k = 0; k < nv; ++k) Sv[k] = mms1_S(c->eps, Pi->tau, mms->t, xi, g->v1[k]);
+                project1d(c, g, Pi, Mx, Sv, PS);
+                for (int k = 0; k < nv; ++k) Gh[k] += (Sv[k] - PS[k]) / Pi->tau;
+            }
             double a = c->eps / (c->eps + dt * Pi->tau), b = dt * Pi->tau / (c->eps + dt * Pi->tau);
             ksum hs = {0};
             for (int k = 0; k < nv; ++k) {
@@ -1018,7 +1048,7 @@ static int step1d(const o_cfg *c, const o_grid *g, double *Q, double *G, double 
             }
             Hn[i] = 0.5 * c->eps * g->dv1 * kval(&hs);       /* eqn5-26 */
         }
-        free(Mx); free(Z); free(PZ); free(Gh); free(t1); free(zero);
+        free(Mx); free(Z); free(PZ); free(Gh); free(t1); free(Sv); free(PS); free(zero);
     }
     memcpy(G, Gn, sizeof(double) * (size_t)nx * nv);
     /* macro update (eqn5-27) */
@@ -1046,12 +1076,70 @@ static int step1d(const o_cfg *c, const o_grid *g, double *Q, double *G, double 
     for (int i = 0; i < nx; ++i) {
         for (int r = 0; r < 3; ++r) Q[3 * i + r] -= dt / g->dx * (F[3 * (i + 1) + r] - F[3 * i + r]);
         Q[3 * i + 2] -= dt / g->dx * (Hf[i + 1] - Hf[i]);
+        if (mms) {
+            const double src = dt * pow(O_PI, 1.5) * cos(2.0 * O_PI * (c->x_lo + (i + 0.5) * g->dx - mms->t));
+            Q[3 * i + 0] += -8.0 * src;
+            Q[3 * i + 1] += 11.0 * src;
+            Q[3 * i + 2] += -7.0 * src;
+        }
         o_prim1 Pn;
         prim1d(c, Q + 3 * i, &Pn);
         if (!(Pn.rho > 0.0) || !(Pn.T > 0.0) || !isfinite(Pn.u)) ++bad;
     }
     free(F); free(Hf);
     return bad;
+}
+
+/* The manufactured-solution run of the 1D convergence study (Sec. 3.4, tab5-2)
+ * on the grid of c (periodic in x): exact point values at the cell centres at
+ * t = 0, steps of the CFL rule reset to land on t_final, the source terms above.
+ * errs receives the relative L2 errors of Q and of G against the exact solution
+ * at t_final (the study's definitions).  Returns O_OK or an error code. */
+int o_mms1d(const o_cfg *c, double t_final, double errs[2])
+{
+    if (cfg_check(c) || c->dim != 1) return O_EINVAL;
+    o_grid g;
+    if (grid_make(c, &g)) return O_ENOMEM;
+    int nx = g.nx, nv = g.nv1, rc = O_OK;
+    double *Q = malloc(sizeof(double) * 3 * nx), *G = malloc(sizeof(double) * (size_t)nx * nv);
+    double *Gn = malloc(sizeof(double) * (size_t)nx * nv), *Hn = calloc(nx, sizeof(double));
+    o_prim1 *P = malloc(sizeof(o_prim1) * nx);
+    const double sq = sqrt(O_PI);
+    for (int i = 0; i < nx; ++i) {
+        const double x = c->x_lo + (i + 0.5) * g.dx, B = mms1_B(0.0, x);
+        Q[3 * i + 0] = 3.0 * sq * B;
+        Q[3 * i + 1] = -sq * B;
+        Q[3 * i + 2] = 2.25 * sq * B;
+        for (int k = 0; k < nv; ++k) G[(size_t)i * nv + k] = mms1_g(c->eps, 0.0, x, g.v1[k]);
+    }
+    int nsteps = 0;
+    const double dt = o_dt(c, t_final, &nsteps);
+    o_mms1 m = {0.0};
+    for (int s = 0; s < nsteps; ++s) {
+        m.t = s * dt;
+        if (step1d(c, &g, Q, G, Gn, Hn, P, dt, &m)) { rc = O_ENONPHYS; break; }
+    }
+    if (rc == O_OK) {
+        ksum eq = {0}, nq = {0}, eg = {0}, ng = {0};
+        for (int i = 0; i < nx; ++i) {
+            const double x = c->x_lo + (i + 0.5) * g.dx, B = mms1_B(t_final, x);
+            const double qe[3] = {3.0 * sq * B, -sq * B, 2.25 * sq * B};
+            for (int r = 0; r < 3; ++r) {
+                kadd(&eq, (Q[3 * i + r] - qe[r]) * (Q[3 * i + r] - qe[r]));
+                kadd(&nq, qe[r] * qe[r]);
+            }
+            for (int k = 0; k < nv; ++k) {
+                const double ge = mms1_g(c->eps, t_final, x, g.v1[k]), d = G[(size_t)i * nv + k] - ge;
+                kadd(&eg, d * d);
+                kadd(&ng, ge * ge);
+            }
+        }
+        errs[0] = sqrt(kval(&eq) / kval(&nq));
+        errs[1] = sqrt(kval(&eg) / kval(&ng));
+    }
+    free(Q); free(G); free(Gn); free(Hn); free(P);
+    grid_free(&g);
+    return rc;
 }
 
 /* Run nsteps 1D steps on Q [nx][3] and G [nx][nv]; H (may be NULL) gets H of the last step. */
@@ -1068,7 +1156,7 @@ int o_run1d(const o_cfg *c, double *Q, double *G, int nsteps, double *H, int *fa
     double *Hn = calloc(nx, sizeof(double));
     double dt = step_dt(c);
     for (int s = 0; s < nsteps; ++s) {
-        if (step1d(c, &g, Q, G, Gn, Hn, P, dt)) { rc = O_ENONPHYS; if (failed_step) *failed_step = s + 1; break; }
+        if (step1d(c, &g, Q, G, Gn, Hn, P, dt, NULL)) { rc = O_ENONPHYS; if (failed_step) *failed_step = s + 1; break; }
     }
     if (H) memcpy(H, Hn, sizeof(double) * nx);
     free(P); free(Gn); free(Hn);
