@@ -12,7 +12,8 @@
  * What it computes, section by section of the paper:
  *   1D1V (d_x = d_v = 1, BGK):    Sec. 3.2-3.4, eqs. (eqn5-19)-(eqn5-27),
  *                                 KFVS flux (flux1d_1)-(flux1d_2), periodic and
- *                                 extrapolation boundary conditions.
+ *                                 extrapolation boundary conditions; the
+ *                                 manufactured-solution run of Sec. 3.4.
  *   2D2V (d_x = d_v = 2, ES-BGK): Sec. 5.2-5.4: micro operator splitting
  *                                 (micro-2D-split-1..3), upwind Z, projection
  *                                 (zhat-2D-*, coeffs-2D-*), G-hat (eqn5-97),
@@ -41,6 +42,10 @@
  *     y-ghosts from Q**.
  *   - "Inflow" sides: a fixed ghost Maxwellian (rho, u, T), micro ghost g = 0,
  *     wall machinery otherwise.
+ *   - Manufactured solution (Sec. 3.4): the tau inside the residual S is the
+ *     cell's tau_i^n, the one that divides S in G-hat; S and the macro source
+ *     are taken at t^n and the cell centre; the initial Q and G are the exact
+ *     point values at cell centres.
  *
  * Velocity sums are Neumaier-compensated and run k fastest, then l.
  */
