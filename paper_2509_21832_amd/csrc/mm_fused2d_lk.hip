@@ -48,11 +48,28 @@ struct PassLK {
     int lane, i, k, l0, L;
     int row_bytes;          // bytes of one row of cells of g
     int off_c, off_u;       // byte offsets in its row of this lane's value of cell i and of its upwind cell
-    double v1d, v2bd, hd;   // v1 of this lane; v2(m) = v2b + m h
+    double v1d, v2bd, hd;   // v1 of this lane; v2 of node m: v2b + m h
     TC v1, cx, v2b, h, idy;
 
-    __device__ __forceinline__ TC v2(int m) const { return v2b + (TC)m * h; }
-    __device__ __forceinline__ double v2d(int m) const { return v2bd + (double)m * hd; }
+    // The node loops step v2 along the lane, w <- w + h from v2b: one add per
+    // node (v2b + m h with the constant m would cost a register copy as well)
+
+    // Moment sums along a lane's nodes run over the centred node index
+    // t = m - (NPT - 1) / 2 (exact constants once the node loop is unrolled):
+    // sum t^p F.  With the lane's centre velocity vc, v2 of node m is vc + t h, and the
+    // sums of v2 powers follow once per row.  Centring keeps the expansion's terms
+    // no larger than those of the direct sums.
+    static constexpr double tn(int m) { return m - 0.5 * (NPT - 1); }
+    __device__ __forceinline__ double vc() const { return v2bd + 0.5 * (NPT - 1) * hd; }
+    // (sum F, sum t F, sum t^2 F) -> (sum F, sum v1 F, sum v2 F, sum |v|^2 F)
+    __device__ __forceinline__ void raw4(const double *S, double (&s)[4]) const
+    {
+        const double c = vc();
+        s[0] = S[0];
+        s[1] = v1d * S[0];
+        s[2] = c * S[0] + hd * S[1];
+        s[3] = (v1d * v1d + c * c) * S[0] + (2.0 * c * hd) * S[1] + (hd * hd) * S[2];
+    }
 
     // A Gaussian of the cell along this lane's nodes, e(m) = exp(quadratic in m),
     // follows the exact recurrence e(m+1) = e(m) r(m), r(m+1) = r(m) k, in FP64
@@ -82,9 +99,12 @@ struct PassLK {
                   exp(-(2.0 * qb * a + qc * (2.0 * w + hd)) * hd), R[R_KG]};
     }
 
-    // g of row r of cells (of G or Gn) as a buffer
+    // g of row r of cells (of G or Gn) as a buffer.  r is wave-uniform; stating it
+    // keeps the resource in SGPRs also where the compiler merges call sites (a
+    // resource it cannot prove uniform costs a waterfall loop per access)
     __device__ __forceinline__ __amdgpu_buffer_rsrc_t row(const TS *base, int r) const
     {
+        r = __builtin_amdgcn_readfirstlane(r);
         return buf_rsrc(base + (size_t)r * P->nx * (64 * NPT), row_bytes);
     }
     static constexpr int NB = 64 * (int)sizeof(TS);   // byte stride of node m
@@ -119,36 +139,34 @@ struct PassLK {
 #pragma unroll
             for (int m = 0; m < NPT; ++m) Z[m] = cx * (gc[m] - gn[m]);
         }
-        double t0 = 0.0, t2 = 0.0, t22 = 0.0;
+        double S[3] = {0.0, 0.0, 0.0};
 #pragma unroll
         for (int m = 0; m < NPT; ++m) {
-            const double z = (double)Z[m], w = v2d(m), u = w * z;
-            t0 += z;
-            t2 += u;
-            t22 += w * u;
+            const double z = (double)Z[m];
+            S[0] += z;
+            S[1] += tn(m) * z;
+            S[2] += (tn(m) * tn(m)) * z;
         }
-        double s[4] = {t0, v1d * t0, t2, v1d * v1d * t0 + t22};
+        double s[4];
+        raw4(S, s);
         wave_sum<4>(s, lane);
-        Cell<TC> cl;
-        load_cell(R, cl);
-        TC cp[4];
-        proj_poly(cl, s, cp);
-        const TC K = cp[0] + cp[1] * v1 + cp[3] * v1 * v1;
+        double o[4];
+        proj_raw(R, s, o);
+        const TC c2 = (TC)o[2], c3 = (TC)o[3], K = (TC)(o[0] + (o[1] + o[3] * v1d) * v1d);
         const TC dt = (TC)P->dt;
         Gq mq = maxw_q(R);
+        TC w = v2b;
 #pragma unroll
-        for (int m = 0; m < NPT; ++m) {
-            const TC w = v2(m);
-            const TC pm = (cp[3] * w + cp[2]) * w + K;
+        for (int m = 0; m < NPT; ++m, w += h) {
+            const TC pm = (c3 * w + c2) * w + K;
             out[m] = gc[m] + dt * (pm * (TC)mq.next() - Z[m]);
         }
     }
 
     // y-transport of node m: v2 (G(j) - G(j -/+ 1)) / dy upwind, written as
     // |v2| / dy (G(j) - G(upwind)) (the same value)
-    __device__ __forceinline__ TC zy(int m, const TC (&lo)[NPT], const TC (&ce)[NPT], const TC (&hi)[NPT]) const
+    __device__ __forceinline__ TC zy(int m, TC w, const TC (&lo)[NPT], const TC (&ce)[NPT], const TC (&hi)[NPT]) const
     {
-        const TC w = v2(m);
         return (fabs(w) * idy) * (ce[m] - (w < (TC)0 ? hi[m] : lo[m]));
     }
 
@@ -157,29 +175,29 @@ struct PassLK {
     __device__ __forceinline__ void wall_row(int jr, const TC (&lo)[NPT], const TC (&ce)[NPT], const TC (&hi)[NPT],
                                              const Rec &R)
     {
-        Cell<TC> cl;
-        load_cell(R, cl);
         TC Zy[NPT];
-        double t0 = 0.0, t2 = 0.0, t22 = 0.0;
+        double S[3] = {0.0, 0.0, 0.0};
+        TC wz = v2b;
 #pragma unroll
-        for (int m = 0; m < NPT; ++m) {
-            Zy[m] = zy(m, lo, ce, hi);
-            const double z = (double)Zy[m], vd = v2d(m), u = vd * z;
-            t0 += z;
-            t2 += u;
-            t22 += vd * u;
+        for (int m = 0; m < NPT; ++m, wz += h) {
+            Zy[m] = zy(m, wz, lo, ce, hi);
+            const double z = (double)Zy[m];
+            S[0] += z;
+            S[1] += tn(m) * z;
+            S[2] += (tn(m) * tn(m)) * z;
         }
-        double s[4] = {t0, v1d * t0, t2, v1d * v1d * t0 + t22};
+        double s[4];
+        raw4(S, s);
         wave_sum<4>(s, lane);
-        TC cz[4];
-        proj_poly(cl, s, cz);
-        const TC Kz = cz[0] + cz[1] * v1 + cz[3] * v1 * v1, dt = (TC)P->dt;
+        double o[4];
+        proj_raw(R, s, o);
+        const TC c2 = (TC)o[2], c3 = (TC)o[3], Kz = (TC)(o[0] + (o[1] + o[3] * v1d) * v1d), dt = (TC)P->dt;
         const auto ws = row(Gn, jr);
         Gq mq = maxw_q(R);
+        TC w = v2b;
 #pragma unroll
-        for (int m = 0; m < NPT; ++m) {
-            const TC w = v2(m);
-            const TC pz = (cz[3] * w + cz[2]) * w + Kz;
+        for (int m = 0; m < NPT; ++m, w += h) {
+            const TC pz = (c3 * w + c2) * w + Kz;
             buf_store((TS)(ce[m] + dt * (pz * (TC)mq.next() - Zy[m])), ws, off_c, NB * m);
         }
     }
@@ -198,81 +216,80 @@ struct PassLK {
 
     // y-sweep, G-hat (eqn5-97), relaxation and H for interior row j with window
     // (lo, ce, hi).  The ES term (calG - M) / eps is formed in FP64 from the two
-    // Gaussians, then converted to the compute type.
+    // Gaussians, then converted to the compute type.  The relaxation
+    //   G^{n+1} = ra (ce + dt (pz M - Zy)) + rb (G-hat - pb M)
+    // has pz M = Pi[Zy] and pb M = Pi[G-hat] (G-hat is not projected in the
+    // paper's form: pb = 0).  Pi is linear, so with d = ra dt Zy - rb' G-hat
+    // (rb' = rb, or 0 in the paper's form)
+    //   G^{n+1} = [ra ce - d + (rb - rb') G-hat] + Pi[d]:
+    // the first node loop forms the bracket and the moments of d, and after one
+    // wavefront sum Pi[d] = (q0 + q1 v1 + q2 v2 + q3 |v|^2) M.
     __device__ __forceinline__ void finish_row(size_t c, int jr, const TC (&lo)[NPT], const TC (&ce)[NPT],
                                                const TC (&hi)[NPT], const Rec &R)
     {
-        Cell<TC> cl;
-        load_cell(R, cl);
         const bool discrete = P->proj_mode == PROJ_DISCRETE;
-        const double a = v1d - cl.u1d;              // w1 of this lane
+        const double u2d = R[R_U2];
+        const double a = v1d - R[R_U1];             // w1 of this lane
         TC C[4];
         ghat_cubic(R, a, C);
         const Gq mq0 = maxw_q(R);
         Gq gq = es_q(R);
-        const double iepsd = R[R_IEPS];
-        const TC u2 = cl.u2;
-        const TC dt = (TC)P->dt, ra = (TC)cl.ra, rb = (TC)cl.rb, radt = ra * dt;
-        // G^{n+1} = ra (ce + dt (pz M - Zy)) + rb (G-hat - pb M) regrouped as
-        // [ra ce - ra dt Zy + rb G-hat] + (ra dt pz - rb pb) M: the bracket is
-        // formed here, the projection part after the velocity sums
+        const double iepsd = R[R_IEPS], rbd = R[R_B];
+        const TC u2 = (TC)u2d;
+        const TC ra = (TC)R[R_A], radt = ra * (TC)P->dt;
+        const TC rbp = discrete ? (TC)rbd : (TC)0, rbq = discrete ? (TC)0 : (TC)rbd;
         TC part[STASH ? 1 : NPT];
-        double acc[6] = {0, 0, 0, 0, 0, 0};
+        double S[3] = {0.0, 0.0, 0.0};
         {
             Gq mq = mq0;
+            TC w = v2b;
 #pragma unroll
-            for (int m = 0; m < NPT; ++m) {
-                const TC w = v2(m), w2 = w - u2;
-                const TC zv = zy(m, lo, ce, hi);
+            for (int m = 0; m < NPT; ++m, w += h) {
+                const TC w2 = w - u2;
+                const TC zv = zy(m, w, lo, ce, hi);
                 const double Md = mq.next();
                 const TC M = (TC)Md, es = (TC)((gq.next() - Md) * iepsd);
                 const TC bv = M * (((C[3] * w2 + C[2]) * w2 + C[1]) * w2 + C[0]) + es;
-                const TC pv = ra * ce[m] - radt * zv + rb * bv;
+                const TC d = radt * zv - rbp * bv;
+                const TC pv = ra * ce[m] + (rbq * bv - d);
                 if constexpr (STASH) st[m * 64 + lane] = pv;
                 else part[m] = pv;
-                const double vd = v2d(m);
-                const double z = (double)zv, b = (double)bv;
-                const double uz = vd * z, ub = vd * b;
-                acc[0] += z;
-                acc[1] += uz;
-                acc[2] += vd * uz;
-                acc[3] += b;
-                acc[4] += ub;
-                acc[5] += vd * ub;
+                const double dd = (double)d;
+                S[0] += dd;
+                S[1] += tn(m) * dd;
+                S[2] += (tn(m) * tn(m)) * dd;
             }
         }
-        const double v1s = v1d * v1d;
-        double s[8] = {acc[0], v1d * acc[0], acc[1], v1s * acc[0] + acc[2],
-                       acc[3], v1d * acc[3], acc[4], v1s * acc[3] + acc[5]};
-        wave_sum<8>(s, lane);
-        TC cz[4], cb[4] = {(TC)0, (TC)0, (TC)0, (TC)0};
-        proj_poly(cl, s, cz);
-        if (discrete) proj_poly(cl, s + 4, cb);
-        // ra dt pz - rb pb as a quadratic in v2 at this lane's v1
-        const TC vv = v1 * v1;
-        const TC q3 = radt * cz[3] - rb * cb[3], q2 = radt * cz[2] - rb * cb[2];
-        const TC q0 = radt * (cz[0] + cz[1] * v1 + cz[3] * vv) - rb * (cb[0] + cb[1] * v1 + cb[3] * vv);
+        double s[4];
+        raw4(S, s);
+        wave_sum<4>(s, lane);
+        double o[4];
+        proj_raw(R, s, o);
+        const TC q3 = (TC)o[3], q2 = (TC)o[2], q0 = (TC)(o[0] + (o[1] + o[3] * v1d) * v1d);
         const auto ws = row(Gn, jr);
         // recompute the node values below rather than hold all NPT of them from the first loop
         refresh();
-        double h0 = 0.0, h1 = 0.0, h2 = 0.0, h3 = 0.0;
-        const double u2d = cl.u2d;
+        double T[4] = {0.0, 0.0, 0.0, 0.0};
         Gq mq = mq0;
+        TC w = v2b;
 #pragma unroll
-        for (int m = 0; m < NPT; ++m) {
-            const TC w = v2(m);
+        for (int m = 0; m < NPT; ++m, w += h) {
             const TC M = (TC)mq.next();
             const TC pv = STASH ? st[m * 64 + lane] : part[STASH ? 0 : m];
             const TS gn = (TS)(((q3 * w + q2) * w + q0) * M + pv);
             buf_store(gn, ws, off_c, NB * m);
-            const double g = (double)gn, w2 = v2d(m) - u2d;
-            const double ug = g * w2, ug2 = ug * w2;
-            h0 += g;
-            h1 += ug;
-            h2 += ug2;
-            h3 += ug2 * w2;
+            const double g = (double)gn;
+            T[0] += g;
+            T[1] += tn(m) * g;
+            T[2] += (tn(m) * tn(m)) * g;
+            T[3] += (tn(m) * tn(m) * tn(m)) * g;
         }
-        double hs[4] = {a * a * a * h0, a * a * h1, a * h2, h3};
+        // sum g w2^p with w2 = v2 - u2 = e + t h (e: the lane's centre velocity minus u2)
+        const double e = vc() - u2d, e2 = e * e, h2 = hd * hd;
+        const double g1 = e * T[0] + hd * T[1];
+        const double g2 = e2 * T[0] + (2.0 * e * hd) * T[1] + h2 * T[2];
+        const double g3 = (e2 * e) * T[0] + (3.0 * e2 * hd) * T[1] + (3.0 * e * h2) * T[2] + (h2 * hd) * T[3];
+        double hs[4] = {a * a * a * T[0], a * a * g1, a * g2, g3};
         wave_sum<4>(hs, lane);
         if (lane == 0) {
             const double f = P->eps * P->dv1 * P->dv2;
@@ -575,16 +592,15 @@ __global__ __launch_bounds__(256) void k_wall_lk(TS *__restrict__ Gn, double *__
             acc[5] += w * ub;
         }
     }
-    const double v1s = v1 * v1;
-    double s[8] = {acc[0], v1 * acc[0], acc[1], v1s * acc[0] + acc[2],
-                   acc[3], v1 * acc[3], acc[4], v1s * acc[3] + acc[5]};
-    wave_sum<8>(s, lane);
-    Cell<double> cl;
-    load_cell(RecP{R}, cl);
-    double cz[4], cb[4] = {0.0, 0.0, 0.0, 0.0};
-    proj_poly(cl, s, cz);
-    if (discrete) proj_poly(cl, s + 4, cb);
-    const double Kz = cz[0] + cz[1] * v1 + cz[3] * v1s, Kb = cb[0] + cb[1] * v1 + cb[3] * v1s;
+    // G-hat = -itau (mup - Pi[mup]) + (es - Pi[es]) (es unprojected in the paper's
+    // form) = -itau mup + es + Pi[itau mup - es]: one projection of combined moments
+    const double v1s = v1 * v1, eb = discrete ? 1.0 : 0.0;
+    double s[4] = {itau * acc[0] - eb * acc[3], v1 * (itau * acc[0] - eb * acc[3]), itau * acc[1] - eb * acc[4],
+                   v1s * (itau * acc[0] - eb * acc[3]) + (itau * acc[2] - eb * acc[5])};
+    wave_sum<4>(s, lane);
+    double o[4];
+    proj_raw(RecP{R}, s, o);
+    const double K = o[0] + o[1] * v1 + o[3] * v1s;
     const double ra = R[R_A], rb = R[R_B];
     const double a = v1 - u1;
     double h0 = 0.0, h1 = 0.0, h2 = 0.0, h3 = 0.0;
@@ -592,8 +608,7 @@ __global__ __launch_bounds__(256) void k_wall_lk(TS *__restrict__ Gn, double *__
 #pragma unroll
     for (int m = 0; m < NPT; ++m) {
         const double w = v2b + m * h, M = mq.next();
-        const double pz = (cz[3] * w + cz[2]) * w + Kz, pb = (cb[3] * w + cb[2]) * w + Kb;
-        const double gh = -itau * (mup[m] - pz * M) + (es[m] - pb * M);
+        const double gh = -itau * mup[m] + es[m] + ((o[3] * w + o[2]) * w + K) * M;
         const TS gn = (TS)(ra * g[m] + rb * gh);
         buf_store(gn, rs, off, NB * m);
         const double gv = (double)gn, w2 = w - u2;

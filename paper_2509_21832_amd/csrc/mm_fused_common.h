@@ -22,12 +22,14 @@ __device__ __forceinline__ double hilo(unsigned hi, unsigned lo)
     return __hiloint2double((int)hi, (int)lo);
 }
 
-// DPP move of both halves of a double (ctrl: a DPP control code)
+// DPP move of both halves of a double (ctrl: a DPP control code).  Every row
+// and bank is written and the patterns used here read valid lanes only, so no
+// old value is kept (one DPP move per half, no copy).
 template <int CTRL>
 __device__ __forceinline__ double dpp(double v)
 {
-    const int lo = __builtin_amdgcn_update_dpp(__double2loint(v), __double2loint(v), CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(__double2hiint(v), __double2hiint(v), CTRL, 0xF, 0xF, false);
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false);
     return __hiloint2double(hi, lo);
 }
 
@@ -220,6 +222,20 @@ __device__ __forceinline__ void proj_poly(const Cell<TC> &c, const double *s, TC
     out[1] = (TC)(A[1] * rsT - 2.0 * c3 * u1);
     out[2] = (TC)(A[2] * rsT - 2.0 * c3 * u2);
     out[0] = (TC)(A[0] - A[1] * rsT * u1 - A[2] * rsT * u2 + c3 * (u1 * u1 + u2 * u2) - A[3]);
+}
+
+// The same coefficients from the raw moments s = sum (1, v1, v2, |v|^2) F with
+// the record's composite map (R_PM): one symmetric 4x4 product.
+template <typename RT>
+__device__ __forceinline__ void proj_raw(const RT &R, const double *s, double out[4])
+{
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        double v = 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v += R[R_PM + sym4(a, q)] * s[q];
+        out[a] = v;
+    }
 }
 
 // Geometry of the launch: columns are grouped WPG to a workgroup; rows are cut

@@ -59,7 +59,12 @@ enum {
     R_DA, R_DC,           // QA - 1/(2T), QC - 1/(2T): ES exponent minus Maxwellian exponent
     R_KM, R_KG,           // exp(-2 h^2 / 2T), exp(-2 QC h^2) with h = (64 / nv1) dv2 (lane-k node step
                           // in v2): second-difference factors of the Maxwellian and ES exponents
-    REC = 40
+    R_PM,         // 10 entries: symmetric 4x4 matrix T^t P0 T mapping the raw moments
+                  // sum (1, v1, v2, |v|^2) F straight to (c0, c1, c2, c3) with
+                  // Pi F = (c0 + c1 v1 + c2 v2 + c3 |v|^2) M; T takes raw moments to moments
+                  // against phi = (1, w1/sqrt T, w2/sqrt T, |w|^2/(2T) - 1), and its
+                  // transpose takes phi coefficients back to the polynomial in v
+    REC = 48
 };
 // wall cells: the four neighbour Maxwellians (x-, x+, y-, y+), each as
 // (rho / (2 pi T), u1, u2, 1 / (2T))

@@ -153,7 +153,7 @@ __global__ __launch_bounds__(4 * PREP_CELLS) void k_prep2d(const double *__restr
             if (!exp_range_ok(P.v1_lo, P.dv1, P.nv1, P.v2_lo, P.dv2, P.nv2, s.u1, s.u2, i2T, qa, qb, qc))
                 atomicMin(flag, step);
         } else if (role == 1) {
-            for (int q = R_KG + 1; q < REC; ++q) R[q] = 0.0;     // unused tail of the record
+            for (int q = R_PM + 10; q < REC; ++q) R[q] = 0.0;    // unused tail of the record
             const double tau = tau_of(P, s.rho, s.p, s.T);
             R[R_RST] = 1.0 / sqrt(s.T);
             R[R_MPRE] = s.rho / (2.0 * MM_PI * s.T);
@@ -250,6 +250,26 @@ __global__ __launch_bounds__(4 * PREP_CELLS) void k_prep2d(const double *__restr
                     for (int b = 0; b < a; ++b) A[a][b] = A[b][a];
                 spd_inverse4(A, dA, R + R_P0);
             }
+            // the same projection from raw moments: PM = T^t P0 T
+            const double rsT = 1.0 / sqrt(s.T), i2T = 1.0 / (2.0 * s.T);
+            const double Tm[4][4] = {{1.0, 0.0, 0.0, 0.0},
+                                     {-rsT * s.u1, rsT, 0.0, 0.0},
+                                     {-rsT * s.u2, 0.0, rsT, 0.0},
+                                     {i2T * (s.u1 * s.u1 + s.u2 * s.u2) - 1.0, -2.0 * s.u1 * i2T,
+                                      -2.0 * s.u2 * i2T, i2T}};
+            double PT[4][4];
+            for (int a = 0; a < 4; ++a)
+                for (int q = 0; q < 4; ++q) {
+                    double v = 0.0;
+                    for (int b = 0; b < 4; ++b) v += R[R_P0 + sym4(a, b)] * Tm[b][q];
+                    PT[a][q] = v;
+                }
+            for (int a = 0; a < 4; ++a)
+                for (int q = a; q < 4; ++q) {
+                    double v = 0.0;
+                    for (int b = 0; b < 4; ++b) v += Tm[b][a] * PT[b][q];
+                    R[R_PM + sym4(a, q)] = v;
+                }
         }
     }
     __syncthreads();
