@@ -85,6 +85,15 @@ struct PassLK {
             return v;
         }
     };
+    // start values (e(0), r(0)) of a Gaussian's recurrence: the x-sweep of row j+1
+    // makes the Maxwellian's, and in FP64 the finish of that row one step later
+    // reuses them (timed: FP64 faster by a few percent; the FP32 instance, which
+    // runs two wavefronts per SIMD, slower, so it computes them again)
+    static constexpr bool MQ_RING = sizeof(TC) == 8;
+    struct GqS {
+        double e, r;
+    };
+    GqS mq_cur{0.0, 0.0};   // the Maxwellian start values of the next row to finish
     // the Maxwellian of record R: mpre exp(-(w1^2 + w2(m)^2) / 2T)
     __device__ __forceinline__ Gq maxw_q(const Rec &R) const
     {
@@ -124,7 +133,7 @@ struct PassLK {
     bool edge_col;   // wave-uniform: some lane of this column has zero_nb
 
     // x-sweep of row r: G*(i, r) into out; R: the record of cell (i, r)
-    __device__ __forceinline__ void xsweep(int r, TC (&out)[NPT], const Rec &R)
+    __device__ __forceinline__ GqS xsweep(int r, TC (&out)[NPT], const Rec &R)
     {
         TC gc[NPT], Z[NPT];
         {
@@ -154,13 +163,15 @@ struct PassLK {
         proj_raw(R, s, o);
         const TC c2 = (TC)o[2], c3 = (TC)o[3], K = (TC)(o[0] + (o[1] + o[3] * v1d) * v1d);
         const TC dt = (TC)P->dt;
-        Gq mq = maxw_q(R);
+        const Gq m0 = maxw_q(R);
+        Gq mq = m0;
         TC w = v2b;
 #pragma unroll
         for (int m = 0; m < NPT; ++m, w += h) {
             const TC pm = (c3 * w + c2) * w + K;
             out[m] = gc[m] + dt * (pm * (TC)mq.next() - Z[m]);
         }
+        return GqS{m0.e, m0.r};
     }
 
     // y-transport of node m: v2 (G(j) - G(j -/+ 1)) / dy upwind, written as
@@ -173,7 +184,7 @@ struct PassLK {
     // y-sweep of a wall-adjacent cell: G** only.  The wall form of G-hat, the
     // relaxation and H of these cells are done by k_wall_relax2d afterwards.
     __device__ __forceinline__ void wall_row(int jr, const TC (&lo)[NPT], const TC (&ce)[NPT], const TC (&hi)[NPT],
-                                             const Rec &R)
+                                             const Rec &R, GqS ms)
     {
         TC Zy[NPT];
         double S[3] = {0.0, 0.0, 0.0};
@@ -193,7 +204,7 @@ struct PassLK {
         proj_raw(R, s, o);
         const TC c2 = (TC)o[2], c3 = (TC)o[3], Kz = (TC)(o[0] + (o[1] + o[3] * v1d) * v1d), dt = (TC)P->dt;
         const auto ws = row(Gn, jr);
-        Gq mq = maxw_q(R);
+        Gq mq = MQ_RING ? Gq{ms.e, ms.r, R[R_KM]} : maxw_q(R);
         TC w = v2b;
 #pragma unroll
         for (int m = 0; m < NPT; ++m, w += h) {
@@ -225,14 +236,14 @@ struct PassLK {
     // the first node loop forms the bracket and the moments of d, and after one
     // wavefront sum Pi[d] = (q0 + q1 v1 + q2 v2 + q3 |v|^2) M.
     __device__ __forceinline__ void finish_row(size_t c, int jr, const TC (&lo)[NPT], const TC (&ce)[NPT],
-                                               const TC (&hi)[NPT], const Rec &R)
+                                               const TC (&hi)[NPT], const Rec &R, GqS ms)
     {
         const bool discrete = P->proj_mode == PROJ_DISCRETE;
         const double u2d = R[R_U2];
         const double a = v1d - R[R_U1];             // w1 of this lane
         TC C[4];
         ghat_cubic(R, a, C);
-        const Gq mq0 = maxw_q(R);
+        const Gq mq0 = MQ_RING ? Gq{ms.e, ms.r, R[R_KM]} : maxw_q(R);
         Gq gq = es_q(R);
         const double iepsd = R[R_IEPS], rbd = R[R_B];
         const TC u2 = (TC)u2d;
@@ -374,18 +385,23 @@ struct PassLK {
             solve = micro_row(j);
             if (!solve && !micro_row(j + 1) && !micro_row(j + 2)) return;
         }
+        GqS nx{0.0, 0.0};
         if (j + 1 < P->ny) {
-            xsweep(j + 1, win[HI], rec_at(j + 1, rv[HI]));
+            nx = xsweep(j + 1, win[HI], rec_at(j + 1, rv[HI]));
         }
-        else if (P->bc[3].kind == BC_PERIODIC) xsweep(0, win[HI], rec_at(0, rv[HI]));
+        else if (P->bc[3].kind == BC_PERIODIC) nx = xsweep(0, win[HI], rec_at(0, rv[HI]));
         else ghost(P->bc[3].kind, win[CE], win[HI]);
+        // row j finishes with the start values its own x-sweep made one step ago
+        // (a row that was not swept is not finished either)
+        const GqS ms = mq_cur;
+        mq_cur = nx;
         __builtin_amdgcn_sched_barrier(0);
         if (CL && !solve) return;
         refresh();
         const size_t c = (size_t)j * P->nx + i;
         const Rec R = rec_at(j, rv[CE]);
-        if (R[R_WALL] != 0.0) wall_row(j, win[LO], win[CE], win[HI], R);
-        else finish_row(c, j, win[LO], win[CE], win[HI], R);
+        if (R[R_WALL] != 0.0) wall_row(j, win[LO], win[CE], win[HI], R, ms);
+        else finish_row(c, j, win[LO], win[CE], win[HI], R, ms);
         __builtin_amdgcn_sched_barrier(0);
     }
 };
@@ -472,7 +488,7 @@ __global__ __launch_bounds__(64 * WPG, (LKTraits<TC, NPT>::occupancy)) void k_fu
     ps.fetch_rec(j0 + 1, rv[2]);
     // closure form: the prologue rows are needed only for solved rows of the segment
     if (!CL || ps.micro_row(j0 - 1) || ps.micro_row(j0) || ps.micro_row(j0 + 1))
-        ps.xsweep(j0, win[1], ps.rec_at(j0, rv[1]));
+        ps.mq_cur = ps.xsweep(j0, win[1], ps.rec_at(j0, rv[1]));
     if (!CL || ps.micro_row(j0)) {
         if (j0 > 0) ps.xsweep(j0 - 1, win[0], ps.rec_at(j0 - 1, rv[0]));
         else if (P.bc[2].kind == BC_PERIODIC) ps.xsweep(P.ny - 1, win[0], ps.rec_at(P.ny - 1, rv[0]));
