@@ -577,6 +577,109 @@ __global__ __launch_bounds__(256) void k_macro2d(const double *__restrict__ Qin,
     for (int m = 0; m < 6; ++m) Qout[6 * (size_t)c + m] = qo[m];
 }
 
+// The same sweep with one workgroup per line of cells along the sweep (a row
+// for dir 0, a column for dir 1; lines of at most MACRO_LINE cells).  Each cell
+// is collided once and its two half fluxes F+ and F- (which share a, b, J and K)
+// are formed once into LDS; the faces are then F+ (low cell) + F- (high cell),
+// the wrap for a periodic side, or the boundary face of the edge cell.  The
+// four-lane form above repeats the collision and the half fluxes of a cell up to
+// five times, which made it bound by FP64 arithmetic.
+constexpr int MACRO_LINE = 512;   // 48 KB of LDS per workgroup at most
+
+__device__ __forceinline__ void kfvs_pair(const double q[6], int d, double Fp[6], double Fm[6])
+{
+    kfvs_half(q, d, 1.0, Fp);
+    kfvs_half(q, d, -1.0, Fm);
+}
+
+template <int DIR>
+__global__ __launch_bounds__(256) void k_macro_line(const double *__restrict__ Qin, const double *__restrict__ H,
+                                                    double *__restrict__ Qout, int *__restrict__ flag, int step,
+                                                    Params P)
+{
+    extern __shared__ double s_f[];   // [2][n][6]: F+ and F- of every cell of the line
+    const int n = DIR == 0 ? P.nx : P.ny;
+    const int nline = DIR == 0 ? P.ny : P.nx;
+    // dispatch puts workgroup b on XCD b mod 8: neighbouring lines share an XCD
+    const int per = (nline + 7) / 8;
+    const int line = (blockIdx.x % 8) * per + blockIdx.x / 8;
+    if (line >= nline) return;
+    const int stride = DIR == 0 ? 1 : P.nx;
+    const int base = DIR == 0 ? line * P.nx : line;
+    const int slo = DIR == 0 ? 0 : 2, shi = DIR == 0 ? 1 : 3;
+    const double h = DIR == 0 ? P.dx : P.dy;
+    const int hoff = DIR == 0 ? 0 : 1;
+    double *Fp = s_f, *Fm = s_f + 6 * n;
+    constexpr int CPT = MACRO_LINE / 256;   // cells per thread
+    double qs[CPT][6];
+#pragma unroll
+    for (int u = 0; u < CPT; ++u) {
+        const int pos = threadIdx.x + 256 * u;
+        if (pos >= n) break;
+        load_q(Qin, base + pos * stride, qs[u]);
+        if (DIR == 0) collide(P, qs[u]);
+        double a[6], b[6];
+        kfvs_pair(qs[u], DIR, a, b);
+#pragma unroll
+        for (int m = 0; m < 6; ++m) {
+            Fp[6 * pos + m] = a[m];
+            Fm[6 * pos + m] = b[m];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < CPT; ++u) {
+        const int pos = threadIdx.x + 256 * u;
+        if (pos >= n) break;
+        const int c = base + pos * stride;
+        const double *qc = qs[u];
+        double FL[6], FR[6];
+        if (pos > 0) {
+            for (int m = 0; m < 6; ++m) FL[m] = Fp[6 * (pos - 1) + m] + Fm[6 * pos + m];
+        } else if (P.bc[slo].kind == BC_PERIODIC) {
+            for (int m = 0; m < 6; ++m) FL[m] = Fp[6 * (n - 1) + m] + Fm[m];
+        } else {
+            boundary_face(P, slo, qc, qc, DIR, FL);
+        }
+        if (pos < n - 1) {
+            for (int m = 0; m < 6; ++m) FR[m] = Fp[6 * pos + m] + Fm[6 * (pos + 1) + m];
+        } else if (P.bc[shi].kind == BC_PERIODIC) {
+            for (int m = 0; m < 6; ++m) FR[m] = Fp[6 * (n - 1) + m] + Fm[m];
+        } else {
+            boundary_face(P, shi, qc, qc, DIR, FR);
+        }
+        const int cl = pos > 0 ? c - stride : c + (n - 1) * stride;
+        const int cr = pos < n - 1 ? c + stride : c - (n - 1) * stride;
+        double HL[3], HR[3];
+        if (pos > 0) {
+            for (int a = 0; a < 3; ++a) HL[a] = 0.5 * (H[4 * (size_t)c + hoff + a] + H[4 * (size_t)cl + hoff + a]);
+        } else {
+            const int kind = P.bc[slo].kind;
+            for (int a = 0; a < 3; ++a) {
+                const double hc = H[4 * (size_t)c + hoff + a];
+                HL[a] = kind == BC_EXTRAP ? hc : kind == BC_PERIODIC ? 0.5 * (hc + H[4 * (size_t)cl + hoff + a]) : 0.5 * hc;
+            }
+        }
+        if (pos < n - 1) {
+            for (int a = 0; a < 3; ++a) HR[a] = 0.5 * (H[4 * (size_t)cr + hoff + a] + H[4 * (size_t)c + hoff + a]);
+        } else {
+            const int kind = P.bc[shi].kind;
+            for (int a = 0; a < 3; ++a) {
+                const double hc = H[4 * (size_t)c + hoff + a];
+                HR[a] = kind == BC_EXTRAP ? hc : kind == BC_PERIODIC ? 0.5 * (H[4 * (size_t)cr + hoff + a] + hc) : 0.5 * hc;
+            }
+        }
+        double qo[6];
+        for (int m = 0; m < 6; ++m) qo[m] = qc[m] - P.dt / h * (FR[m] - FL[m]);
+        for (int a = 0; a < 3; ++a) qo[3 + a] -= P.dt * (HR[a] - HL[a]) / h;
+        if (DIR == 1) {
+            collide(P, qo);
+            if (q_bad(qo)) atomicMin(flag, step + 1);
+        }
+        for (int m = 0; m < 6; ++m) Qout[6 * (size_t)c + m] = qo[m];
+    }
+}
+
 // g-moments for diagnostics: dv sum (1, v1, v2, |v|^2/2) G and
 // eps dv sum ((w1^2 - w2^2)/2, w1 w2, |w|^2/2) G per cell
 template <typename TG>
@@ -733,9 +836,18 @@ void launch_micro_ref2d(const double *G, double *Gs, double *Gn, double *H, cons
 void launch_macro2d(double *Q, double *Qs, const double *H, int *flag, int step, const Params &P, hipStream_t st)
 {
     const int n = P.nx * P.ny;
-    // four lanes per cell
-    hipLaunchKernelGGL(k_macro2d<0>, dim3((4 * n + 255) / 256), dim3(256), 0, st, Q, H, Qs, flag, step, P);
-    hipLaunchKernelGGL(k_macro2d<1>, dim3((4 * n + 255) / 256), dim3(256), 0, st, Qs, H, Q, flag, step, P);
+    // one workgroup per line where a line fits MACRO_LINE cells, else four lanes per cell
+    const auto line_grid = [](int nline) { return dim3(((nline + 7) / 8) * 8); };
+    if (P.nx <= MACRO_LINE)
+        hipLaunchKernelGGL(k_macro_line<0>, line_grid(P.ny), dim3(256), 12 * sizeof(double) * P.nx, st, Q, H, Qs,
+                           flag, step, P);
+    else
+        hipLaunchKernelGGL(k_macro2d<0>, dim3((4 * n + 255) / 256), dim3(256), 0, st, Q, H, Qs, flag, step, P);
+    if (P.ny <= MACRO_LINE)
+        hipLaunchKernelGGL(k_macro_line<1>, line_grid(P.nx), dim3(256), 12 * sizeof(double) * P.ny, st, Qs, H, Q,
+                           flag, step, P);
+    else
+        hipLaunchKernelGGL(k_macro2d<1>, dim3((4 * n + 255) / 256), dim3(256), 0, st, Qs, H, Q, flag, step, P);
 }
 
 void launch_wall_relax2d(void *Gn, int g_bytes, double *H, const double *rec, const double *wrec, const Params &P,

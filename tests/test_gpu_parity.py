@@ -124,6 +124,19 @@ def test_small_2d_reference_pass(name):
     parity(p, Q, G, 30, label=name + "_ref", reference=True)
 
 
+@pytest.mark.parametrize("gen", ["walls", "periodic"])
+@pytest.mark.parametrize("shape", [(520, 3), (3, 520)])
+def test_long_lines_macro(shape, gen):
+    """Lines of more than 512 cells along a sweep take the four-lanes-per-cell macro
+    kernel; the other direction takes the one-workgroup-per-line kernel."""
+    nx, ny = shape
+    if gen == "walls":
+        p, Q, G = W.quadrant2d(seed=16, nx=nx, ny=ny, nv=8, eps=0.1)
+    else:
+        p, Q, G = W.smooth2d(seed=17, nx=nx, ny=ny, nv=8, eps=0.05)
+    parity(p, Q, G, 10, label=f"long_{gen}_{nx}x{ny}")
+
+
 def test_large_velocity_grid_uses_reference_pass():
     """nv1 > 64 is outside the fused pass; the library falls back to the unfused pass."""
     p, Q, G = W.quadrant2d(seed=15, nx=6, ny=5, nv=12, eps=0.1)
