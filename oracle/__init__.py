@@ -67,6 +67,7 @@ def lib():
         L.o_run2d.argtypes = [cp, dp, dp, C.c_int, dp, ip]
         L.o_run1d.argtypes = [cp, dp, dp, C.c_int, dp, ip]
         L.o_mms1d.argtypes = [cp, C.c_double, dp]
+        L.o_mms2d.argtypes = [cp, C.c_double, dp]
         L.o_micro2d.argtypes = [cp, dp, dp, dp]
         L.o_macro2d.argtypes = [cp, dp, dp]
         L.o_ghat2d.argtypes = [cp, dp, dp]
@@ -181,6 +182,16 @@ def mms1d(p, t_final):
     rc = lib().o_mms1d(C.byref(cfg(p)), float(t_final), _dp(e))
     if rc:
         raise RuntimeError(f"o_mms1d failed ({rc})")
+    return float(e[0]), float(e[1])
+
+
+def mms2d(p, t_final):
+    """The 2D manufactured-solution run of the convergence study (Sec. 6.2, tab5-4)
+    on the grid of p (periodic in x and y): (macro, micro) relative L2 errors at t_final."""
+    e = np.zeros(2)
+    rc = lib().o_mms2d(C.byref(cfg(p)), float(t_final), _dp(e))
+    if rc:
+        raise RuntimeError(f"o_mms2d failed ({rc})")
     return float(e[0]), float(e[1])
 
 

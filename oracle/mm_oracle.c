@@ -22,7 +22,8 @@
  *                                 (macro2d-split1..4) with TR-BDF2 collision and
  *                                 KFVS fluxes (flux-2D-1/2); boundary conditions
  *                                 of Sec. 5.3.1-5.3.2, 5.4.1-5.4.2 and the
- *                                 diffuse (moving) walls of Sec. 6.3.
+ *                                 diffuse (moving) walls of Sec. 6.3; the
+ *                                 manufactured-solution run of Sec. 6.2.
  *
  * Readings taken where the paper is garbled or silent (each listed in the
  * design notes of the repository):
@@ -42,10 +43,11 @@
  *     y-ghosts from Q**.
  *   - "Inflow" sides: a fixed ghost Maxwellian (rho, u, T), micro ghost g = 0,
  *     wall machinery otherwise.
- *   - Manufactured solution (Sec. 3.4): the tau inside the residual S is the
- *     cell's tau_i^n, the one that divides S in G-hat; S and the macro source
- *     are taken at t^n and the cell centre; the initial Q and G are the exact
- *     point values at cell centres.
+ *   - Manufactured solutions: S and the macro sources are taken at t^n and the
+ *     cell centre, and the initial Q and G are exact point values at cell
+ *     centres.  The tau inside S: the cell's tau_i^n in the 1D study (Sec. 3.4),
+ *     that of the exact state in the 2D study (Sec. 6.2); each is the reading
+ *     closer to the printed table of that study.
  *
  * Velocity sums are Neumaier-compensated and run k fastest, then l.
  */
@@ -538,8 +540,91 @@ static void hflux2d(const o_cfg *c, const o_grid *g, const o_prim *P, const doub
  * eqn5-98), then H^{n+1} (eqn5-99) with u^n.  prim holds the state of Q^n.
  * G is overwritten with G^{n+1}; Gs is scratch of the same size.
  */
+/* Manufactured-solution source of the 2D convergence study (Sec. 6.2): the
+ * invented f = A(v) B(t, x, y) with A = e^{-|v - (1,1)|^2} + 2 e^{-|v + (1,1)|^2},
+ * B = 2 - sin 2 pi (t - x) cos 2 pi (t - y).  Its moments give
+ * Q = pi B (3, -1, -1, 9/2, 3, 9/2), i.e. rho = 3 pi B, u = -(1,1)/3 and the
+ * pressure tensor pi B (25/6, 8/3, 25/6).  Its residual
+ *   S = f_t + v.grad f - (tau / eps)(calG - f)
+ * enters G-hat as (1/tau_ij^n)(I - Pi)[S] at t^n, and the macro step, between the
+ * y-sweep and the second collision half step, as dt times the exact velocity
+ * integrals of (1, v1, v2, v1^2, v1 v2, v2^2) S.  calG is the ES Gaussian of
+ * f's moments.  S is a function of (t, x, v) of the invented solution alone: its
+ * tau is that of the exact state; only the prefactor 1/tau_ij^n is the cell's. */
+typedef struct { double t; } o_mms2;
+
+static double mms2_A(double v1, double v2)
+{
+    return exp(-(v1 - 1.0) * (v1 - 1.0) - (v2 - 1.0) * (v2 - 1.0)) +
+           2.0 * exp(-(v1 + 1.0) * (v1 + 1.0) - (v2 + 1.0) * (v2 + 1.0));
+}
+static double mms2_B(double t, double x, double y)
+{
+    return 2.0 - sin(2.0 * O_PI * (t - x)) * cos(2.0 * O_PI * (t - y));
+}
+/* B_x and B_y (B_t = -(B_x + B_y)) */
+static void mms2_dB(double t, double x, double y, double *Bx, double *By)
+{
+    *Bx = 2.0 * O_PI * cos(2.0 * O_PI * (t - x)) * cos(2.0 * O_PI * (t - y));
+    *By = -2.0 * O_PI * sin(2.0 * O_PI * (t - x)) * sin(2.0 * O_PI * (t - y));
+}
+/* conserved moments of f at (t, x, y) */
+static void mms2_q(double t, double x, double y, double q[6])
+{
+    const double pB = O_PI * mms2_B(t, x, y);
+    q[0] = 3.0 * pB; q[1] = -pB; q[2] = -pB; q[3] = 4.5 * pB; q[4] = 3.0 * pB; q[5] = 4.5 * pB;
+}
+/* int v1^a v2^b A dv (a + b <= 3): each Gaussian term factors into 1D moments
+ * of a normal variable with mean c and variance 1/2 */
+static double mms2_momA(int a, int b)
+{
+    const double cs[2] = {1.0, -1.0}, ws[2] = {1.0, 2.0};
+    double s = 0.0;
+    for (int n = 0; n < 2; ++n) {
+        double m[4], c = cs[n];
+        m[0] = 1.0; m[1] = c; m[2] = c * c + 0.5; m[3] = c * c * c + 1.5 * c;
+        s += ws[n] * O_PI * m[a] * m[b];
+    }
+    return s;
+}
+/* S at the nodes of cell (x, y) at time t */
+static void mms2_S_nodes(const o_cfg *c, const o_grid *g, double t, double x, double y, double *S)
+{
+    double q[6], Bx, By;
+    o_prim Pe;
+    mms2_q(t, x, y, q);
+    prim2d(c, q, &Pe);
+    mms2_dB(t, x, y, &Bx, &By);
+    const double B = mms2_B(t, x, y);
+    for (int l = 0; l < g->nv2; ++l)
+        for (int k = 0; k < g->nv1; ++k) {
+            const double v1 = g->v1[k], v2 = g->v2[l], A = mms2_A(v1, v2);
+            S[l * g->nv1 + k] = A * ((v1 - 1.0) * Bx + (v2 - 1.0) * By) - Pe.tau / c->eps * (gauss2d(&Pe, v1, v2) - A * B);
+        }
+}
+/* int (1, v1, v2, v1^2, v1 v2, v2^2) S dv at (t, x, y): the transport part from
+ * moments of A; the collision part has int v v (calG - f) = rho calT - P (zero
+ * for the conserved moments) */
+static void mms2_S_moments(const o_cfg *c, double t, double x, double y, double out[6])
+{
+    static const int ex[6][2] = {{0, 0}, {1, 0}, {0, 1}, {2, 0}, {1, 1}, {0, 2}};
+    double q[6], Bx, By;
+    o_prim Pe;
+    mms2_q(t, x, y, q);
+    prim2d(c, q, &Pe);
+    mms2_dB(t, x, y, &Bx, &By);
+    const double coll[6] = {0.0, 0.0, 0.0, Pe.rho * Pe.S11 - Pe.P11, Pe.rho * Pe.S12 - Pe.P12,
+                            Pe.rho * Pe.S22 - Pe.P22};
+    for (int r = 0; r < 6; ++r) {
+        const int a = ex[r][0], b = ex[r][1];
+        const double m0 = mms2_momA(a, b);
+        out[r] = Bx * (mms2_momA(a + 1, b) - m0) + By * (mms2_momA(a, b + 1) - m0) - Pe.tau / c->eps * coll[r];
+    }
+}
+
 static void micro2d(const o_cfg *c, const o_grid *g, const o_prim *prim,
-                    double *G, double *Gs, double *H, double dt)
+                    double *G, double *Gs, double *H, double dt,
+                    const o_mms2 *mms)
 {
     int nv = g->nv;
     micro_sweep2d(c, g, prim, G, Gs, 0, dt);   /* G^n -> G*   */
@@ -557,6 +642,12 @@ static void micro2d(const o_cfg *c, const o_grid *g, const o_prim *prim,
                 const o_prim *P = &prim[cc];
                 maxw_table2d(g, P, Mx);
                 ghat2d(c, g, prim, i, j, Mx, Gh, t1, t2);
+                if (mms) {
+                    const double x = c->x_lo + (i + 0.5) * g->dx, y = c->y_lo + (j + 0.5) * g->dy;
+                    mms2_S_nodes(c, g, mms->t, x, y, t2);
+                    project2d(c, g, P, Mx, t2, t1);
+                    for (int p = 0; p < nv; ++p) Gh[p] += (t2[p] - t1[p]) / P->tau;
+                }
                 double a = c->eps / (c->eps + dt * P->tau);
                 double b = dt * P->tau / (c->eps + dt * P->tau);
                 double *Gc = G + cc * nv;
@@ -748,12 +839,22 @@ static void macro_sweep2d(const o_cfg *c, const o_grid *g, const double *Qin, do
 }
 
 /* Macro step (Sec. 5.4): Q^n -> Q* -> Q** -> Q*** -> Q^{n+1}; returns the number of non-physical cells */
-static int macro2d(const o_cfg *c, const o_grid *g, double *Q, double *Qt, const double *H, double dt)
+static int macro2d(const o_cfg *c, const o_grid *g, double *Q, double *Qt, const double *H, double dt,
+                   const o_mms2 *mms)
 {
     size_t ncell = (size_t)g->nx * g->ny;
     for (size_t cc = 0; cc < ncell; ++cc) collide2d(c, Q + 6 * cc, dt);
     macro_sweep2d(c, g, Q, Qt, H, 0, dt);
     macro_sweep2d(c, g, Qt, Q, H, 1, dt);
+    if (mms) {   /* the source step between the y-sweep and the second half step */
+        for (int j = 0; j < g->ny; ++j)
+            for (int i = 0; i < g->nx; ++i) {
+                const size_t cc = cidx(g, i, j);
+                double src[6];
+                mms2_S_moments(c, mms->t, c->x_lo + (i + 0.5) * g->dx, c->y_lo + (j + 0.5) * g->dy, src);
+                for (int r = 0; r < 6; ++r) Q[6 * cc + r] += dt * src[r];
+            }
+    }
     int bad = 0;
     for (size_t cc = 0; cc < ncell; ++cc) {
         collide2d(c, Q + 6 * cc, dt);
@@ -802,12 +903,84 @@ int o_run2d(const o_cfg *c, double *Q, double *G, int nsteps, double *H, int *fa
     }
     for (int s = 0; s < nsteps; ++s) {
         for (size_t cc = 0; cc < ncell; ++cc) prim2d(c, Q + 6 * cc, &prim[cc]);
-        micro2d(c, &g, prim, G, Gs, Hn, dt);
-        if (macro2d(c, &g, Q, Qt, Hn, dt)) { rc = O_ENONPHYS; if (failed_step) *failed_step = s + 1; break; }
+        micro2d(c, &g, prim, G, Gs, Hn, dt, NULL);
+        if (macro2d(c, &g, Q, Qt, Hn, dt, NULL)) { rc = O_ENONPHYS; if (failed_step) *failed_step = s + 1; break; }
     }
     if (H) memcpy(H, Hn, sizeof(double) * ncell * 4);
 done:
     free(prim); free(Gs); free(Hn); free(Qt);
+    grid_free(&g);
+    return rc;
+}
+
+/* The manufactured-solution run of the 2D convergence study (Sec. 6.2, tab5-4)
+ * on the grid of c (periodic in x and y): exact point values at cell centres
+ * and nodes at t = 0 (g = (f - M)/eps with M the Maxwellian of f's moments),
+ * steps of the CFL rule of c reset to land on t_final, the source terms above.
+ * errs receives the relative L2 errors of Q = (rho, rho u, E) and of G against
+ * the exact solution at t_final.  Returns O_OK or an error code. */
+int o_mms2d(const o_cfg *c, double t_final, double errs[2])
+{
+    if (cfg_check(c) || c->dim != 2) return O_EINVAL;
+    o_grid g;
+    if (grid_make(c, &g)) return O_ENOMEM;
+    const size_t ncell = (size_t)g.nx * g.ny, nv = g.nv;
+    int rc = O_OK;
+    double *Q = malloc(sizeof(double) * 6 * ncell), *G = malloc(sizeof(double) * ncell * nv);
+    double *Gs = malloc(sizeof(double) * ncell * nv), *Hn = calloc(4 * ncell, sizeof(double));
+    double *Qt = malloc(sizeof(double) * 6 * ncell);
+    o_prim *prim = malloc(sizeof(o_prim) * ncell);
+    if (!Q || !G || !Gs || !Hn || !Qt || !prim) { rc = O_ENOMEM; goto done; }
+    /* exact g at time t of cell cc into out */
+#define MMS2_G(t, cc, out)                                                                           \
+    do {                                                                                             \
+        const int ii = (int)((cc) % g.nx), jj = (int)((cc) / g.nx);                                  \
+        const double xx = c->x_lo + (ii + 0.5) * g.dx, yy = c->y_lo + (jj + 0.5) * g.dy;             \
+        double qe[6];                                                                                \
+        o_prim Pe;                                                                                   \
+        mms2_q(t, xx, yy, qe);                                                                       \
+        prim2d(c, qe, &Pe);                                                                          \
+        const double B = mms2_B(t, xx, yy);                                                          \
+        for (int l = 0; l < g.nv2; ++l)                                                              \
+            for (int k = 0; k < g.nv1; ++k)                                                          \
+                (out)[l * g.nv1 + k] = (mms2_A(g.v1[k], g.v2[l]) * B -                               \
+                                        maxw2d(Pe.rho, Pe.u1, Pe.u2, Pe.T, g.v1[k], g.v2[l])) / c->eps; \
+    } while (0)
+    for (size_t cc = 0; cc < ncell; ++cc) {
+        mms2_q(0.0, c->x_lo + (cc % g.nx + 0.5) * g.dx, c->y_lo + (cc / g.nx + 0.5) * g.dy, Q + 6 * cc);
+        MMS2_G(0.0, cc, G + cc * nv);
+    }
+    int nsteps = 0;
+    const double dt = o_dt(c, t_final, &nsteps);
+    for (int s = 0; s < nsteps; ++s) {
+        o_mms2 m = {s * dt};
+        for (size_t cc = 0; cc < ncell; ++cc) prim2d(c, Q + 6 * cc, &prim[cc]);
+        micro2d(c, &g, prim, G, Gs, Hn, dt, &m);
+        if (macro2d(c, &g, Q, Qt, Hn, dt, &m)) { rc = O_ENONPHYS; break; }
+    }
+    if (rc == O_OK) {
+        ksum eq = {0}, nq = {0}, eg = {0}, ng = {0};
+        double *ge = Gs;   /* scratch */
+        for (size_t cc = 0; cc < ncell; ++cc) {
+            double qe[6];
+            mms2_q(t_final, c->x_lo + (cc % g.nx + 0.5) * g.dx, c->y_lo + (cc / g.nx + 0.5) * g.dy, qe);
+            for (int r = 0; r < 6; ++r) {
+                kadd(&eq, (Q[6 * cc + r] - qe[r]) * (Q[6 * cc + r] - qe[r]));
+                kadd(&nq, qe[r] * qe[r]);
+            }
+            MMS2_G(t_final, cc, ge);
+            for (size_t p = 0; p < nv; ++p) {
+                const double d = G[cc * nv + p] - ge[p];
+                kadd(&eg, d * d);
+                kadd(&ng, ge[p] * ge[p]);
+            }
+        }
+        errs[0] = sqrt(kval(&eq) / kval(&nq));
+        errs[1] = sqrt(kval(&eg) / kval(&ng));
+    }
+#undef MMS2_G
+done:
+    free(Q); free(G); free(Gs); free(Hn); free(Qt); free(prim);
     grid_free(&g);
     return rc;
 }
@@ -822,7 +995,7 @@ int o_micro2d(const o_cfg *c, const double *Q, double *G, double *H)
     o_prim *prim = malloc(sizeof(o_prim) * ncell);
     double *Gs = malloc(sizeof(double) * ncell * g.nv);
     for (size_t cc = 0; cc < ncell; ++cc) prim2d(c, Q + 6 * cc, &prim[cc]);
-    micro2d(c, &g, prim, G, Gs, H, step_dt(c));
+    micro2d(c, &g, prim, G, Gs, H, step_dt(c), NULL);
     free(prim); free(Gs);
     grid_free(&g);
     return O_OK;
@@ -836,7 +1009,7 @@ int o_macro2d(const o_cfg *c, double *Q, const double *H)
     if (grid_make(c, &g)) return O_ENOMEM;
     size_t ncell = (size_t)g.nx * g.ny;
     double *Qt = malloc(sizeof(double) * ncell * 6);
-    int bad = macro2d(c, &g, Q, Qt, H, step_dt(c));
+    int bad = macro2d(c, &g, Q, Qt, H, step_dt(c), NULL);
     free(Qt);
     grid_free(&g);
     return bad ? O_ENONPHYS : O_OK;
