@@ -579,23 +579,21 @@ __global__ __launch_bounds__(256) void k_macro2d(const double *__restrict__ Qin,
 
 // The same sweep with one workgroup per line of cells along the sweep (a row
 // for dir 0, a column for dir 1; lines of at most MACRO_LINE cells).  Each cell
-// is collided once and its two half fluxes F+ and F- (which share a, b, J and K)
-// are formed once into LDS; the faces are then F+ (low cell) + F- (high cell),
-// the wrap for a periodic side, or the boundary face of the edge cell.  The
-// four-lane form above repeats the collision and the half fluxes of a cell up to
-// five times, which made it bound by FP64 arithmetic.
+// is collided and its two half fluxes are formed once, F+ by an even lane and
+// F- by the odd lane next to it, into LDS; the faces are then F+ (low cell) +
+// F- (high cell), the wrap for a periodic side, or the boundary face of the
+// edge cell, and the even lane updates the cell.  The heat-flux values a cell
+// needs are loaded before the flux work so their latency overlaps it.  (The
+// four-lane form above repeats the collision and the half fluxes of a cell up
+// to five times, which made it bound by FP64 arithmetic.)
 constexpr int MACRO_LINE = 512;   // 48 KB of LDS per workgroup at most
-
-__device__ __forceinline__ void kfvs_pair(const double q[6], int d, double Fp[6], double Fm[6])
-{
-    kfvs_half(q, d, 1.0, Fp);
-    kfvs_half(q, d, -1.0, Fm);
-}
+constexpr int MACRO_THREADS = 512;
 
 template <int DIR>
-__global__ __launch_bounds__(256) void k_macro_line(const double *__restrict__ Qin, const double *__restrict__ H,
-                                                    double *__restrict__ Qout, int *__restrict__ flag, int step,
-                                                    Params P)
+__global__ __launch_bounds__(MACRO_THREADS) void k_macro_line(const double *__restrict__ Qin,
+                                                              const double *__restrict__ H,
+                                                              double *__restrict__ Qout, int *__restrict__ flag,
+                                                              int step, Params P)
 {
     extern __shared__ double s_f[];   // [2][n][6]: F+ and F- of every cell of the line
     const int n = DIR == 0 ? P.nx : P.ny;
@@ -609,27 +607,37 @@ __global__ __launch_bounds__(256) void k_macro_line(const double *__restrict__ Q
     const int slo = DIR == 0 ? 0 : 2, shi = DIR == 0 ? 1 : 3;
     const double h = DIR == 0 ? P.dx : P.dy;
     const int hoff = DIR == 0 ? 0 : 1;
+    const bool odd = (threadIdx.x & 1) != 0;
     double *Fp = s_f, *Fm = s_f + 6 * n;
-    constexpr int CPT = MACRO_LINE / 256;   // cells per thread
-    double qs[CPT][6];
+    constexpr int CPT = MACRO_LINE / (MACRO_THREADS / 2);   // cells per lane pair
+    double qs[CPT][6], hc[CPT][3], hl[CPT][3], hr[CPT][3];
 #pragma unroll
     for (int u = 0; u < CPT; ++u) {
-        const int pos = threadIdx.x + 256 * u;
+        const int pos = (threadIdx.x >> 1) + (MACRO_THREADS / 2) * u;
         if (pos >= n) break;
-        load_q(Qin, base + pos * stride, qs[u]);
-        if (DIR == 0) collide(P, qs[u]);
-        double a[6], b[6];
-        kfvs_pair(qs[u], DIR, a, b);
-#pragma unroll
-        for (int m = 0; m < 6; ++m) {
-            Fp[6 * pos + m] = a[m];
-            Fm[6 * pos + m] = b[m];
+        const int c = base + pos * stride;
+        const int cl = pos > 0 ? c - stride : c + (n - 1) * stride;
+        const int cr = pos < n - 1 ? c + stride : c - (n - 1) * stride;
+        load_q(Qin, c, qs[u]);
+        if (!odd) {
+            for (int a = 0; a < 3; ++a) {
+                hc[u][a] = H[4 * (size_t)c + hoff + a];
+                hl[u][a] = H[4 * (size_t)cl + hoff + a];
+                hr[u][a] = H[4 * (size_t)cr + hoff + a];
+            }
         }
+        if (DIR == 0) collide(P, qs[u]);
+        double F[6];
+        kfvs_half(qs[u], DIR, odd ? -1.0 : 1.0, F);
+        double *dst = odd ? Fm : Fp;
+#pragma unroll
+        for (int m = 0; m < 6; ++m) dst[6 * pos + m] = F[m];
     }
     __syncthreads();
+    if (odd) return;
 #pragma unroll
     for (int u = 0; u < CPT; ++u) {
-        const int pos = threadIdx.x + 256 * u;
+        const int pos = (threadIdx.x >> 1) + (MACRO_THREADS / 2) * u;
         if (pos >= n) break;
         const int c = base + pos * stride;
         const double *qc = qs[u];
@@ -648,26 +656,20 @@ __global__ __launch_bounds__(256) void k_macro_line(const double *__restrict__ Q
         } else {
             boundary_face(P, shi, qc, qc, DIR, FR);
         }
-        const int cl = pos > 0 ? c - stride : c + (n - 1) * stride;
-        const int cr = pos < n - 1 ? c + stride : c - (n - 1) * stride;
         double HL[3], HR[3];
         if (pos > 0) {
-            for (int a = 0; a < 3; ++a) HL[a] = 0.5 * (H[4 * (size_t)c + hoff + a] + H[4 * (size_t)cl + hoff + a]);
+            for (int a = 0; a < 3; ++a) HL[a] = 0.5 * (hc[u][a] + hl[u][a]);
         } else {
             const int kind = P.bc[slo].kind;
-            for (int a = 0; a < 3; ++a) {
-                const double hc = H[4 * (size_t)c + hoff + a];
-                HL[a] = kind == BC_EXTRAP ? hc : kind == BC_PERIODIC ? 0.5 * (hc + H[4 * (size_t)cl + hoff + a]) : 0.5 * hc;
-            }
+            for (int a = 0; a < 3; ++a)
+                HL[a] = kind == BC_EXTRAP ? hc[u][a] : kind == BC_PERIODIC ? 0.5 * (hc[u][a] + hl[u][a]) : 0.5 * hc[u][a];
         }
         if (pos < n - 1) {
-            for (int a = 0; a < 3; ++a) HR[a] = 0.5 * (H[4 * (size_t)cr + hoff + a] + H[4 * (size_t)c + hoff + a]);
+            for (int a = 0; a < 3; ++a) HR[a] = 0.5 * (hr[u][a] + hc[u][a]);
         } else {
             const int kind = P.bc[shi].kind;
-            for (int a = 0; a < 3; ++a) {
-                const double hc = H[4 * (size_t)c + hoff + a];
-                HR[a] = kind == BC_EXTRAP ? hc : kind == BC_PERIODIC ? 0.5 * (H[4 * (size_t)cr + hoff + a] + hc) : 0.5 * hc;
-            }
+            for (int a = 0; a < 3; ++a)
+                HR[a] = kind == BC_EXTRAP ? hc[u][a] : kind == BC_PERIODIC ? 0.5 * (hr[u][a] + hc[u][a]) : 0.5 * hc[u][a];
         }
         double qo[6];
         for (int m = 0; m < 6; ++m) qo[m] = qc[m] - P.dt / h * (FR[m] - FL[m]);
@@ -839,13 +841,13 @@ void launch_macro2d(double *Q, double *Qs, const double *H, int *flag, int step,
     // one workgroup per line where a line fits MACRO_LINE cells, else four lanes per cell
     const auto line_grid = [](int nline) { return dim3(((nline + 7) / 8) * 8); };
     if (P.nx <= MACRO_LINE)
-        hipLaunchKernelGGL(k_macro_line<0>, line_grid(P.ny), dim3(256), 12 * sizeof(double) * P.nx, st, Q, H, Qs,
-                           flag, step, P);
+        hipLaunchKernelGGL(k_macro_line<0>, line_grid(P.ny), dim3(MACRO_THREADS), 12 * sizeof(double) * P.nx, st,
+                           Q, H, Qs, flag, step, P);
     else
         hipLaunchKernelGGL(k_macro2d<0>, dim3((4 * n + 255) / 256), dim3(256), 0, st, Q, H, Qs, flag, step, P);
     if (P.ny <= MACRO_LINE)
-        hipLaunchKernelGGL(k_macro_line<1>, line_grid(P.nx), dim3(256), 12 * sizeof(double) * P.ny, st, Qs, H, Q,
-                           flag, step, P);
+        hipLaunchKernelGGL(k_macro_line<1>, line_grid(P.nx), dim3(MACRO_THREADS), 12 * sizeof(double) * P.ny, st,
+                           Qs, H, Q, flag, step, P);
     else
         hipLaunchKernelGGL(k_macro2d<1>, dim3((4 * n + 255) / 256), dim3(256), 0, st, Qs, H, Q, flag, step, P);
 }
