@@ -25,7 +25,10 @@ namespace {
 
 using namespace fused;
 
-template <typename TS, typename TC, int NPT, bool CL>
+// SYM: the v2 grid is symmetric about 0 with nv2 / 2 a multiple of 64 / nv1, so
+// node m of every lane has v2 < 0 exactly when m < NPT / 2 and the y-upwind side
+// is known when the kernel is compiled (checked on the host at launch)
+template <typename TS, typename TC, int NPT, bool CL, bool SYM>
 struct PassLK {
     // FP64: cell records are loaded rows ahead into VGPRs (one wavefront per SIMD
     // has the registers); FP32 keeps two wavefronts per SIMD and reads them in place
@@ -178,7 +181,12 @@ struct PassLK {
     // |v2| / dy (G(j) - G(upwind)) (the same value)
     __device__ __forceinline__ TC zy(int m, TC w, const TC (&lo)[NPT], const TC (&ce)[NPT], const TC (&hi)[NPT]) const
     {
-        return (fabs(w) * idy) * (ce[m] - (w < (TC)0 ? hi[m] : lo[m]));
+        if constexpr (SYM) {
+            if (m < NPT / 2) return (-w * idy) * (ce[m] - hi[m]);
+            return (w * idy) * (ce[m] - lo[m]);
+        } else {
+            return (fabs(w) * idy) * (ce[m] - (w < (TC)0 ? hi[m] : lo[m]));
+        }
     }
 
     // y-sweep of a wall-adjacent cell: G** only.  The wall form of G-hat, the
@@ -418,7 +426,7 @@ struct LKTraits {
     static constexpr int occupancy = big ? MM_LK_OCC64 : 2;
 };
 
-template <typename TS, typename TC, int NPT, bool CL>
+template <typename TS, typename TC, int NPT, bool CL, bool SYM>
 __global__ __launch_bounds__(64 * WPG, (LKTraits<TC, NPT>::occupancy)) void k_fused2d_lk(const TS *__restrict__ G, TS *__restrict__ Gn,
                                                             double *__restrict__ H, const double *__restrict__ rec,
                                                             const double *__restrict__ wrec,
@@ -430,7 +438,7 @@ __global__ __launch_bounds__(64 * WPG, (LKTraits<TC, NPT>::occupancy)) void k_fu
     if (t >= geo.ntiles) return;
     const int cg = t % geo.ncg, sg = t / geo.ncg;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform: cell indices live in SGPRs
-    using Pass = PassLK<TS, TC, NPT, CL>;
+    using Pass = PassLK<TS, TC, NPT, CL, SYM>;
     Pass ps;
     __shared__ TC s_st[Pass::STASH ? WPG * NPT * 64 : 1];
     ps.st = s_st + (Pass::STASH ? wv * NPT * 64 : 0);
@@ -506,15 +514,15 @@ __global__ __launch_bounds__(64 * WPG, (LKTraits<TC, NPT>::occupancy)) void k_fu
     if (j + 1 < j1) ps.template step<1, 2, 0>(j + 1, j1, win, rv);
 }
 
-template <typename TS, typename TC, bool CL>
+template <typename TS, typename TC, bool CL, bool SYM>
 bool launch_lk_t(int npt, const void *G, void *Gn, double *H, const double *rec, const double *wrec,
                  const Params *Pd, const Geom &geo, const uint8_t *cls, hipStream_t st)
 {
     const dim3 grid(((geo.ntiles + 7) / 8) * 8), block(64 * WPG);
 #define MM_CASE(N)                                                                                          \
     case N:                                                                                                 \
-        hipLaunchKernelGGL((k_fused2d_lk<TS, TC, N, CL>), grid, block, 0, st, (const TS *)G, (TS *)Gn, H,   \
-                           rec, wrec, Pd, geo, cls);                                                        \
+        hipLaunchKernelGGL((k_fused2d_lk<TS, TC, N, CL, SYM>), grid, block, 0, st, (const TS *)G, (TS *)Gn,  \
+                           H, rec, wrec, Pd, geo, cls);                                                     \
         return true;
     switch (npt) {
         MM_CASE(1)
@@ -680,6 +688,18 @@ bool launch_wall_lk2d(void *Gn, int g_bytes, double *H, const double *rec, const
 #undef MM_CASE
 }
 
+// The v2 grid is symmetric about 0 and each lane has as many nodes below 0 as
+// above (nv2 / 2 a multiple of L = 64 / nv1): node m of every lane has v2 < 0
+// exactly when m < NPT / 2.  The two middle nodes are checked with a margin of a
+// quarter node spacing, far beyond rounding.
+static bool v2_symmetric_lk(const Params &P)
+{
+    const int L = 64 / P.nv1;
+    if (P.nv2 % (2 * L) != 0) return false;
+    const double below = P.v2_lo + (P.nv2 / 2 - 0.5) * P.dv2, above = P.v2_lo + (P.nv2 / 2 + 0.5) * P.dv2;
+    return below < -0.25 * P.dv2 && above > 0.25 * P.dv2 && fabs(below + above) < 1e-9 * P.dv2;
+}
+
 bool launch_micro_lk2d(const void *G, void *Gn, double *H, const double *rec, const double *wrec,
                        const Params &P, const Params *Pd, int precision, const uint8_t *cls, hipStream_t st)
 {
@@ -694,10 +714,14 @@ bool launch_micro_lk2d(const void *G, void *Gn, double *H, const double *rec, co
         gc.seg = P.ny < 4 ? P.ny : 4;        // at most 61 (one class bit per lane)
         gc.nseg = (P.ny + gc.seg - 1) / gc.seg;
         gc.ntiles = gc.ncg * gc.nseg;
-        return precision != 0 && launch_lk_t<float, float, true>(npt, G, Gn, H, rec, wrec, Pd, gc, cls, st);
+        return precision != 0 && launch_lk_t<float, float, true, false>(npt, G, Gn, H, rec, wrec, Pd, gc, cls, st);
     }
-    return precision == 0 ? launch_lk_t<double, double, false>(npt, G, Gn, H, rec, wrec, Pd, geo, nullptr, st)
-                          : launch_lk_t<float, float, false>(npt, G, Gn, H, rec, wrec, Pd, geo, nullptr, st);
+    // the static y-upwind side is used by the FP32 instance only: in FP64 it raised
+    // the register count past 256 and was slower (timed) for the AGPR copies
+    if (precision != 0 && v2_symmetric_lk(P))
+        return launch_lk_t<float, float, false, true>(npt, G, Gn, H, rec, wrec, Pd, geo, nullptr, st);
+    return precision == 0 ? launch_lk_t<double, double, false, false>(npt, G, Gn, H, rec, wrec, Pd, geo, nullptr, st)
+                          : launch_lk_t<float, float, false, false>(npt, G, Gn, H, rec, wrec, Pd, geo, nullptr, st);
 }
 
 } // namespace mm
