@@ -182,8 +182,13 @@ struct PassLK {
     __device__ __forceinline__ TC zy(int m, TC w, const TC (&lo)[NPT], const TC (&ce)[NPT], const TC (&hi)[NPT]) const
     {
         if constexpr (SYM) {
-            if (m < NPT / 2) return (-w * idy) * (ce[m] - hi[m]);
-            return (w * idy) * (ce[m] - lo[m]);
+            const TC up = m < NPT / 2 ? hi[m] : lo[m];
+            const TC aw = m < NPT / 2 ? -w : w;
+            TC d = ce[m] - up;
+            // FP64: pin the difference where it is used; left free, the compiler
+            // forms the row's differences early and needs more than 256 VGPRs
+            if constexpr (sizeof(TC) == 8) asm volatile("" : "+v"(d));
+            return (aw * idy) * d;
         } else {
             return (fabs(w) * idy) * (ce[m] - (w < (TC)0 ? hi[m] : lo[m]));
         }
@@ -716,10 +721,10 @@ bool launch_micro_lk2d(const void *G, void *Gn, double *H, const double *rec, co
         gc.ntiles = gc.ncg * gc.nseg;
         return precision != 0 && launch_lk_t<float, float, true, false>(npt, G, Gn, H, rec, wrec, Pd, gc, cls, st);
     }
-    // the static y-upwind side is used by the FP32 instance only: in FP64 it raised
-    // the register count past 256 and was slower (timed) for the AGPR copies
-    if (precision != 0 && v2_symmetric_lk(P))
-        return launch_lk_t<float, float, false, true>(npt, G, Gn, H, rec, wrec, Pd, geo, nullptr, st);
+    if (v2_symmetric_lk(P))
+        return precision == 0
+                   ? launch_lk_t<double, double, false, true>(npt, G, Gn, H, rec, wrec, Pd, geo, nullptr, st)
+                   : launch_lk_t<float, float, false, true>(npt, G, Gn, H, rec, wrec, Pd, geo, nullptr, st);
     return precision == 0 ? launch_lk_t<double, double, false, false>(npt, G, Gn, H, rec, wrec, Pd, geo, nullptr, st)
                           : launch_lk_t<float, float, false, false>(npt, G, Gn, H, rec, wrec, Pd, geo, nullptr, st);
 }
