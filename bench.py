@@ -190,8 +190,8 @@ def main():
                          "scales the HBM byte counters of a profiler run)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the solver has no multi-GPU path "
-              "in this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the solver has no multi-GPU path",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch

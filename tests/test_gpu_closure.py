@@ -2,7 +2,7 @@
 features and indicator, the network's forward pass and gradient (bf16 matrix
 cores vs an FP64 evaluation at the same rounding points), the rebuilt micro
 part, two hybrid steps assembled from oracle pieces, and the trained closure
-judged by the full micro solve."""
+checked against the full micro solve."""
 import numpy as np
 import pytest
 
@@ -348,9 +348,9 @@ def trained():
     return net, losses
 
 
-def test_trained_closure_judged_by_micro_solve(trained):
+def test_trained_closure_against_micro_solve(trained):
     """Held-out cavity at eps = 3e-3 (between training values, another seed): macro rel-L1
-    after 100 steps against the FP64 full micro solve (the judge) <= 1e-2 with most cells on
+    after 100 steps against the FP64 full micro solve (the reference) <= 1e-2 with most cells on
     the closure and below the error of the Navier-Stokes-Fourier closure; on held-out
     snapshots, the network's heat flux (the moment that closes the macro system) closer to
     the micro solve than the NSF closure (the method without the network), its stress no
@@ -361,7 +361,7 @@ def test_trained_closure_judged_by_micro_solve(trained):
     assert losses[-1] < 0.5 * losses[0]
     p, Q, G = W.cavity2d(seed=40, nx=64, ny=64, nv=16, eps=3e-3, amp=0.2)
     steps = 100
-    with B.Solver(p, Q, G) as s:                                    # judge: FP64 full solve
+    with B.Solver(p, Q, G) as s:                                    # reference: FP64 full solve
         s.step(steps)
         Qref = s.moments()
     res = {}
@@ -375,7 +375,7 @@ def test_trained_closure_judged_by_micro_solve(trained):
     with B.Solver(dict(p, precision="mixed"), Q, G) as s:
         s.step(steps)
         emix = rel_l1(s.moments(), Qref)
-    log(f"[judge] macro rel-L1 vs FP64 full solve: net {res['net'][0]:.3e} (closure fraction "
+    log(f"[reference] macro rel-L1 vs FP64 full solve: net {res['net'][0]:.3e} (closure fraction "
         f"{res['net'][1]:.2f}), NSF {res['nsf'][0]:.3e}, FP32-storage full solve {emix:.3e}")
     assert res["net"][0] <= 1e-2
     assert res["net"][1] >= 0.5
