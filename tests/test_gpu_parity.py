@@ -63,6 +63,11 @@ LANE_K = {
         lambda: W.smooth2d(seed=26, nx=10, ny=18, eps=0.1, proj_mode="paper"), 32, 16),
     # an asymmetric v2 box: the y-upwind direction is decided per node at run time
     "lk_32x32_asym_v2": lambda: _asym_v2(),
+    # nu = -1 (the paper's value for its 2D studies): the ES tensor 2T I - P/rho at the
+    # edge of admissibility, on a periodic box
+    "lk_32x32_nu_minus1": lambda: W.smooth2d(seed=28, nx=10, ny=11, nv=32, V=6.0, eps=0.08, nu=-1.0),
+    # a small Knudsen number: the ES term (calG - M)/eps is amplified most
+    "lk_32x32_eps_1e-4": lambda: W.cavity2d(seed=29, nx=9, ny=13, nv=32, eps=1e-4, amp=0.1),
 }
 
 
