@@ -20,13 +20,14 @@ __device__ __forceinline__ CellPrim prim_of(const double *q)
 {
     CellPrim c;
     c.rho = q[0];
-    c.u1 = q[1] / q[0];
-    c.u2 = q[2] / q[0];
+    const double ir = 1.0 / q[0];   // one division per cell
+    c.u1 = q[1] * ir;
+    c.u2 = q[2] * ir;
     c.P11 = q[3] - q[1] * c.u1;
     c.P12 = q[4] - q[1] * c.u2;
     c.P22 = q[5] - q[2] * c.u2;
     c.p = 0.5 * (c.P11 + c.P22);
-    c.T = c.p / c.rho;
+    c.T = c.p * ir;
     return c;
 }
 
@@ -81,21 +82,38 @@ __device__ __forceinline__ void spd_inverse4(const double A[4][4], double scale,
 // S[q] = sum_k w_k^q exp(-w_k^2 i2T), q = 0..4, over the nodes w_k = w0 + (k + 1/2) h,
 // k < n.  The Gaussian follows e(k+1) = e(k) r(k), r(k+1) = r(k) kappa (its
 // exponent is quadratic in k), restarted from a direct exponential every 8
-// nodes so the relative error stays within a few tens of ulps.
+// nodes so the relative error stays within a few tens of ulps.  Within a chunk
+// of 8 nodes the sums run over the centred index t = k - 7/2 (exact constants):
+// T_p = sum t^p e, and S_q gains sum_p C(q, p) wc^(q-p) h^p T_p with wc the
+// chunk's centre.
 __device__ inline void gauss_sums(double w0, double h, int n, double i2T, double S[5])
 {
     const double kap = exp(-2.0 * h * h * i2T);
+    const double h2 = h * h, h3 = h2 * h, h4 = h2 * h2;
     for (int k0 = 0; k0 < n; k0 += 8) {
         const double wb = w0 + (k0 + 0.5) * h;
         double e = exp(-wb * wb * i2T), r = exp(-(2.0 * wb + h) * h * i2T);
         const int kn = n - k0 < 8 ? n - k0 : 8;
-        for (int k = 0; k < kn; ++k) {
-            const double w = wb + k * h;
-            double m = e;
-            for (int q = 0; q < 5; ++q) { S[q] += m; m *= w; }
-            e *= r;
-            r *= kap;
+        double T[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            if (k < kn) {
+                const double t = k - 3.5;
+                T[0] += e;
+                T[1] += t * e;
+                T[2] += (t * t) * e;
+                T[3] += (t * t * t) * e;
+                T[4] += (t * t * t * t) * e;
+                e *= r;
+                r *= kap;
+            }
         }
+        const double wc = wb + 3.5 * h, wc2 = wc * wc, wc3 = wc2 * wc;
+        S[0] += T[0];
+        S[1] += wc * T[0] + h * T[1];
+        S[2] += wc2 * T[0] + 2.0 * wc * h * T[1] + h2 * T[2];
+        S[3] += wc3 * T[0] + 3.0 * wc2 * h * T[1] + 3.0 * wc * h2 * T[2] + h3 * T[3];
+        S[4] += wc2 * wc2 * T[0] + 4.0 * wc3 * h * T[1] + 6.0 * wc2 * h2 * T[2] + 4.0 * wc * h3 * T[3] + h4 * T[4];
     }
 }
 
