@@ -311,6 +311,47 @@ int mm_closure_features(mm_ctx *ctx, float *feat_host, float *kn_host, unsigned 
  * (q1, q2, S11, S12, S22) / eps of each cell, as a closure step does. */
 int mm_closure_rebuild(mm_ctx *ctx, const float *out_host, const unsigned char *mask);
 
+/* =====================================================================
+ * Stepping without allocation.
+ *
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  The caller
+ * owns the state in device memory; every intermediate buffer of the step (the
+ * per-cell records, the wall records, the macro half state, H when h_dev is
+ * NULL, the non-physical flag and the device copy of the parameters) lives in
+ * one static device array of the library, MM_NOALLOC_BYTES_PER_CELL bytes per
+ * cell for at most MM_NOALLOC_MAX_CELLS cells (about 39 MB), which every GPU the
+ * library runs this on holds until the process ends.  The call makes no
+ * hipMalloc, hipFree, memset or host-to-device copy.
+ * ===================================================================== */
+#define MM_NOALLOC_MAX_CELLS 65536
+#define MM_NOALLOC_BYTES_PER_CELL 592   /* (6 + 4 + 48 + 16) doubles */
+
+/*
+ * mm_step2d_noalloc -- nsteps steps of the 2D step, as mm_step runs them for an
+ * MM_FP64 or MM_MIXED context of cfg (the fused phase-space pass: nv1 * nv2 a
+ * multiple of 64, up to 1024 nodes in FP64, 2304 with g in FP32).
+ *   q_dev   device Q [ny][nx][6] FP64: Q^n on entry, the result on return.
+ *   g_dev0, g_dev1  two distinct device G buffers [ny][nx][nv2][nv1], FP64
+ *           (MM_FP64) or FP32 (MM_MIXED); g_dev0 holds G^n on entry, and the
+ *           result is in g_dev0 after an even and in g_dev1 after an odd nsteps.
+ *   h_dev   device H [ny][nx][4] FP64 of the last step, or NULL (H stays in the
+ *           static array).
+ *   failed_step  NULL: the work is only enqueued on cfg->stream (NULL: the null
+ *           stream) and the call returns; usable under stream capture.
+ *           Otherwise the call waits for the stream and, as mm_step does,
+ *           returns MM_ENONPHYS with *failed_step the first non-physical step,
+ *           counted from 0 at the start of this call (-1 when none).
+ * Calls on one GPU share its static array, which keeps the last call's contents
+ * (the parameters, flag and H are set afresh by every call): calls that overlap
+ * on one GPU race, whatever their streams.
+ * Errors: MM_EINVAL (bad configuration, dim != 2, another precision, a velocity
+ * grid the fused pass does not take, more than MM_NOALLOC_MAX_CELLS cells, NULL
+ * or equal G buffers), MM_EDEVICE (HIP failure), MM_ENONPHYS.
+ */
+int mm_step2d_noalloc(const mm_config *cfg, double *q_dev, void *g_dev0, void *g_dev1, double *h_dev, int nsteps,
+                      int *failed_step);
+
 #ifdef __cplusplus
 }
 #endif

@@ -24,7 +24,7 @@ EXPORTS = ("mm_init", "mm_step", "mm_step_async", "mm_sync", "mm_moments", "mm_g
            "mm_free", "mm_dt", "mm_failed_step", "mm_strerror", "mm_timing", "mm_timing_get", "mm_device_ptrs",
            "mm_get_g_cells", "mm_mlp_create", "mm_mlp_free", "mm_mlp_fit_norm", "mm_mlp_get", "mm_mlp_set",
            "mm_mlp_forward", "mm_mlp_grad", "mm_mlp_train", "mm_closure_attach", "mm_closure_cells",
-           "mm_closure_snapshot", "mm_closure_features", "mm_closure_rebuild")
+           "mm_closure_snapshot", "mm_closure_features", "mm_closure_rebuild", "mm_step2d_noalloc")
 
 MLP_NPARAM = 5893
 MLP_NNORM = 52
@@ -98,6 +98,7 @@ def _load():
     L.mm_closure_snapshot.argtypes = [vp, C.c_double, C.c_int, vp, vp, C.c_int, C.POINTER(C.c_int)]
     L.mm_closure_features.argtypes = [vp, fp, fp, bp]
     L.mm_closure_rebuild.argtypes = [vp, fp, bp]
+    L.mm_step2d_noalloc.argtypes = [cp, vp, vp, vp, vp, C.c_int, C.POINTER(C.c_int)]
     for name in EXPORTS:
         getattr(L, name)
     return L
@@ -177,6 +178,31 @@ def dt(p, t_final=0.0):
     if d < 0:
         raise MMError(MM_EINVAL, "mm_dt")
     return d, n.value
+
+
+NOALLOC_MAX_CELLS = 65536
+
+
+def step2d_noalloc(p, q, g0, g1, nsteps, h=None, stream=None, device=0, wait=True):
+    """mm_step2d_noalloc on caller-owned device tensors: q float64 [ny, nx, 6] (in/out),
+    g0 / g1 the two G buffers (float64 for fp64, float32 for mixed; g0 holds G^n, the
+    result is in g0 after an even and in g1 after an odd nsteps), h float64 [ny, nx, 4]
+    or None.  wait=False only enqueues; otherwise returns -1 or raises NonPhysical."""
+    import torch
+    gdt = torch.float64 if p.get("precision", "fp64") == "fp64" else torch.float32
+    ncell, nv = p["nx"] * p["ny"], p["nv1"] * p["nv2"]
+    for t, dtp, n in ((q, torch.float64, 6 * ncell), (g0, gdt, nv * ncell), (g1, gdt, nv * ncell),
+                      (h, torch.float64, 4 * ncell)):
+        if t is None:
+            continue
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dtp and t.is_contiguous() and t.numel() == n):
+            raise TypeError("expected contiguous GPU tensors of the configuration's sizes and precisions")
+    fs = C.c_int(-1)
+    rc = _lib.mm_step2d_noalloc(C.byref(config(p, stream, device)), q.data_ptr(), g0.data_ptr(), g1.data_ptr(),
+                                h.data_ptr() if h is not None else None, int(nsteps),
+                                C.byref(fs) if wait else None)
+    _check(rc, "mm_step2d_noalloc")
+    return fs.value
 
 
 class Solver:

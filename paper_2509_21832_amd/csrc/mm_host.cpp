@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -103,6 +104,41 @@ double dt_rule(const mm_config *c)
     const double dy = (c->y_hi - c->y_lo) / c->ny;
     if (c->cfl_rule == MM_CFL_SUM) return c->cfl / (V1 / dx + V2 / dy);
     return c->cfl * std::fmin(dx / V1, dy / V2);
+}
+
+// kernel parameters of a checked configuration
+void build_params(const mm_config *cfg, mm::Params &P)
+{
+    P.nx = cfg->nx;
+    P.ny = cfg->dim == 2 ? cfg->ny : 1;
+    P.nv1 = cfg->nv1;
+    P.nv2 = cfg->dim == 2 ? cfg->nv2 : 1;
+    P.nv = P.nv1 * P.nv2;
+    P.x_lo = cfg->x_lo;
+    P.y_lo = cfg->y_lo;
+    P.v1_lo = cfg->v1_lo;
+    P.v2_lo = cfg->v2_lo;
+    P.dx = (cfg->x_hi - cfg->x_lo) / cfg->nx;
+    P.dy = cfg->dim == 2 ? (cfg->y_hi - cfg->y_lo) / cfg->ny : 1.0;
+    P.dv1 = (cfg->v1_hi - cfg->v1_lo) / cfg->nv1;
+    P.dv2 = cfg->dim == 2 ? (cfg->v2_hi - cfg->v2_lo) / cfg->nv2 : 1.0;
+    P.eps = cfg->eps;
+    P.dt = cfg->dt > 0.0 ? cfg->dt : dt_rule(cfg);
+    P.nu = cfg->nu;
+    P.tau_model = cfg->tau_model;
+    P.tau_coef = cfg->tau_coef;
+    P.proj_mode = cfg->proj_mode;
+    P.wall_es_term = cfg->wall_es_term ? 1 : 0;
+    for (int s = 0; s < 4; ++s) {
+        const mm_bc &b = cfg->bc[s];
+        P.bc[s].kind = (cfg->dim == 1 && s >= 2) ? mm::BC_EXTRAP : b.kind;
+        P.bc[s].T_wall = b.T_wall;
+        P.bc[s].u_wall = b.u_wall;
+        P.bc[s].rho = b.rho;
+        P.bc[s].u1 = b.u1;
+        P.bc[s].u2 = b.u2;
+        P.bc[s].T = b.T;
+    }
 }
 
 // host-side validation of a macro state given to the library
@@ -346,6 +382,70 @@ int finish(mm_ctx *c)
 
 } // namespace
 
+
+// ---------------------------------------------------------------------------
+// Allocation-free stepping (mm_step2d_noalloc).  Every intermediate buffer of
+// the 2D step lives in one static device array per GPU, carved as
+//   [Params | flag | Q half state 6N | H 4N | cell records REC N | wall records WREC N]
+// with N = MM_NOALLOC_MAX_CELLS; each region starts on a 256-byte boundary.
+namespace noalloc {
+
+constexpr size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+constexpr size_t N = MM_NOALLOC_MAX_CELLS;
+constexpr size_t OFF_PARAMS = 0;
+constexpr size_t OFF_FLAG = align256(OFF_PARAMS + sizeof(mm::Params));
+constexpr size_t OFF_QS = align256(OFF_FLAG + sizeof(int));
+constexpr size_t OFF_H = align256(OFF_QS + sizeof(double) * 6 * N);
+constexpr size_t OFF_REC = align256(OFF_H + sizeof(double) * 4 * N);
+constexpr size_t OFF_WREC = align256(OFF_REC + sizeof(double) * mm::REC * N);
+constexpr size_t BYTES = align256(OFF_WREC + sizeof(double) * mm::WREC * N);
+static_assert(MM_NOALLOC_BYTES_PER_CELL == sizeof(double) * (6 + 4 + mm::REC + mm::WREC),
+              "per-cell figure of the header");
+
+constexpr int MAX_DEVICES = 64;
+std::mutex lock;
+void *dev_ptr[MAX_DEVICES] = {};
+
+} // namespace noalloc
+
+// The array itself.  In host code its name is only a stand-in for the symbol:
+// kernels and copies take the device address that hipGetSymbolAddress returns
+// for the current device (noalloc_base).
+static __device__ __align__(256) unsigned char scratch[noalloc::BYTES];
+
+// Parameters, flag and (optionally) H of one call, set on the device by a kernel
+// so that the call records no memset or host-to-device copy.
+__global__ void k_noalloc_setup(mm::Params P, mm::Params *Pd, int *flag, double *H, int nH)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t == 0) {
+        *Pd = P;
+        *flag = INT_MAX;
+    }
+    for (int i = t; i < nH; i += gridDim.x * blockDim.x) H[i] = 0.0;
+}
+
+namespace {
+
+// device address of `scratch` on `device` (made current by the caller); looked up
+// once per device and kept until the process ends
+unsigned char *noalloc_base(int device)
+{
+    if (device < 0 || device >= noalloc::MAX_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> g(noalloc::lock);
+    if (!noalloc::dev_ptr[device]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+            hipGetLastError();
+            return nullptr;
+        }
+        noalloc::dev_ptr[device] = ptr;
+    }
+    return (unsigned char *)noalloc::dev_ptr[device];
+}
+
+} // namespace
+
 extern "C" {
 
 double mm_dt(const mm_config *cfg, double t_final, int *nsteps)
@@ -380,36 +480,7 @@ int mm_init(const mm_config *cfg, const double *q0, const double *g0, mm_ctx **o
         return MM_ENONPHYS;
     }
     mm::Params &P = c->P;
-    P.nx = cfg->nx;
-    P.ny = cfg->dim == 2 ? cfg->ny : 1;
-    P.nv1 = cfg->nv1;
-    P.nv2 = cfg->dim == 2 ? cfg->nv2 : 1;
-    P.nv = c->nv;
-    P.x_lo = cfg->x_lo;
-    P.y_lo = cfg->y_lo;
-    P.v1_lo = cfg->v1_lo;
-    P.v2_lo = cfg->v2_lo;
-    P.dx = (cfg->x_hi - cfg->x_lo) / cfg->nx;
-    P.dy = cfg->dim == 2 ? (cfg->y_hi - cfg->y_lo) / cfg->ny : 1.0;
-    P.dv1 = (cfg->v1_hi - cfg->v1_lo) / cfg->nv1;
-    P.dv2 = cfg->dim == 2 ? (cfg->v2_hi - cfg->v2_lo) / cfg->nv2 : 1.0;
-    P.eps = cfg->eps;
-    P.dt = mm_dt(cfg, 0.0, nullptr);
-    P.nu = cfg->nu;
-    P.tau_model = cfg->tau_model;
-    P.tau_coef = cfg->tau_coef;
-    P.proj_mode = cfg->proj_mode;
-    P.wall_es_term = cfg->wall_es_term ? 1 : 0;
-    for (int s = 0; s < 4; ++s) {
-        const mm_bc &b = cfg->bc[s];
-        P.bc[s].kind = (cfg->dim == 1 && s >= 2) ? mm::BC_EXTRAP : b.kind;
-        P.bc[s].T_wall = b.T_wall;
-        P.bc[s].u_wall = b.u_wall;
-        P.bc[s].rho = b.rho;
-        P.bc[s].u1 = b.u1;
-        P.bc[s].u2 = b.u2;
-        P.bc[s].T = b.T;
-    }
+    build_params(cfg, P);
     c->gbytes = cfg->precision == MM_FP64 ? 8 : 4;
     c->fused = cfg->dim == 2 && mm::fused_supported(P, cfg->precision) && !std::getenv("MM_REFERENCE_PASS");
     if (cfg->dim == 2 && !c->fused && cfg->precision != MM_FP64) {
@@ -724,6 +795,51 @@ int mm_closure_rebuild(mm_ctx *ctx, const float *out_host, const unsigned char *
     hipFree(valid);
     hipFree(vnext);
     return rc;
+}
+
+int mm_step2d_noalloc(const mm_config *cfg, double *q_dev, void *g_dev0, void *g_dev1, double *h_dev, int nsteps,
+                      int *failed_step)
+{
+    if (failed_step) *failed_step = -1;
+    int rc = check_cfg(cfg);
+    if (rc) return rc;
+    if (cfg->dim != 2 || (cfg->precision != MM_FP64 && cfg->precision != MM_MIXED)) return MM_EINVAL;
+    if (!q_dev || !g_dev0 || !g_dev1 || g_dev0 == g_dev1 || nsteps < 0) return MM_EINVAL;
+    if ((long long)cfg->nx * cfg->ny > MM_NOALLOC_MAX_CELLS) return MM_EINVAL;
+    mm::Params P;
+    build_params(cfg, P);
+    if (!mm::fused_supported(P, cfg->precision)) return MM_EINVAL;
+    if (hipSetDevice(cfg->device) != hipSuccess) return MM_EDEVICE;
+    unsigned char *base = noalloc_base(cfg->device);
+    if (!base) return MM_EDEVICE;
+    mm::Params *Pd = (mm::Params *)(base + noalloc::OFF_PARAMS);
+    int *flag = (int *)(base + noalloc::OFF_FLAG);
+    double *Qs = (double *)(base + noalloc::OFF_QS);
+    double *H = h_dev ? h_dev : (double *)(base + noalloc::OFF_H);
+    double *rec = (double *)(base + noalloc::OFF_REC);
+    double *wrec = (double *)(base + noalloc::OFF_WREC);
+    hipStream_t st = (hipStream_t)cfg->stream;
+    const int ncell = cfg->nx * cfg->ny;
+    hipLaunchKernelGGL(k_noalloc_setup, dim3((4 * ncell + 255) / 256), dim3(256), 0, st, P, Pd, flag, H, 4 * ncell);
+    void *G[2] = {g_dev0, g_dev1};
+    int cur = 0;
+    for (int s = 0; s < nsteps; ++s) {
+        mm::launch_prep2d(q_dev, rec, wrec, flag, s, P, st);
+        mm::launch_micro_fused2d(G[cur], G[1 - cur], H, rec, wrec, P, Pd, cfg->precision, st);
+        mm::launch_wall_relax2d(G[1 - cur], cfg->precision == MM_FP64 ? 8 : 4, H, rec, wrec, P, st);
+        mm::launch_macro2d(q_dev, Qs, H, flag, s, P, st);
+        cur = 1 - cur;
+    }
+    if (hipGetLastError() != hipSuccess) return MM_EDEVICE;
+    if (!failed_step) return MM_OK;                 // enqueued only
+    if (hipStreamSynchronize(st) != hipSuccess) return MM_EDEVICE;
+    int f = INT_MAX;
+    if (hipMemcpy(&f, flag, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return MM_EDEVICE;
+    if (f != INT_MAX) {
+        *failed_step = f;
+        return MM_ENONPHYS;
+    }
+    return MM_OK;
 }
 
 } // extern "C"
