@@ -11,9 +11,10 @@
  *
  * What it computes, section by section of the paper:
  *   1D1V (d_x = d_v = 1, BGK):    Sec. 3.2-3.4, eqs. (eqn5-19)-(eqn5-27),
- *                                 KFVS flux (flux1d_1)-(flux1d_2), periodic and
- *                                 extrapolation boundary conditions; the
- *                                 manufactured-solution run of Sec. 3.4.
+ *                                 KFVS flux (flux1d_1)-(flux1d_2), periodic,
+ *                                 extrapolation and diffuse-wall (Sec. 4.3)
+ *                                 boundary conditions; the manufactured-solution
+ *                                 run of Sec. 3.4.
  *   2D2V (d_x = d_v = 2, ES-BGK): Sec. 5.2-5.4: micro operator splitting
  *                                 (micro-2D-split-1..3), upwind Z, projection
  *                                 (zhat-2D-*, coeffs-2D-*), G-hat (eqn5-97),
@@ -39,6 +40,9 @@
  *   - Wall cells keep the ES term (G - M)/eps in G-hat.
  *   - Ghost indices "(N_x, j)", "(i, N_y)" of the wall ghost states are read
  *     as N_x + 1 and N_y + 1.
+ *   - 1D wall interface temperatures: the integral definition of Sec. 4.3
+ *     (second over zeroth moment of the half-and-half distribution); its
+ *     printed closed form has another denominator.
  *   - Wall densities: micro ghosts from Q^n, macro x-ghosts from Q*, macro
  *     y-ghosts from Q**.
  *   - "Inflow" sides: a fixed ghost Maxwellian (rho, u, T), micro ghost g = 0,
@@ -1149,6 +1153,44 @@ static void flux_full1d(const double *q, double *out)
     out[2] = 0.5 * rho * u * (3.0 * T + u * u);
 }
 
+/* Diffuse walls in 1D (Sec. 4.3, wall_bc_1/2).  side 0: the wall at x_lo emits
+ * its Maxwellian into v > 0; side 1: the wall at x_hi into v < 0.  The wall
+ * density makes the mass flux through the wall vanish: the wall's half flux
+ * balances the half flux of the adjacent cell's Maxwellian toward the wall.
+ * Half-range moments of the cell's Maxwellian N(u, T) rho (alpha, beta as in
+ * flux1d_2): int_{v<0} (1, v, v^2) M = rho (beta-, u beta- - alpha,
+ * (T + u^2) beta- - u alpha); int_{v>0} likewise with beta+ and +alpha. */
+static double wall_rho1d(const o_prim1 *P, double T_wall, int side)
+{
+    const double alpha = sqrt(P->T / (2.0 * O_PI)) * exp(-P->u * P->u / (2.0 * P->T));
+    const double e = erf(P->u / sqrt(2.0 * P->T));
+    /* |mass flux of the cell toward the wall| / (flux of a unit-density wall Maxwellian) */
+    const double toward = side == 0 ? alpha - P->u * 0.5 * (1.0 - e) : alpha + P->u * 0.5 * (1.0 + e);
+    return P->rho * toward / sqrt(T_wall / (2.0 * O_PI));
+}
+
+/* Temperature at a wall interface (the formula of Sec. 4.3 as its integral
+ * definition states it): second moment over zeroth moment of the distribution
+ * that is the wall's Maxwellian on the velocities leaving the wall and the
+ * cell's Maxwellian on those entering it. */
+static double wall_T1d(const o_prim1 *P, double T_wall, int side)
+{
+    const double alpha = sqrt(P->T / (2.0 * O_PI)) * exp(-P->u * P->u / (2.0 * P->T));
+    const double e = erf(P->u / sqrt(2.0 * P->T));
+    const double rw = wall_rho1d(P, T_wall, side);
+    double m0, m2;
+    if (side == 0) {            /* cell on v < 0, wall on v > 0 */
+        const double bm = 0.5 * (1.0 - e);
+        m0 = P->rho * bm + 0.5 * rw;
+        m2 = P->rho * ((P->T + P->u * P->u) * bm - P->u * alpha) + 0.5 * rw * T_wall;
+    } else {                    /* cell on v > 0, wall on v < 0 */
+        const double bp = 0.5 * (1.0 + e);
+        m0 = P->rho * bp + 0.5 * rw;
+        m2 = P->rho * ((P->T + P->u * P->u) * bp + P->u * alpha) + 0.5 * rw * T_wall;
+    }
+    return m2 / m0;
+}
+
 /* Manufactured-solution source of the 1D convergence study (Sec. 3.4): the
  * invented f = A(v) B(t, x), A = e^{-(v-1)^2} + 2 e^{-(v+1)^2},
  * B = 2 + sin 2 pi (x - t), whose moments give rho = 3 sqrt(pi) B, u = -1/3,
@@ -1198,6 +1240,9 @@ static int step1d(const o_cfg *c, const o_grid *g, double *Q, double *G, double 
                                : (is_open(c->bc[1].kind) ? zero : Gc);
             double Tm = im >= 0 ? P[im].T : Pi->T, Tp = ip >= 0 ? P[ip].T : Pi->T;
             double Tiph = 0.5 * (Tp + Pi->T), Timh = 0.5 * (Tm + Pi->T);
+            /* wall interfaces: the temperature of the half-and-half distribution (Sec. 4.3) */
+            if (im < 0 && c->bc[0].kind == O_BC_WALL) Timh = wall_T1d(Pi, c->bc[0].T_wall, 0);
+            if (ip < 0 && c->bc[1].kind == O_BC_WALL) Tiph = wall_T1d(Pi, c->bc[1].T_wall, 1);
             double dT = (Tiph - Timh) / (g->dx * Pi->T);
             for (int k = 0; k < nv; ++k) {
                 double v = g->v1[k], w = v - Pi->u;
@@ -1244,6 +1289,23 @@ static int step1d(const o_cfg *c, const o_grid *g, double *Q, double *G, double 
             o_kfvs_half1d(Q + 0, -1, fm);
             for (int r = 0; r < 3; ++r) F[3 * f + r] = fp[r] + fm[r];
             Hf[f] = 0.5 * (Hn[0] + Hn[nx - 1]);
+        } else if (c->bc[f == 0 ? 0 : 1].kind == O_BC_WALL) {
+            /* KFVS between the wall Maxwellian (rho_wall, 0, T_wall) and the edge
+             * cell; H of the ghost is 0, so H_{1/2} = H_1 / 2 (Sec. 4.3) */
+            const int side = f == 0 ? 0 : 1, e = f == 0 ? 0 : nx - 1;
+            o_prim1 Pe;
+            prim1d(c, Q + 3 * e, &Pe);
+            const double Tw = c->bc[side].T_wall, rw = wall_rho1d(&Pe, Tw, side);
+            const double qw[3] = {rw, 0.0, 0.5 * rw * Tw};
+            if (side == 0) {
+                o_kfvs_half1d(qw, +1, fp);
+                o_kfvs_half1d(Q + 3 * e, -1, fm);
+            } else {
+                o_kfvs_half1d(Q + 3 * e, +1, fp);
+                o_kfvs_half1d(qw, -1, fm);
+            }
+            for (int r = 0; r < 3; ++r) F[3 * f + r] = fp[r] + fm[r];
+            Hf[f] = 0.5 * Hn[e];
         } else {
             int e = f == 0 ? 0 : nx - 1;
             flux_full1d(Q + 3 * e, F + 3 * f);
@@ -1325,7 +1387,10 @@ int o_run1d(const o_cfg *c, double *Q, double *G, int nsteps, double *H, int *fa
 {
     if (failed_step) *failed_step = -1;
     if (cfg_check(c) || c->dim != 1) return O_EINVAL;
-    if (is_open(c->bc[0].kind) || is_open(c->bc[1].kind)) return O_EINVAL;
+    if (c->bc[0].kind == O_BC_INFLOW || c->bc[1].kind == O_BC_INFLOW) return O_EINVAL;
+    if ((c->bc[0].kind == O_BC_WALL && !(c->bc[0].T_wall > 0.0)) ||
+        (c->bc[1].kind == O_BC_WALL && !(c->bc[1].T_wall > 0.0)))
+        return O_EINVAL;
     o_grid g;
     if (grid_make(c, &g)) return O_ENOMEM;
     int nx = g.nx, nv = g.nv1, rc = O_OK;
