@@ -9,8 +9,17 @@ snapshots of the solver's own runs) on the same workload, each form's
 macro-moment error against the FP64 oracle after 100 steps, the phase-space
 pass's HBM roofline fraction, and the oracle timed on the host cores.
 
+Beside the headline the line carries `sweeps`: the same step timed on the
+cavity box at every Knudsen number of its sweep (FP64 and g in FP32), on the
+512 x 512 x 48 x 48 Gaussian blast (g in FP32, and FP64 for the speedup), and
+in the learned-closure form at three Knudsen numbers, each with its error
+against a stored oracle result and its phase-space pass against the roofline.
+
+Every timed form first runs at least 200 ms of warm-up steps (and at least W
+steps), so clocks and caches are in their steady state.
+
 Prints one JSON line.  Usage:
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--forms fp64,mixed,closure] [--no-cpu]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--forms fp64,mixed,closure] [--no-cpu] [--no-sweep]
 """
 import argparse
 import hashlib
@@ -28,6 +37,8 @@ import mm_workloads as W  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0     # MI355X HBM3E
 GOLDEN = os.path.join(ROOT, "tests", "golden", "c3_cavity_100steps.npz")
+GOLDEN_C4 = os.path.join(ROOT, "tests", "golden", "c4_blast_checkpoints.npz")
+WARMUP_SECONDS = 0.2
 # sources of the phase-space pass; the committed counter figures are valid only for this hash
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2509_21832_amd", "csrc", f)
                   for f in ("mm_fused2d.hip", "mm_fused2d_lk.hip", "mm_fused_common.h", "mm_internal.h")]
@@ -59,7 +70,13 @@ def make_solver(B, p, Q, G, closure):
 
 def time_form(B, torch, p, Q, G, steps, warmup, closure=None):
     s = make_solver(B, p, Q, G, closure)
-    s.step(warmup)
+    # warm-up: at least `warmup` steps and at least WARMUP_SECONDS of them
+    s.step(max(warmup, 1))
+    done = max(warmup, 1)
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < WARMUP_SECONDS:
+        s.step(5)
+        done += 5
     torch.cuda.synchronize()
     s.timing(True)
     t0 = time.perf_counter()
@@ -83,62 +100,93 @@ def time_form(B, torch, p, Q, G, steps, warmup, closure=None):
     frac = None
     if p["precision"] == "closure":
         ncl, _ = s.closure_cells()
-        frac = ncl / ((warmup + 2 * steps) * p["nx"] * p["ny"])
+        frac = ncl / ((done + 2 * steps) * p["nx"] * p["ny"])
     s.close()
     return {"seconds": t3 - t2, "seconds_timed_run": t1 - t0,
             "micro_ms": ms_micro / max(n_micro, 1), "prep_ms": ms_prep / max(n_prep, 1),
             "macro_ms": ms_macro / max(n_macro, 1), "wall_ms": ms_wall / max(n_wall, 1),
             "closure_ms": ms_cl / max(n_cl, 1), "launches": n_micro,
-            "closure_fraction": frac}
+            "closure_fraction": frac, "warmup_steps": done}
+
+
+def _golden_cells(ref, key, ny, nx):
+    """Stored oracle values on every stride-th cell and (where stored) the boundary ring:
+    (mask [ny][nx], values [ny][nx][6] with NaN off the mask)."""
+    st = int(ref["stride"])
+    vals = np.full((ny, nx, 6), np.nan)
+    vals[::st, ::st] = ref[key + "_sample"]
+    if key + "_row_lo" in ref:
+        vals[0] = ref[key + "_row_lo"]
+        vals[-1] = ref[key + "_row_hi"]
+        vals[:, 0] = ref[key + "_col_lo"]
+        vals[:, -1] = ref[key + "_col_hi"]
+    return ~np.isnan(vals[:, :, 0]), vals
 
 
 def oracle_error(B, p, eps, seed=0, closure=None):
-    """Macro rel-L1 after 100 steps against the oracle's stored result (sampled cells)."""
+    """Macro rel-L1 after 100 steps of the cavity box against the oracle's stored result
+    (every 4th cell in x and y, and the whole boundary ring)."""
     if not os.path.exists(GOLDEN):
         return None
     ref = np.load(GOLDEN)
     key = f"eps{eps:g}"
     if key + "_sample" not in ref:
         return None
-    st = int(ref["stride"])
     p0, Q0, G0 = W.cavity2d(seed=seed, eps=eps)
     p0["precision"] = p["precision"]
     with make_solver(B, p0, Q0, G0, closure) as s:
         s.step(int(ref["steps"]))
         Q = s.moments().reshape(p0["ny"], p0["nx"], 6)
-    a = Q[::st, ::st, :]
-    b = ref[key + "_sample"]
+    mask, vals = _golden_cells(ref, key, p0["ny"], p0["nx"])
+    return float(np.abs(Q[mask] - vals[mask]).sum() / np.abs(vals[mask]).sum())
+
+
+def oracle_error_c4(B, p, steps=10):
+    """Macro rel-L1 of the 512^2 x 48^2 blast after `steps` steps against the oracle's
+    stored checkpoint (every 8th cell)."""
+    if not os.path.exists(GOLDEN_C4):
+        return None
+    ref = np.load(GOLDEN_C4)
+    key = f"step{steps}"
+    if key + "_sample" not in ref:
+        return None
+    p0, Q0, G0 = W.blast2d(seed=0)
+    p0["precision"] = p["precision"]
+    with B.Solver(p0, Q0, G0) as s:
+        s.step(steps)
+        Q = s.moments().reshape(p0["ny"], p0["nx"], 6)
+    st = int(ref["stride"])
+    a, b = Q[::st, ::st, :], ref[key + "_sample"]
     return float(np.abs(a - b).sum() / np.abs(b).sum())
 
 
-def cpu_baseline(p, Q, G, budget_s=20.0):
-    """The oracle on the host cores, on a bounded sample of the workload: full-size steps."""
+def cpu_baseline(p, seeds=(0, 1, 2)):
+    """The oracle on the host cores, on a bounded sample of the workload: one full-size
+    step from each of three seeded initial states (all OpenMP threads; the median is
+    the value), then one full step on a single thread."""
     import oracle
     threads = oracle.threads()
-    t0 = time.perf_counter()
-    Qc, Gc, H = oracle.run(p, Q.reshape(-1), G.reshape(-1), 1)
-    t1 = time.perf_counter()
-    per = t1 - t0
-    n = max(0, min(4, int(budget_s / per) - 1))
-    if n:
-        t0 = time.perf_counter()
-        oracle.run(p, Qc, Gc, n)
-        per = (time.perf_counter() - t0) / n
-    steps = n if n else 1
     pts = p["nx"] * p["ny"] * p["nv1"] * p["nv2"]
-    # one more full step on a single thread
+    per = []
+    for sd in seeds:
+        p0, Q, G = W.cavity2d(seed=sd, eps=p["eps"])
+        t0 = time.perf_counter()
+        oracle.run(p0, Q.reshape(-1), G.reshape(-1), 1)
+        per.append(time.perf_counter() - t0)
+    med = float(np.median(per))
     oracle.set_threads(1)
     try:
+        p0, Q, G = W.cavity2d(seed=seeds[0], eps=p["eps"])
         t0 = time.perf_counter()
-        oracle.run(p, Qc, Gc, 1)
+        oracle.run(p0, Q.reshape(-1), G.reshape(-1), 1)
         per1 = time.perf_counter() - t0
     finally:
         oracle.set_threads(threads)
-    return {"value": pts / per, "unit": "phase-space cell-updates/s", "cores": threads, "kind": "oracle",
+    return {"value": pts / med, "unit": "phase-space cell-updates/s", "cores": threads, "kind": "oracle",
             "value_1thread": pts / per1,
-            "sample": f"{steps} full step(s) of the {p['nx']}x{p['ny']}x{p['nv1']}x{p['nv2']} workload "
-                      f"({per:.2f} s per step, {threads} OpenMP threads), then 1 step on 1 thread "
-                      f"({per1:.2f} s)"}
+            "sample": f"1 full step of the {p['nx']}x{p['ny']}x{p['nv1']}x{p['nv2']} workload from each of seeds "
+                      f"{list(seeds)} ({', '.join(f'{x:.2f}' for x in per)} s; median {med:.2f} s per step, "
+                      f"{threads} OpenMP threads), then 1 step on 1 thread ({per1:.2f} s)"}
 
 
 def copy_bandwidth(torch, gib=1.0, reps=10):
@@ -176,6 +224,43 @@ def traffic_entry(precision):
     return e.get("bytes_per_launch")
 
 
+def roofline(form, pts, micro_ms, copy_gbs):
+    """Roofline object of the fused phase-space pass: algorithmic bytes (read g once,
+    write g once) over its mean duration from HIP events on the solver's stream."""
+    bpp = bytes_per_point(form)
+    r = {"bound": "hbm", "kernel": "k_fused2d_lk", "bytes_per_launch": bpp * pts,
+         "achieved": bpp * pts / (micro_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    r["frac"] = r["achieved"] / HBM_PEAK_GBS
+    r["copy_gbs"] = copy_gbs
+    r["frac_of_copy"] = r["achieved"] / copy_gbs
+    r["traffic"] = None
+    return r
+
+
+def run_form(B, torch, form, p, Q, G, steps, warmup, copy_gbs, closure=None, err=None):
+    pf = dict(p)
+    pf["precision"] = form
+    pts = pf["nx"] * pf["ny"] * pf["nv1"] * pf["nv2"]
+    r = time_form(B, torch, pf, Q, G, steps, warmup, closure)
+    r["value"] = pts * steps / r["seconds"]
+    r["ms_per_step"] = 1e3 * r["seconds"] / steps
+    r["err_vs_oracle"] = err(pf) if err else None
+    r["roofline"] = roofline(form, pts, r["micro_ms"], copy_gbs) if form != "closure" else None
+    return r
+
+
+def summary(r, base=None):
+    """The figures of one timed form that go into the JSON line."""
+    out = {"value": r["value"], "ms_per_step": r["ms_per_step"], "err_vs_oracle": r["err_vs_oracle"],
+           "micro_pass_ms": r["micro_ms"], "wall_cells_ms": r["wall_ms"], "prep_ms": r["prep_ms"],
+           "macro_ms": r["macro_ms"], "closure_kernels_ms": r["closure_ms"],
+           "closure_fraction": r["closure_fraction"], "warmup_steps": r["warmup_steps"],
+           "roofline_frac": r["roofline"]["frac"] if r["roofline"] else None,
+           "achieved_gbs": r["roofline"]["achieved"] if r["roofline"] else None}
+    out["speedup_vs_fp64"] = r["value"] / base["value"] if base else None
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -185,6 +270,8 @@ def main():
     ap.add_argument("--eps", type=float, default=1e-2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-error", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true",
+                    help="time only the headline workload (no eps sweeps, no 512^2 x 48^2 blast)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="first run one plain device-to-device copy of MIB MiB (the reference kernel that "
                          "scales the HBM byte counters of a profiler run)")
@@ -211,14 +298,17 @@ def main():
     copy_gbs = copy_bandwidth(torch)
     log(f"device copy: {copy_gbs:.0f} GB/s (read + write)")
 
+    def c3_err(eps, closure=None):
+        return None if args.no_error else (lambda pf: oracle_error(B, pf, eps, closure=closure))
+
     p, Q, G = W.cavity2d(seed=0, eps=args.eps)
     pts = p["nx"] * p["ny"] * p["nv1"] * p["nv2"]
     forms = {}
     closure = None
-    for form in [f for f in args.forms.split(",") if f]:
-        pf = dict(p)
-        pf["precision"] = form
-        if form == "closure" and closure is None:
+
+    def get_closure():
+        nonlocal closure
+        if closure is None:
             # the network, trained on the GPU by the library's kernels (not timed)
             from paper_2509_21832_amd import closure as CL
             t0 = time.perf_counter()
@@ -227,29 +317,71 @@ def main():
                        "train_seconds": time.perf_counter() - t0, "train_samples": nsamp,
                        "final_loss": float(losses[-1])}
             log(f"closure network: {nsamp} samples, {closure['train_seconds']:.1f} s, loss {losses[-1]:.4f}")
+        return closure
+
+    for form in [f for f in args.forms.split(",") if f]:
+        cl = get_closure() if form == "closure" else None
         try:
-            r = time_form(B, torch, pf, Q, G, args.steps, args.warmup, closure)
+            r = run_form(B, torch, form, p, Q, G, args.steps, args.warmup, copy_gbs, cl, c3_err(args.eps, cl))
         except B.MMError as e:
             log(f"form {form}: {e}")
             continue
-        r["value"] = pts * args.steps / r["seconds"]
-        r["ms_per_step"] = 1e3 * r["seconds"] / args.steps
-        r["err_vs_oracle"] = None if args.no_error else oracle_error(B, pf, args.eps, closure=closure)
-        bpp = bytes_per_point(form)
-        # dominant kernel: the fused phase-space pass (one launch per step, every point
-        # read once and written once); its duration from HIP events on the solver's stream
-        r["roofline"] = {"bound": "hbm", "kernel": "k_fused2d_lk", "bytes_per_launch": bpp * pts,
-                         "achieved": bpp * pts / (r["micro_ms"] * 1e-3) / 1e9,
-                         "peak": HBM_PEAK_GBS, "unit": "GB/s"}
-        r["roofline"]["frac"] = r["roofline"]["achieved"] / HBM_PEAK_GBS
-        r["roofline"]["copy_gbs"] = copy_gbs
-        r["roofline"]["frac_of_copy"] = r["roofline"]["achieved"] / copy_gbs
-        r["roofline"]["traffic"] = traffic_entry(form)
-        if form == "closure":
-            r["roofline"] = None      # the closure pass touches only the solved cells
+        if r["roofline"]:
+            r["roofline"]["traffic"] = traffic_entry(form)
         forms[form] = r
         log(f"{form}: {r['ms_per_step']:.3f} ms/step, {r['value']:.3e} updates/s, micro pass "
             f"{r['micro_ms']:.3f} ms, err {r['err_vs_oracle']}")
+
+    sweeps = None
+    if not args.no_sweep:
+        sweeps = {"c3_cavity_eps": [], "c4_blast": {}, "c5_closure_eps": []}
+        base = {}
+        # the cavity box at every eps of its sweep (and 3e-3 for the closure's baseline)
+        for eps in (1e-3, 3e-3, 1e-2, 1e-1, 1.0):
+            pe, Qe, Ge = W.cavity2d(seed=0, eps=eps)
+            row = {"eps": eps}
+            for form in ("fp64", "mixed"):
+                if eps == args.eps and form in forms:
+                    r = forms[form]
+                else:
+                    r = run_form(B, torch, form, pe, Qe, Ge, args.steps, args.warmup, copy_gbs,
+                                 err=c3_err(eps))
+                row[form] = summary(r, base.get(eps))
+                if form == "fp64":
+                    base[eps] = r
+                log(f"c3 eps={eps:g} {form}: {r['ms_per_step']:.3f} ms/step, pass {r['micro_ms']:.3f} ms, "
+                    f"err {r['err_vs_oracle']}")
+            sweeps["c3_cavity_eps"].append(row)
+        # the learned closure at three eps, against the FP64 step at the same eps
+        if "closure" in args.forms:
+            for eps in (1e-3, 3e-3, 1e-2):
+                pe, Qe, Ge = W.cavity2d(seed=0, eps=eps)
+                cl = get_closure()
+                if eps == args.eps and "closure" in forms:
+                    r = forms["closure"]
+                else:
+                    r = run_form(B, torch, "closure", pe, Qe, Ge, args.steps, args.warmup, copy_gbs, cl,
+                                 c3_err(eps, cl))
+                row = {"eps": eps, "closure": summary(r, base.get(eps))}
+                sweeps["c5_closure_eps"].append(row)
+                log(f"c5 eps={eps:g}: {r['ms_per_step']:.3f} ms/step, closure cells {r['closure_fraction']}, "
+                    f"err {r['err_vs_oracle']}")
+        # the 512^2 x 48^2 blast: g in FP32, and FP64 for the speedup
+        pb, Qb, Gb = W.blast2d(seed=0)
+        c4 = {}
+        for form in ("fp64", "mixed"):
+            errf = None if args.no_error else (lambda pf: oracle_error_c4(B, pf))
+            r = run_form(B, torch, form, pb, Qb, Gb, max(10, args.steps // 4), args.warmup, copy_gbs, err=errf)
+            c4[form] = r
+            log(f"c4 {form}: {r['ms_per_step']:.3f} ms/step, pass {r['micro_ms']:.3f} ms, err {r['err_vs_oracle']}")
+        sweeps["c4_blast"] = {
+            "workload": f"2D2V Gaussian blast {pb['nx']}x{pb['ny']} cells x {pb['nv1']}x{pb['nv2']} velocity nodes "
+                        f"on [-8,8]^2, walls, eps={pb['eps']:g}",
+            "phase_points": pb["nx"] * pb["ny"] * pb["nv1"] * pb["nv2"],
+            "err_steps": 10,
+            "fp64": summary(c4["fp64"]), "mixed": summary(c4["mixed"], c4["fp64"]),
+            "roofline_mixed": c4["mixed"]["roofline"], "roofline_fp64": c4["fp64"]["roofline"]}
+        del Qb, Gb
 
     main_form = forms.get("fp64") or next(iter(forms.values()))
     out = {
@@ -270,19 +402,14 @@ def main():
                    "phase_points": pts, "eps": args.eps, "seed": 0},
         "roofline": main_form["roofline"],
         "err_vs_oracle": main_form["err_vs_oracle"],
-        "forms": {k: {"value": v["value"], "ms_per_step": v["ms_per_step"], "err_vs_oracle": v["err_vs_oracle"],
-                      "speedup_vs_fp64": v["value"] / forms["fp64"]["value"] if "fp64" in forms else None,
-                      "micro_pass_ms": v["micro_ms"], "wall_cells_ms": v["wall_ms"], "prep_ms": v["prep_ms"],
-                      "macro_ms": v["macro_ms"], "closure_kernels_ms": v["closure_ms"],
-                      "closure_fraction": v["closure_fraction"],
-                      "roofline_frac": v["roofline"]["frac"] if v["roofline"] else None}
-                  for k, v in forms.items()},
+        "forms": {k: summary(v, forms.get("fp64")) for k, v in forms.items()},
+        "sweeps": sweeps,
         "kernel_hash": kernel_hash(),
     }
     if closure is not None:
         out["closure_training"] = {k: closure[k] for k in ("train_seconds", "train_samples", "final_loss")}
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(p, Q, G)
+        out["cpu_baseline"] = cpu_baseline(p)
     print(json.dumps(out), flush=True)
 
 

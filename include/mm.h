@@ -56,9 +56,10 @@ enum {
     MM_BC_EXTRAP = 0,    /* constant extrapolation ("outflow"), Sec. 5.3.1 / 5.4.1   */
     MM_BC_PERIODIC = 1,  /* periodic, Sec. 5.3.2 / 5.4.2 (both sides of an axis)    */
     MM_BC_WALL = 2,      /* diffusely reflecting wall at T_wall, moving tangentially
-                            with u_wall (the lid), Sec. 6.3                          */
+                            with u_wall (the lid), Sec. 6.3; in 1D the walls of
+                            Sec. 4.3 (u_wall unused)                                 */
     MM_BC_INFLOW = 3     /* fixed ghost Maxwellian (rho, u1, u2, T) entering the box;
-                            wall machinery otherwise (g = 0 ghosts, H ghost = 0)     */
+                            wall machinery otherwise (g = 0 ghosts, H ghost = 0); 2D only */
 };
 
 /* collision parameter tau(rho, p, T) */
@@ -119,17 +120,29 @@ typedef struct {
     int device;                       /* HIP device ordinal                         */
     void *stream;                     /* hipStream_t to enqueue on; NULL: the library
                                          creates its own (default-priority) stream  */
+    void *dev_buffers[3];             /* 2D only, optional: caller-owned device buffers
+                                         G0, G1 (each [ny][nx][nv2][nv1], FP64 for
+                                         MM_FP64, FP32 otherwise) and Q ([ny][nx][6]
+                                         FP64), used instead of library allocations
+                                         (zero-copy state, e.g. torch tensors); all
+                                         three or none.  They must outlive the context,
+                                         which never frees them.  G^n is in G0 after an
+                                         even and in G1 after an odd number of steps
+                                         (mm_device_ptrs names the current one). */
 } mm_config;
 
 /*
  * mm_init -- validate cfg, allocate device state, upload the initial data.
- *   q0: host Q^0 (layout above), required.
+ *   q0: host Q^0 (layout above); required, except with cfg->dev_buffers, where
+ *       NULL means that Q^0 and G^0 are already in the Q and G0 buffers (taken
+ *       as they are: the state is checked by the first step, not here).
  *   g0: host G^0 (layout above) or NULL for g = 0, the paper's initial
- *       condition in every example.
+ *       condition in every example (with q0 != NULL).
  *   *out receives the context, or NULL on failure (nothing leaks).
  * Errors: MM_EINVAL (bad sizes, eps <= 0, cfl <= 0, nu outside [-1, 1) in 2D,
- * unpaired periodic sides, walls in 1D, T_wall <= 0), MM_ENONPHYS (Q^0 not
- * physical), MM_ENOMEM, MM_EDEVICE.
+ * unpaired periodic sides, inflow sides in 1D, T_wall <= 0, dev_buffers partly set, set
+ * in 1D or with two equal G buffers), MM_ENONPHYS (Q^0 not physical), MM_ENOMEM,
+ * MM_EDEVICE.
  */
 int mm_init(const mm_config *cfg, const double *q0, const double *g0, mm_ctx **out);
 
@@ -182,6 +195,32 @@ double mm_dt(const mm_config *cfg, double t_final, int *nsteps);
 
 /* mm_failed_step -- first step whose macro state was non-physical, or -1. */
 int mm_failed_step(const mm_ctx *ctx);
+
+/* source terms */
+enum {
+    MM_SOURCE_NONE = 0,
+    MM_SOURCE_MMS = 1   /* the manufactured solution of the paper's convergence study:
+                           1D (Sec. 3.4): f = (e^-(v-1)^2 + 2 e^-(v+1)^2)(2 + sin 2pi(x - t));
+                           2D (Sec. 6.2): f = (e^-|v-(1,1)|^2 + 2 e^-|v+(1,1)|^2)
+                                              (2 - sin 2pi(t - x) cos 2pi(t - y)).
+                           Its residual S = f_t + v . grad f - (tau / eps)(calG[f] - f)
+                           (calG[f] = M[f] in 1D) enters each step at the old time level
+                           t^n and the cell centre: (1 / tau_ij^n)(I - Pi)[S] is added to
+                           G-hat, and dt times the velocity moments of S (closed form)
+                           to the macro update (1D: with the flux differences, eqn5-27;
+                           2D: after the y-sweep, before the second collision half
+                           step).  The tau inside S is the cell's tau_i^n in 1D and
+                           that of the invented state in 2D.                         */
+};
+
+/*
+ * mm_set_source -- from the next step on, add the source `kind`, with the current
+ * state taken to be at time t0 (t^n = t0 + n dt for the n-th following step).
+ * The initial state is the caller's (e.g. the invented solution's point values
+ * at the cell centres).  Not with MM_CLOSURE.  Errors: MM_EINVAL, MM_ENOMEM,
+ * MM_EDEVICE, MM_ESTATE.
+ */
+int mm_set_source(mm_ctx *ctx, int kind, double t0);
 
 /* mm_strerror -- static text for a status code. */
 const char *mm_strerror(int status);

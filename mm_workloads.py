@@ -178,6 +178,27 @@ def smooth2d(seed=0, nx=16, ny=16, nv=16, V=8.0, eps=0.1, bc=None, amp=0.2, u_am
     return p, Q, zero_g(p)
 
 
+def cylsod2d(nx=320, nv=14, eps=5e-5, sub=20, **kw):
+    """Cylindrical Sod problem (Sec. 6.2): [-1,1]^2 x [-9,9]^2, extrapolation on every side,
+    nu = 0 and tau = rho, CFL 0.95 with the rule CFL = dt (V1/dx + V2/dy) the printed run
+    follows (213 steps to t = 0.07 at 320^2).  Q_in = (1, 0, 0, 5, 0, 5) inside r = 0.5,
+    Q_out = (0.125, 0, 0, 0.5, 0, 0.5) outside; a cell the circle cuts takes
+    w Q_in + (1 - w) Q_out, w the fraction of sub x sub points of the cell inside."""
+    p = problem2d(nx, nx, nv, nv, 9.0, eps=eps, cfl=0.95, nu=0.0, bc=extrap2d(), x=(-1.0, 1.0), y=(-1.0, 1.0),
+                  tau_model="rho", tau_coef=1.0, **kw)
+    p["cfl_rule"] = "sum"
+    h = 2.0 / nx
+    lo = -1.0 + h * np.arange(nx)                          # cell lower edges
+    off = (np.arange(sub) + 0.5) * h / sub
+    px = (lo[:, None] + off[None, :]).reshape(-1)          # sub points per cell, all cells
+    inside = (px[None, :] ** 2 + px[:, None] ** 2) < 0.25   # [y points][x points]
+    w = inside.reshape(nx, sub, nx, sub).mean(axis=(1, 3))  # [j][i]
+    q_in = np.array([1.0, 0.0, 0.0, 5.0, 0.0, 5.0])
+    q_out = np.array([0.125, 0.0, 0.0, 0.5, 0.0, 0.5])
+    Q = w[..., None] * q_in + (1.0 - w[..., None]) * q_out
+    return p, Q, zero_g(p)
+
+
 CONFIGS = {
     "c1_sod1d": lambda seed=0: sod1d(),
     "c2_quadrant": lambda seed=0: quadrant2d(seed=seed),

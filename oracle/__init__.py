@@ -68,6 +68,10 @@ def lib():
         L.o_run1d.argtypes = [cp, dp, dp, C.c_int, dp, ip]
         L.o_mms1d.argtypes = [cp, C.c_double, dp]
         L.o_mms2d.argtypes = [cp, C.c_double, dp]
+        L.o_mms1d_run.argtypes = [cp, C.c_double, C.c_int, dp, dp, dp]
+        L.o_mms2d_run.argtypes = [cp, C.c_double, C.c_int, dp, dp, dp]
+        L.o_mms1d_exact.argtypes = [cp, C.c_double, dp, dp]
+        L.o_mms2d_exact.argtypes = [cp, C.c_double, dp, dp]
         L.o_micro2d.argtypes = [cp, dp, dp, dp]
         L.o_macro2d.argtypes = [cp, dp, dp]
         L.o_ghat2d.argtypes = [cp, dp, dp]
@@ -193,6 +197,36 @@ def mms2d(p, t_final):
     if rc:
         raise RuntimeError(f"o_mms2d failed ({rc})")
     return float(e[0]), float(e[1])
+
+
+def mms_exact(p, t):
+    """(Q, G): the invented solution of the convergence study (1D: Sec. 3.4, 2D: Sec. 6.2)
+    at time t, point values at the cell centres, in the solver's layouts."""
+    ncell = p["nx"] * p.get("ny", 1)
+    nv = p["nv1"] * p.get("nv2", 1)
+    Q = np.zeros(ncell * (6 if p["dim"] == 2 else 3))
+    G = np.zeros(ncell * nv)
+    fn = lib().o_mms2d_exact if p["dim"] == 2 else lib().o_mms1d_exact
+    if fn(C.byref(cfg(p)), float(t), _dp(Q), _dp(G)):
+        raise ValueError("mms_exact")
+    return Q, G
+
+
+def mms_run(p, t_final, max_steps=-1):
+    """The convergence-study run of p (from the exact point values at t = 0, the Delta t reset
+    to land on t_final, the source terms), stopped after max_steps steps (< 0: all):
+    returns (Q, G, errs) with errs = (macro, micro) relative L2 errors, or None if stopped
+    early."""
+    ncell = p["nx"] * p.get("ny", 1)
+    nv = p["nv1"] * p.get("nv2", 1)
+    Q = np.zeros(ncell * (6 if p["dim"] == 2 else 3))
+    G = np.zeros(ncell * nv)
+    e = np.full(2, np.nan)
+    fn = lib().o_mms2d_run if p["dim"] == 2 else lib().o_mms1d_run
+    rc = fn(C.byref(cfg(p)), float(t_final), int(max_steps), _dp(Q), _dp(G), _dp(e))
+    if rc:
+        raise RuntimeError(f"mms run failed ({rc})")
+    return Q, G, (None if np.isnan(e[0]) else (float(e[0]), float(e[1])))
 
 
 def micro2d(p, Q, G):

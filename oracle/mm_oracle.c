@@ -923,7 +923,46 @@ done:
  * steps of the CFL rule of c reset to land on t_final, the source terms above.
  * errs receives the relative L2 errors of Q = (rho, rho u, E) and of G against
  * the exact solution at t_final.  Returns O_OK or an error code. */
+/* The run of o_mms2d stopped after at most max_steps steps (max_steps < 0: all of
+ * them); Q_out [ny][nx][6] and G_out [ny][nx][nv2][nv1] (either may be NULL)
+ * receive the final state, errs (may be NULL) the errors when the run reached
+ * t_final. */
+int o_mms2d_run(const o_cfg *c, double t_final, int max_steps, double *Q_out, double *G_out, double errs[2]);
+
 int o_mms2d(const o_cfg *c, double t_final, double errs[2])
+{
+    return o_mms2d_run(c, t_final, -1, NULL, NULL, errs);
+}
+
+/* exact point values of the invented solution at time t at the cell centres */
+int o_mms2d_exact(const o_cfg *c, double t, double *Q, double *G)
+{
+    if (cfg_check(c) || c->dim != 2) return O_EINVAL;
+    o_grid g;
+    if (grid_make(c, &g)) return O_ENOMEM;
+    const long ncell = (long)g.nx * g.ny;
+#pragma omp parallel for schedule(static)
+    for (long cc = 0; cc < ncell; ++cc) {
+        const int ii = (int)(cc % g.nx), jj = (int)(cc / g.nx);
+        const double xx = c->x_lo + (ii + 0.5) * g.dx, yy = c->y_lo + (jj + 0.5) * g.dy;
+        double qe[6];
+        o_prim Pe;
+        mms2_q(t, xx, yy, qe);
+        if (Q) for (int r = 0; r < 6; ++r) Q[6 * cc + r] = qe[r];
+        if (G) {
+            prim2d(c, qe, &Pe);
+            const double B = mms2_B(t, xx, yy);
+            for (int l = 0; l < g.nv2; ++l)
+                for (int k = 0; k < g.nv1; ++k)
+                    G[cc * g.nv + l * g.nv1 + k] =
+                        (mms2_A(g.v1[k], g.v2[l]) * B - maxw2d(Pe.rho, Pe.u1, Pe.u2, Pe.T, g.v1[k], g.v2[l])) / c->eps;
+        }
+    }
+    grid_free(&g);
+    return O_OK;
+}
+
+int o_mms2d_run(const o_cfg *c, double t_final, int max_steps, double *Q_out, double *G_out, double errs[2])
 {
     if (cfg_check(c) || c->dim != 2) return O_EINVAL;
     o_grid g;
@@ -956,13 +995,16 @@ int o_mms2d(const o_cfg *c, double t_final, double errs[2])
     }
     int nsteps = 0;
     const double dt = o_dt(c, t_final, &nsteps);
-    for (int s = 0; s < nsteps; ++s) {
+    const int nrun = max_steps >= 0 && max_steps < nsteps ? max_steps : nsteps;
+    for (int s = 0; s < nrun; ++s) {
         o_mms2 m = {s * dt};
         for (size_t cc = 0; cc < ncell; ++cc) prim2d(c, Q + 6 * cc, &prim[cc]);
         micro2d(c, &g, prim, G, Gs, Hn, dt, &m);
         if (macro2d(c, &g, Q, Qt, Hn, dt, &m)) { rc = O_ENONPHYS; break; }
     }
-    if (rc == O_OK) {
+    if (rc == O_OK && Q_out) memcpy(Q_out, Q, sizeof(double) * 6 * ncell);
+    if (rc == O_OK && G_out) memcpy(G_out, G, sizeof(double) * ncell * nv);
+    if (rc == O_OK && errs && nrun == nsteps) {
         ksum eq = {0}, nq = {0}, eg = {0}, ng = {0};
         double *ge = Gs;   /* scratch */
         for (size_t cc = 0; cc < ncell; ++cc) {
@@ -1335,7 +1377,35 @@ static int step1d(const o_cfg *c, const o_grid *g, double *Q, double *G, double 
  * t = 0, steps of the CFL rule reset to land on t_final, the source terms above.
  * errs receives the relative L2 errors of Q and of G against the exact solution
  * at t_final (the study's definitions).  Returns O_OK or an error code. */
+int o_mms1d_run(const o_cfg *c, double t_final, int max_steps, double *Q_out, double *G_out, double errs[2]);
+
 int o_mms1d(const o_cfg *c, double t_final, double errs[2])
+{
+    return o_mms1d_run(c, t_final, -1, NULL, NULL, errs);
+}
+
+/* exact point values of the 1D invented solution at time t at the cell centres */
+int o_mms1d_exact(const o_cfg *c, double t, double *Q, double *G)
+{
+    if (cfg_check(c) || c->dim != 1) return O_EINVAL;
+    o_grid g;
+    if (grid_make(c, &g)) return O_ENOMEM;
+    const double sq = sqrt(O_PI);
+    for (int i = 0; i < g.nx; ++i) {
+        const double x = c->x_lo + (i + 0.5) * g.dx, B = mms1_B(t, x);
+        if (Q) {
+            Q[3 * i + 0] = 3.0 * sq * B;
+            Q[3 * i + 1] = -sq * B;
+            Q[3 * i + 2] = 2.25 * sq * B;
+        }
+        if (G) for (int k = 0; k < g.nv1; ++k) G[(size_t)i * g.nv1 + k] = mms1_g(c->eps, t, x, g.v1[k]);
+    }
+    grid_free(&g);
+    return O_OK;
+}
+
+/* the run of o_mms1d, stopped after at most max_steps steps (see o_mms2d_run) */
+int o_mms1d_run(const o_cfg *c, double t_final, int max_steps, double *Q_out, double *G_out, double errs[2])
 {
     if (cfg_check(c) || c->dim != 1) return O_EINVAL;
     o_grid g;
@@ -1354,12 +1424,15 @@ int o_mms1d(const o_cfg *c, double t_final, double errs[2])
     }
     int nsteps = 0;
     const double dt = o_dt(c, t_final, &nsteps);
+    const int nrun = max_steps >= 0 && max_steps < nsteps ? max_steps : nsteps;
     o_mms1 m = {0.0};
-    for (int s = 0; s < nsteps; ++s) {
+    for (int s = 0; s < nrun; ++s) {
         m.t = s * dt;
         if (step1d(c, &g, Q, G, Gn, Hn, P, dt, &m)) { rc = O_ENONPHYS; break; }
     }
-    if (rc == O_OK) {
+    if (rc == O_OK && Q_out) memcpy(Q_out, Q, sizeof(double) * 3 * nx);
+    if (rc == O_OK && G_out) memcpy(G_out, G, sizeof(double) * (size_t)nx * nv);
+    if (rc == O_OK && errs && nrun == nsteps) {
         ksum eq = {0}, nq = {0}, eg = {0}, ng = {0};
         for (int i = 0; i < nx; ++i) {
             const double x = c->x_lo + (i + 0.5) * g.dx, B = mms1_B(t_final, x);

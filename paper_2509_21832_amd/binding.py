@@ -18,13 +18,15 @@ TAU = {"rho": 0, "p": 1, "hs1d": 2, "const": 3}
 PROJ = {"discrete": 0, "paper": 1}
 CFL = {"min": 0, "sum": 1}
 PRECISION = {"fp64": 0, "mixed": 1, "closure": 2}
+SOURCE = {"none": 0, "mms": 1}
 
 # every entry point declared in include/mm.h
 EXPORTS = ("mm_init", "mm_step", "mm_step_async", "mm_sync", "mm_moments", "mm_get_g", "mm_set_state",
            "mm_free", "mm_dt", "mm_failed_step", "mm_strerror", "mm_timing", "mm_timing_get", "mm_device_ptrs",
            "mm_get_g_cells", "mm_mlp_create", "mm_mlp_free", "mm_mlp_fit_norm", "mm_mlp_get", "mm_mlp_set",
            "mm_mlp_forward", "mm_mlp_grad", "mm_mlp_train", "mm_closure_attach", "mm_closure_cells",
-           "mm_closure_snapshot", "mm_closure_features", "mm_closure_rebuild", "mm_step2d_noalloc")
+           "mm_closure_snapshot", "mm_closure_features", "mm_closure_rebuild", "mm_step2d_noalloc",
+           "mm_set_source")
 
 MLP_NPARAM = 5893
 MLP_NNORM = 52
@@ -53,7 +55,8 @@ class mm_config(C.Structure):
                 ("eps", C.c_double), ("cfl", C.c_double), ("cfl_rule", C.c_int), ("nu", C.c_double),
                 ("tau_model", C.c_int), ("tau_coef", C.c_double), ("bc", mm_bc * 4),
                 ("proj_mode", C.c_int), ("wall_es_term", C.c_int), ("dt", C.c_double),
-                ("precision", C.c_int), ("device", C.c_int), ("stream", C.c_void_p)]
+                ("precision", C.c_int), ("device", C.c_int), ("stream", C.c_void_p),
+                ("dev_buffers", C.c_void_p * 3)]
 
 
 def _load():
@@ -99,6 +102,7 @@ def _load():
     L.mm_closure_features.argtypes = [vp, fp, fp, bp]
     L.mm_closure_rebuild.argtypes = [vp, fp, bp]
     L.mm_step2d_noalloc.argtypes = [cp, vp, vp, vp, vp, C.c_int, C.POINTER(C.c_int)]
+    L.mm_set_source.argtypes = [vp, C.c_int, C.c_double]
     for name in EXPORTS:
         getattr(L, name)
     return L
@@ -111,8 +115,9 @@ def lib():
     return _lib
 
 
-def config(p, stream=None, device=0):
-    """mm_config from a problem dictionary (see mm_workloads)."""
+def config(p, stream=None, device=0, dev_buffers=None):
+    """mm_config from a problem dictionary (see mm_workloads); dev_buffers: None or the
+    device addresses (G0, G1, Q) of caller-owned buffers."""
     c = mm_config()
     c.dim = p["dim"]
     c.nx, c.ny = p["nx"], p.get("ny", 1)
@@ -140,6 +145,9 @@ def config(p, stream=None, device=0):
     c.precision = PRECISION[p.get("precision", "fp64")]
     c.device = device
     c.stream = stream
+    if dev_buffers is not None:
+        for k in range(3):
+            c.dev_buffers[k] = dev_buffers[k]
     return c
 
 
@@ -208,20 +216,39 @@ def step2d_noalloc(p, q, g0, g1, nsteps, h=None, stream=None, device=0, wait=Tru
 class Solver:
     """One mm_ctx: Q, G and H live in device memory owned by the library."""
 
-    def __init__(self, p, Q0, G0=None, stream=None, device=0):
+    def __init__(self, p, Q0, G0=None, stream=None, device=0, dev_buffers=None):
+        """dev_buffers: None, or caller-owned GPU tensors (G0, G1, Q) that hold the state
+        (zero-copy; see mm_config.dev_buffers).  With dev_buffers, Q0 = None takes the
+        state already in them."""
         self.p = dict(p)
         self.ncell = p["nx"] * p.get("ny", 1)
         self.nv = p["nv1"] * p.get("nv2", 1)
         self.ncomp = 6 if p["dim"] == 2 else 3
-        q = np.ascontiguousarray(Q0, dtype=np.float64).reshape(-1)
-        if q.size != self.ncell * self.ncomp:
-            raise ValueError("Q0 has the wrong size")
+        addrs = None
+        if dev_buffers is not None:
+            import torch
+            gdt = torch.float64 if p.get("precision", "fp64") == "fp64" else torch.float32
+            sizes = (self.ncell * self.nv, self.ncell * self.nv, self.ncell * self.ncomp)
+            for t, n, dtp in zip(dev_buffers, sizes, (gdt, gdt, torch.float64)):
+                if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dtp and t.is_contiguous()
+                        and t.numel() == n):
+                    raise TypeError("dev_buffers: contiguous GPU tensors (G0, G1, Q) of the state's sizes")
+            addrs = [t.data_ptr() for t in dev_buffers]
+            self._keep = tuple(dev_buffers)       # the buffers must outlive the context
+        if Q0 is None:
+            q = None
+            if addrs is None:
+                raise ValueError("Q0 is required without dev_buffers")
+        else:
+            q = np.ascontiguousarray(Q0, dtype=np.float64).reshape(-1)
+            if q.size != self.ncell * self.ncomp:
+                raise ValueError("Q0 has the wrong size")
         g = None
         if G0 is not None:
             g = np.ascontiguousarray(G0, dtype=np.float64).reshape(-1)
             if g.size != self.ncell * self.nv:
                 raise ValueError("G0 has the wrong size")
-        self._cfg = config(p, stream, device)
+        self._cfg = config(p, stream, device, addrs)
         self._ctx = C.c_void_p()
         _check(_lib.mm_init(C.byref(self._cfg), _dp(q), _dp(g), C.byref(self._ctx)), "mm_init")
 
@@ -257,6 +284,10 @@ class Solver:
 
     def failed_step(self):
         return _lib.mm_failed_step(self._ctx)
+
+    def set_source(self, kind, t0=0.0):
+        """kind: "none" or "mms" (the manufactured solution of the convergence study)."""
+        _check(_lib.mm_set_source(self._ctx, SOURCE[kind], float(t0)), "mm_set_source")
 
     def moments(self, with_h=False, with_gmom=False):
         Q = np.empty(self.ncell * self.ncomp)

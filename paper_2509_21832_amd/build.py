@@ -8,7 +8,7 @@ SRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libmm.so")
 SOURCES = ["mm_host.cpp", "mm_mlp.cpp", "mm_kernels2d.hip", "mm_fused2d.hip", "mm_fused2d_lk.hip",
-           "mm_kernels1d.hip", "mm_closure.hip"]
+           "mm_kernels1d.hip", "mm_closure.hip", "mm_source.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-ffp-contract=fast",
          # no packed FP32 instructions anywhere in device code

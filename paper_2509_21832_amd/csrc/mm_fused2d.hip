@@ -48,11 +48,14 @@ struct Pass {
     double *tab;          // this wavefront's Maxwellian tables: 3 slots x 2 x MAXV
     int lane, i;
 
+    // the Maxwellian of node p = lane + 64 m; 0 on the padding slots p >= nv of the
+    // last node of a lane, so that they add nothing to any sum or to H
     __device__ __forceinline__ TC maxw_tab(int slot, int m) const
     {
-        const int2 kl = skl[lane + 64 * m];
+        const int p = lane + 64 * m;
+        const int2 kl = skl[p];
         const double *t = tab + slot * 2 * MAXV;
-        return (TC)(t[kl.x] * t[MAXV + kl.y]);
+        return p < P->nv ? (TC)(t[kl.x] * t[MAXV + kl.y]) : (TC)0;
     }
 
     __device__ __forceinline__ void build_tables(int slot, const double *R) const

@@ -135,46 +135,64 @@ struct PassLK {
     bool zero_nb;
     bool edge_col;   // wave-uniform: some lane of this column has zero_nb
 
-    // x-sweep of row r: G*(i, r) into out; R: the record of cell (i, r)
-    __device__ __forceinline__ GqS xsweep(int r, TC (&out)[NPT], const Rec &R)
+    // g of cell i and of its upwind x-neighbour in row r, as an x-sweep reads them
+    __device__ __forceinline__ void load_x(int r, TC (&gc)[NPT], TC (&gu)[NPT]) const
     {
-        TC gc[NPT], Z[NPT];
-        {
-            TC gn[NPT];
-            const auto rs = row(G, r);
-            load(rs, off_c, gc);
-            load(rs, off_u, gn);
-            if (edge_col) {
+        const auto rs = row(G, r);
+        load(rs, off_c, gc);
+        load(rs, off_u, gu);
+    }
+
+    // x-sweep from the loaded values: G*(i, r) = g - dt (I - Pi)[Z] into out, with
+    // Z = cx d and d = g(i) - g(upwind).  The first node loop leaves g - dt Z in out
+    // and sums d; after the wavefront sum and the projection the second adds
+    // dt Pi[Z] = (dt q-polynomial) M.  Neither g nor d stays live across the sums.
+    // R: the record of cell (i, r)
+    __device__ __forceinline__ GqS xsweep_v(const TC (&gc)[NPT], TC (&gu)[NPT], TC (&out)[NPT], const Rec &R)
+    {
+        if (edge_col) {
 #pragma unroll
-                for (int m = 0; m < NPT; ++m) gn[m] = zero_nb ? (TC)0 : gn[m];
-            }
-#pragma unroll
-            for (int m = 0; m < NPT; ++m) Z[m] = cx * (gc[m] - gn[m]);
+            for (int m = 0; m < NPT; ++m) gu[m] = zero_nb ? (TC)0 : gu[m];
         }
+        const TC dcx = (TC)P->dt * cx;
         double S[3] = {0.0, 0.0, 0.0};
 #pragma unroll
         for (int m = 0; m < NPT; ++m) {
-            const double z = (double)Z[m];
-            S[0] += z;
-            S[1] += tn(m) * z;
-            S[2] += (tn(m) * tn(m)) * z;
+            const TC d = gc[m] - gu[m];
+            out[m] = gc[m] - dcx * d;
+            const double dd = (double)d;
+            S[0] += dd;
+            S[1] += tn(m) * dd;
+            S[2] += (tn(m) * tn(m)) * dd;
         }
+        const double cxd = fabs(v1d) / P->dx;      // sums of Z = cx d
+        S[0] *= cxd;
+        S[1] *= cxd;
+        S[2] *= cxd;
         double s[4];
         raw4(S, s);
         wave_sum<4>(s, lane);
         double o[4];
         proj_raw(R, s, o);
-        const TC c2 = (TC)o[2], c3 = (TC)o[3], K = (TC)(o[0] + (o[1] + o[3] * v1d) * v1d);
-        const TC dt = (TC)P->dt;
+        const double dtd = P->dt;
+        const TC c2 = (TC)(dtd * o[2]), c3 = (TC)(dtd * o[3]), K = (TC)(dtd * (o[0] + (o[1] + o[3] * v1d) * v1d));
         const Gq m0 = maxw_q(R);
         Gq mq = m0;
         TC w = v2b;
 #pragma unroll
         for (int m = 0; m < NPT; ++m, w += h) {
             const TC pm = (c3 * w + c2) * w + K;
-            out[m] = gc[m] + dt * (pm * (TC)mq.next() - Z[m]);
+            out[m] = pm * (TC)mq.next() + out[m];
         }
         return GqS{m0.e, m0.r};
+    }
+
+    // x-sweep of row r: G*(i, r) into out; R: the record of cell (i, r)
+    __device__ __forceinline__ GqS xsweep(int r, TC (&out)[NPT], const Rec &R)
+    {
+        TC gc[NPT], gu[NPT];
+        load_x(r, gc, gu);
+        return xsweep_v(gc, gu, out, R);
     }
 
     // y-transport of node m: v2 (G(j) - G(j -/+ 1)) / dy upwind, written as

@@ -35,6 +35,7 @@ struct mm_ctx {
     double *Gs = nullptr;          // G* scratch of the reference (unfused) 2D pass
     mm::Params *Pd = nullptr;      // device copy of P (read by the fused pass)
     void *G[2] = {nullptr, nullptr};
+    bool caller_buffers = false;   // G[0], G[1] and Q belong to the caller (cfg.dev_buffers)
     int gbytes = 8, cur = 0;
     int *flag = nullptr;
     int steps_done = 0, failed = -1;
@@ -56,6 +57,11 @@ struct mm_ctx {
     unsigned long long *cl_ncl = nullptr;   // closure cells, summed over steps (device)
     int *cl_snap = nullptr;                  // rows of the snapshot buffers (device)
     int *cl_list = nullptr, *cl_nlist = nullptr;   // cells to rebuild (device)
+    // manufactured-solution source (mm_set_source)
+    int source = MM_SOURCE_NONE;
+    double src_t0 = 0.0;            // time of the state when the source was set
+    int src_step0 = 0;              // steps_done at that moment
+    double *msrc = nullptr;         // 2D: per-cell macro source moments [ncell][6]
 };
 
 namespace {
@@ -84,7 +90,7 @@ int check_cfg(const mm_config *c)
     for (int s = 0; s < nside; ++s) {
         const mm_bc &b = c->bc[s];
         if (b.kind < MM_BC_EXTRAP || b.kind > MM_BC_INFLOW) return MM_EINVAL;
-        if (c->dim == 1 && (b.kind == MM_BC_WALL || b.kind == MM_BC_INFLOW)) return MM_EINVAL;
+        if (c->dim == 1 && b.kind == MM_BC_INFLOW) return MM_EINVAL;
         if (b.kind == MM_BC_WALL && !(b.T_wall > 0.0)) return MM_EINVAL;
         if (b.kind == MM_BC_INFLOW && (!(b.rho > 0.0) || !(b.T > 0.0))) return MM_EINVAL;
     }
@@ -92,6 +98,8 @@ int check_cfg(const mm_config *c)
     if (c->dim == 2 && (c->bc[2].kind == MM_BC_PERIODIC) != (c->bc[3].kind == MM_BC_PERIODIC)) return MM_EINVAL;
     const double pts = (double)c->nx * (c->dim == 2 ? c->ny : 1) * c->nv1 * (c->dim == 2 ? c->nv2 : 1);
     if (pts > 4.0e10) return MM_EINVAL;
+    const int nbuf = (c->dev_buffers[0] != nullptr) + (c->dev_buffers[1] != nullptr) + (c->dev_buffers[2] != nullptr);
+    if (nbuf != 0 && (nbuf != 3 || c->dim != 2 || c->dev_buffers[0] == c->dev_buffers[1])) return MM_EINVAL;
     return MM_OK;
 }
 
@@ -178,19 +186,34 @@ void release(mm_ctx *c)
         c->pool.push_back(t.b);
     }
     for (hipEvent_t e : c->pool) hipEventDestroy(e);
-    double *bufs[] = {c->Q, c->Qs, c->H, c->rec, c->wrec, c->gmom, c->Gs};
+    double *bufs[] = {c->caller_buffers ? nullptr : c->Q, c->Qs, c->H, c->rec, c->wrec, c->gmom, c->Gs, c->msrc};
     for (double *b : bufs)
         if (b) hipFree(b);
     void *cbufs[] = {c->cl_feat, c->cl_kn, c->cl_out, c->cl_edge, c->cl_cls, c->cl_valid[0], c->cl_valid[1],
                      c->cl_ncl, c->cl_snap, c->cl_list, c->cl_nlist};
     for (void *b : cbufs)
         if (b) hipFree(b);
-    for (void *g : c->G)
-        if (g) hipFree(g);
+    if (!c->caller_buffers)
+        for (void *g : c->G)
+            if (g) hipFree(g);
     if (c->flag) hipFree(c->flag);
     if (c->Pd) hipFree(c->Pd);
     if (c->own_stream && c->st) hipStreamDestroy(c->st);
     delete c;
+}
+
+// the bookkeeping of a new state that is already in the device buffers
+int reset_state(mm_ctx *c)
+{
+    const int none = INT_MAX;
+    HIP_TRY(hipMemcpyAsync(c->flag, &none, sizeof(int), hipMemcpyHostToDevice, c->st));
+    // closure form: the given G is current everywhere
+    for (uint8_t *v : c->cl_valid)
+        if (v) HIP_TRY(hipMemsetAsync(v, 1, c->ncell, c->st));
+    HIP_TRY(hipMemsetAsync(c->H, 0, sizeof(double) * 4 * c->ncell, c->st));
+    HIP_TRY(hipStreamSynchronize(c->st));
+    c->failed = -1;
+    return MM_OK;
 }
 
 int upload_state(mm_ctx *c, const double *q, const double *g)
@@ -207,15 +230,7 @@ int upload_state(mm_ctx *c, const double *q, const double *g)
         HIP_TRY(hipMemcpyAsync(c->G[c->cur], tmp.data(), n * 4, hipMemcpyHostToDevice, c->st));
         HIP_TRY(hipStreamSynchronize(c->st));
     }
-    const int none = INT_MAX;
-    HIP_TRY(hipMemcpyAsync(c->flag, &none, sizeof(int), hipMemcpyHostToDevice, c->st));
-    // closure form: the given G is current everywhere
-    for (uint8_t *v : c->cl_valid)
-        if (v) HIP_TRY(hipMemsetAsync(v, 1, c->ncell, c->st));
-    HIP_TRY(hipMemsetAsync(c->H, 0, sizeof(double) * 4 * c->ncell, c->st));
-    HIP_TRY(hipStreamSynchronize(c->st));
-    c->failed = -1;
-    return MM_OK;
+    return reset_state(c);
 }
 
 // feature / class buffers of the closure form and of the snapshot entry points
@@ -303,11 +318,14 @@ int enqueue_steps(mm_ctx *c, int nsteps)
     if (c->closure && !c->closure_set) return MM_EINVAL;
     for (int s = 0; s < nsteps; ++s) {
         const int step = c->steps_done;
+        // time t^n of the old level, for the manufactured-solution source
+        const double tn = c->src_t0 + (step - c->src_step0) * P.dt;
         if (c->cfg.dim == 1) {
             void *Gn = c->G[1 - c->cur];
             {
                 Timer t(c, 0);
-                mm::launch_step1d(c->Q, c->Qs, (const double *)c->G[c->cur], (double *)Gn, c->H, c->flag, step, P, c->st);
+                mm::launch_step1d(c->Q, c->Qs, (const double *)c->G[c->cur], (double *)Gn, c->H, c->flag, step, P, c->st,
+                                  c->source, tn);
             }
             std::swap(c->Q, c->Qs);
         } else {
@@ -346,9 +364,14 @@ int enqueue_steps(mm_ctx *c, int nsteps)
                 mm::launch_micro_ref2d((const double *)c->G[c->cur], c->Gs, (double *)c->G[1 - c->cur], c->H,
                                        c->rec, c->wrec, P, c->st);
             }
+            if (c->source == MM_SOURCE_MMS) {
+                Timer t(c, 0);
+                mm::launch_source2d(c->G[1 - c->cur], c->gbytes, c->H, c->rec, c->msrc, P, tn, c->st);
+            }
             {
                 Timer t(c, 2);
-                mm::launch_macro2d(c->Q, c->Qs, c->H, c->flag, step, P, c->st);
+                mm::launch_macro2d(c->Q, c->Qs, c->H, c->flag, step, P, c->st,
+                                   c->source == MM_SOURCE_MMS ? c->msrc : nullptr);
             }
         }
         if (hipGetLastError() != hipSuccess) {
@@ -468,14 +491,16 @@ int mm_init(const mm_config *cfg, const double *q0, const double *g0, mm_ctx **o
     *out = nullptr;
     int rc = check_cfg(cfg);
     if (rc) return rc;
-    if (!q0) return MM_EINVAL;
+    const bool caller = cfg->dev_buffers[0] != nullptr;
+    if (!q0 && !caller) return MM_EINVAL;
     mm_ctx *c = new (std::nothrow) mm_ctx();
     if (!c) return MM_ENOMEM;
     c->cfg = *cfg;
+    c->caller_buffers = caller;
     c->ncell = cfg->nx * (cfg->dim == 2 ? cfg->ny : 1);
     c->nv = cfg->nv1 * (cfg->dim == 2 ? cfg->nv2 : 1);
     c->ncomp = cfg->dim == 2 ? 6 : 3;
-    if (!state_ok(cfg, q0, c->ncell)) {
+    if (q0 && !state_ok(cfg, q0, c->ncell)) {
         delete c;
         return MM_ENONPHYS;
     }
@@ -506,12 +531,18 @@ int mm_init(const mm_config *cfg, const double *q0, const double *g0, mm_ctx **o
         c->own_stream = true;
     }
     const size_t ncell = c->ncell, npts = ncell * c->nv;
-    bool ok = hipMalloc(&c->Q, sizeof(double) * c->ncomp * ncell) == hipSuccess &&
-              hipMalloc(&c->Qs, sizeof(double) * c->ncomp * ncell) == hipSuccess &&
+    bool ok = hipMalloc(&c->Qs, sizeof(double) * c->ncomp * ncell) == hipSuccess &&
               hipMalloc(&c->H, sizeof(double) * 4 * ncell) == hipSuccess &&
-              hipMalloc(&c->flag, sizeof(int)) == hipSuccess &&
-              hipMalloc(&c->G[0], npts * c->gbytes) == hipSuccess &&
-              hipMalloc(&c->G[1], npts * c->gbytes) == hipSuccess;
+              hipMalloc(&c->flag, sizeof(int)) == hipSuccess;
+    if (caller) {
+        c->G[0] = cfg->dev_buffers[0];
+        c->G[1] = cfg->dev_buffers[1];
+        c->Q = (double *)cfg->dev_buffers[2];
+    } else {
+        ok = ok && hipMalloc(&c->Q, sizeof(double) * c->ncomp * ncell) == hipSuccess &&
+             hipMalloc(&c->G[0], npts * c->gbytes) == hipSuccess &&
+             hipMalloc(&c->G[1], npts * c->gbytes) == hipSuccess;
+    }
     if (ok && cfg->dim == 2)
         ok = hipMalloc(&c->rec, sizeof(double) * mm::REC * ncell) == hipSuccess &&
              hipMalloc(&c->wrec, sizeof(double) * mm::WREC * ncell) == hipSuccess;
@@ -530,7 +561,7 @@ int mm_init(const mm_config *cfg, const double *q0, const double *g0, mm_ctx **o
         release(c);
         return MM_EDEVICE;
     }
-    rc = upload_state(c, q0, g0);
+    rc = q0 ? upload_state(c, q0, g0) : reset_state(c);
     if (rc) {
         release(c);
         return rc;
@@ -635,6 +666,26 @@ int mm_set_state(mm_ctx *ctx, const double *q, const double *g)
 void mm_free(mm_ctx *ctx) { release(ctx); }
 
 int mm_failed_step(const mm_ctx *ctx) { return ctx ? ctx->failed : -1; }
+
+int mm_set_source(mm_ctx *ctx, int kind, double t0)
+{
+    if (!ctx || (kind != MM_SOURCE_NONE && kind != MM_SOURCE_MMS) || !std::isfinite(t0)) return MM_EINVAL;
+    if (ctx->broken) return MM_ESTATE;
+    if (kind == MM_SOURCE_MMS && ctx->closure) return MM_EINVAL;
+    if (hipSetDevice(ctx->cfg.device) != hipSuccess) return MM_EDEVICE;
+    if (hipStreamSynchronize(ctx->st) != hipSuccess) return MM_EDEVICE;
+    if (kind == MM_SOURCE_MMS && ctx->cfg.dim == 2 && !ctx->msrc) {
+        if (hipMalloc(&ctx->msrc, sizeof(double) * 6 * ctx->ncell) != hipSuccess) {
+            hipGetLastError();
+            ctx->msrc = nullptr;
+            return MM_ENOMEM;
+        }
+    }
+    ctx->source = kind;
+    ctx->src_t0 = t0;
+    ctx->src_step0 = ctx->steps_done;
+    return MM_OK;
+}
 
 const char *mm_strerror(int status)
 {
@@ -764,6 +815,9 @@ int mm_closure_rebuild(mm_ctx *ctx, const float *out_host, const unsigned char *
     if (hipSetDevice(ctx->cfg.device) != hipSuccess) return MM_EDEVICE;
     int rc = ensure_closure_buffers(ctx, false);
     if (rc) return rc;
+    // the uploads below go through the null stream, which does not wait for the
+    // context's (non-blocking) stream: finish any enqueued steps first
+    if (hipStreamSynchronize(ctx->st) != hipSuccess) return MM_EDEVICE;
     const size_t n = ctx->ncell;
     // classes = mask and validity = not mask: exactly the masked cells are rebuilt
     uint8_t *cls = nullptr, *valid = nullptr, *vnext = nullptr;

@@ -517,7 +517,7 @@ __device__ __forceinline__ void load_q(const double *Q, int c, double q[6])
 template <int DIR>
 __global__ __launch_bounds__(256) void k_macro2d(const double *__restrict__ Qin, const double *__restrict__ H,
                                                  double *__restrict__ Qout, int *__restrict__ flag, int step,
-                                                 Params P)
+                                                 Params P, const double *__restrict__ msrc)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     const int c = t >> 2, role = t & 3;
@@ -589,6 +589,8 @@ __global__ __launch_bounds__(256) void k_macro2d(const double *__restrict__ Qin,
     for (int m = 0; m < 6; ++m) qo[m] = qc[m] - P.dt / h * (FR[m] - FL[m]);
     for (int a = 0; a < 3; ++a) qo[3 + a] -= P.dt * (HR[a] - HL[a]) / h;
     if (DIR == 1) {
+        if (msrc)
+            for (int m = 0; m < 6; ++m) qo[m] += P.dt * msrc[6 * (size_t)c + m];
         collide(P, qo);
         if (q_bad(qo)) atomicMin(flag, step + 1);
     }
@@ -611,7 +613,7 @@ template <int DIR>
 __global__ __launch_bounds__(MACRO_THREADS) void k_macro_line(const double *__restrict__ Qin,
                                                               const double *__restrict__ H,
                                                               double *__restrict__ Qout, int *__restrict__ flag,
-                                                              int step, Params P)
+                                                              int step, Params P, const double *__restrict__ msrc)
 {
     extern __shared__ double s_f[];   // [2][n][6]: F+ and F- of every cell of the line
     const int n = DIR == 0 ? P.nx : P.ny;
@@ -693,6 +695,8 @@ __global__ __launch_bounds__(MACRO_THREADS) void k_macro_line(const double *__re
         for (int m = 0; m < 6; ++m) qo[m] = qc[m] - P.dt / h * (FR[m] - FL[m]);
         for (int a = 0; a < 3; ++a) qo[3 + a] -= P.dt * (HR[a] - HL[a]) / h;
         if (DIR == 1) {
+            if (msrc)
+                for (int m = 0; m < 6; ++m) qo[m] += P.dt * msrc[6 * (size_t)c + m];
             collide(P, qo);
             if (q_bad(qo)) atomicMin(flag, step + 1);
         }
@@ -853,21 +857,24 @@ void launch_micro_ref2d(const double *G, double *Gs, double *Gn, double *H, cons
     hipLaunchKernelGGL(k_micro_y2d<4>, dim3(n), dim3(256), 0, st, Gs, Gn, H, rec, wrec, P);
 }
 
-void launch_macro2d(double *Q, double *Qs, const double *H, int *flag, int step, const Params &P, hipStream_t st)
+void launch_macro2d(double *Q, double *Qs, const double *H, int *flag, int step, const Params &P, hipStream_t st,
+                    const double *msrc)
 {
     const int n = P.nx * P.ny;
     // one workgroup per line where a line fits MACRO_LINE cells, else four lanes per cell
     const auto line_grid = [](int nline) { return dim3(((nline + 7) / 8) * 8); };
     if (P.nx <= MACRO_LINE)
         hipLaunchKernelGGL(k_macro_line<0>, line_grid(P.ny), dim3(MACRO_THREADS), 12 * sizeof(double) * P.nx, st,
-                           Q, H, Qs, flag, step, P);
+                           Q, H, Qs, flag, step, P, nullptr);
     else
-        hipLaunchKernelGGL(k_macro2d<0>, dim3((4 * n + 255) / 256), dim3(256), 0, st, Q, H, Qs, flag, step, P);
+        hipLaunchKernelGGL(k_macro2d<0>, dim3((4 * n + 255) / 256), dim3(256), 0, st, Q, H, Qs, flag, step, P,
+                           nullptr);
     if (P.ny <= MACRO_LINE)
         hipLaunchKernelGGL(k_macro_line<1>, line_grid(P.nx), dim3(MACRO_THREADS), 12 * sizeof(double) * P.ny, st,
-                           Qs, H, Q, flag, step, P);
+                           Qs, H, Q, flag, step, P, msrc);
     else
-        hipLaunchKernelGGL(k_macro2d<1>, dim3((4 * n + 255) / 256), dim3(256), 0, st, Qs, H, Q, flag, step, P);
+        hipLaunchKernelGGL(k_macro2d<1>, dim3((4 * n + 255) / 256), dim3(256), 0, st, Qs, H, Q, flag, step, P,
+                           msrc);
 }
 
 void launch_wall_relax2d(void *Gn, int g_bytes, double *H, const double *rec, const double *wrec, const Params &P,

@@ -8,7 +8,14 @@ namespace mm {
 void launch_prep2d(const double *Q, double *rec, double *wrec, int *flag, int step, const Params &P, hipStream_t st);
 void launch_micro_ref2d(const double *G, double *Gs, double *Gn, double *H, const double *rec, const double *wrec,
                         const Params &P, hipStream_t st);
-void launch_macro2d(double *Q, double *Qs, const double *H, int *flag, int step, const Params &P, hipStream_t st);
+// msrc: nullptr, or per-cell source moments [ncell][6] added (times dt) between the
+// y-sweep and the second collision half step
+void launch_macro2d(double *Q, double *Qs, const double *H, int *flag, int step, const Params &P, hipStream_t st,
+                    const double *msrc = nullptr);
+// manufactured-solution source of the 2D convergence study at time t (mm_source.hip):
+// adds (rb / tau)(I - Pi)[S] to Gn and its part to H, writes the macro source moments
+void launch_source2d(void *Gn, int g_bytes, double *H, const double *rec, double *msrc, const Params &P, double t,
+                     hipStream_t st);
 void launch_gmom2d(const void *G, int g_bytes, const double *rec, double *out, const Params &P, hipStream_t st);
 
 // wall-adjacent cells after a fused pass (Gn holds G** there)
@@ -32,7 +39,8 @@ bool launch_micro_closure2d(const void *G, void *Gn, double *H, const double *re
                             const Params &P, const Params *Pd, const uint8_t *cls, hipStream_t st);
 
 // 1D
+// mms != 0: with the manufactured-solution source of the 1D convergence study at time t
 void launch_step1d(const double *Q, double *Qn, const double *G, double *Gn, double *H, int *flag, int step,
-                   const Params &P, hipStream_t st);
+                   const Params &P, hipStream_t st, int mms = 0, double t = 0.0);
 
 } // namespace mm

@@ -1,8 +1,10 @@
 """Write the oracle's macro state after 100 steps of the 256^2 x 32^2 cavity
-workload (seed 0) for eps in {1e-3, 1e-2, 1e-1, 1}.
+workload (seed 0) for eps in {1e-3, 3e-3, 1e-2, 1e-1, 1}.
 
 Calls only the oracle.  Stored per eps: Q on every 4th cell in x and y
-(64 x 64 x 6 values, float64) and the domain sums of Q over all cells.
+(64 x 64 x 6 values, float64), Q of the whole boundary ring (the first and last
+row and column, which hold the lid and the wall cells), and the domain sums of
+Q over all cells.
 Run:  python tests/golden/make_c3_reference.py [threads]
 """
 import os
@@ -17,7 +19,7 @@ sys.path.insert(0, ROOT)
 import mm_workloads as W  # noqa: E402
 import oracle  # noqa: E402
 
-EPS = (1e-3, 1e-2, 1e-1, 1.0)
+EPS = (1e-3, 3e-3, 1e-2, 1e-1, 1.0)
 STEPS = 100
 STRIDE = 4
 
@@ -33,6 +35,10 @@ def main():
         Q1 = Q1.reshape(p["ny"], p["nx"], 6)
         key = f"eps{eps:g}"
         out[key + "_sample"] = Q1[::STRIDE, ::STRIDE, :].copy()
+        out[key + "_row_lo"] = Q1[0].copy()
+        out[key + "_row_hi"] = Q1[-1].copy()
+        out[key + "_col_lo"] = Q1[:, 0].copy()
+        out[key + "_col_hi"] = Q1[:, -1].copy()
         out[key + "_sum"] = Q1.reshape(-1, 6).sum(0)
         out[key + "_abssum"] = np.abs(Q1).reshape(-1, 6).sum(0)
         print(f"eps={eps:g}: {time.time() - t0:.1f} s", flush=True)

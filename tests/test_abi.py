@@ -55,7 +55,7 @@ def test_invalid_config_rejected(field, value):
     assert e.value.code == B.MM_EINVAL
 
 
-def test_unpaired_periodic_and_1d_walls_rejected():
+def test_unpaired_periodic_and_1d_inflow_rejected():
     from paper_2509_21832_amd import binding as B
     p, Q, G = W.quadrant2d(nx=4, ny=4, nv=4)
     p["bc"] = [{"kind": "periodic"}, {"kind": "wall"}, {"kind": "wall"}, {"kind": "wall"}]
@@ -63,7 +63,11 @@ def test_unpaired_periodic_and_1d_walls_rejected():
         B.Solver(p, Q)
     assert e.value.code == B.MM_EINVAL
     p1, Q1, G1 = W.sod1d(nx=8, nv=8)
-    p1["bc"][0] = {"kind": "wall"}
+    p1["bc"][0] = {"kind": "inflow"}
+    with pytest.raises(B.MMError) as e:
+        B.Solver(p1, Q1)
+    assert e.value.code == B.MM_EINVAL
+    p1["bc"][0] = {"kind": "wall", "T_wall": 0.0}
     with pytest.raises(B.MMError) as e:
         B.Solver(p1, Q1)
     assert e.value.code == B.MM_EINVAL
