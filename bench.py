@@ -68,13 +68,13 @@ def make_solver(B, p, Q, G, closure):
     return s
 
 
-def time_form(B, torch, p, Q, G, steps, warmup, closure=None):
+def time_form(B, torch, p, Q, G, steps, warmup, closure=None, warmup_seconds=WARMUP_SECONDS):
     s = make_solver(B, p, Q, G, closure)
-    # warm-up: at least `warmup` steps and at least WARMUP_SECONDS of them
+    # warm-up: at least `warmup` steps and at least warmup_seconds of them
     s.step(max(warmup, 1))
     done = max(warmup, 1)
     t0 = time.perf_counter()
-    while time.perf_counter() - t0 < WARMUP_SECONDS:
+    while time.perf_counter() - t0 < warmup_seconds:
         s.step(5)
         done += 5
     torch.cuda.synchronize()
@@ -160,33 +160,37 @@ def oracle_error_c4(B, p, steps=10):
     return float(np.abs(a - b).sum() / np.abs(b).sum())
 
 
-def cpu_baseline(p, seeds=(0, 1, 2)):
+def cpu_baseline(p, seeds=(0, 1, 2), gen=None, one_thread=True):
     """The oracle on the host cores, on a bounded sample of the workload: one full-size
-    step from each of three seeded initial states (all OpenMP threads; the median is
-    the value), then one full step on a single thread."""
+    step from each seeded initial state (all OpenMP threads; the median is the value),
+    then one full step on a single thread."""
     import oracle
+    gen = gen or (lambda sd: W.cavity2d(seed=sd, eps=p["eps"]))
     threads = oracle.threads()
     pts = p["nx"] * p["ny"] * p["nv1"] * p["nv2"]
     per = []
     for sd in seeds:
-        p0, Q, G = W.cavity2d(seed=sd, eps=p["eps"])
+        p0, Q, G = gen(sd)
         t0 = time.perf_counter()
         oracle.run(p0, Q.reshape(-1), G.reshape(-1), 1)
         per.append(time.perf_counter() - t0)
     med = float(np.median(per))
-    oracle.set_threads(1)
-    try:
-        p0, Q, G = W.cavity2d(seed=seeds[0], eps=p["eps"])
-        t0 = time.perf_counter()
-        oracle.run(p0, Q.reshape(-1), G.reshape(-1), 1)
-        per1 = time.perf_counter() - t0
-    finally:
-        oracle.set_threads(threads)
-    return {"value": pts / med, "unit": "phase-space cell-updates/s", "cores": threads, "kind": "oracle",
-            "value_1thread": pts / per1,
-            "sample": f"1 full step of the {p['nx']}x{p['ny']}x{p['nv1']}x{p['nv2']} workload from each of seeds "
-                      f"{list(seeds)} ({', '.join(f'{x:.2f}' for x in per)} s; median {med:.2f} s per step, "
-                      f"{threads} OpenMP threads), then 1 step on 1 thread ({per1:.2f} s)"}
+    out = {"value": pts / med, "unit": "phase-space cell-updates/s", "cores": threads, "kind": "oracle",
+           "sample": f"1 full step of the {p['nx']}x{p['ny']}x{p['nv1']}x{p['nv2']} workload from each of seeds "
+                     f"{list(seeds)} ({', '.join(f'{x:.2f}' for x in per)} s; median {med:.2f} s per step, "
+                     f"{threads} OpenMP threads)"}
+    if one_thread:
+        oracle.set_threads(1)
+        try:
+            p0, Q, G = gen(seeds[0])
+            t0 = time.perf_counter()
+            oracle.run(p0, Q.reshape(-1), G.reshape(-1), 1)
+            per1 = time.perf_counter() - t0
+        finally:
+            oracle.set_threads(threads)
+        out["value_1thread"] = pts / per1
+        out["sample"] += f", then 1 step on 1 thread ({per1:.2f} s)"
+    return out
 
 
 def copy_bandwidth(torch, gib=1.0, reps=10):
@@ -211,14 +215,14 @@ def copy_bandwidth(torch, gib=1.0, reps=10):
     return gbs
 
 
-def traffic_entry(precision):
+def traffic_entry(precision, workload="cavity"):
     """HBM bytes of the phase-space pass from committed rocprofv3 counter runs, if they
     were taken on the current kernel source."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     d = json.load(open(path))
-    e = d.get(precision)
+    e = d.get(precision if workload == "cavity" else f"{workload}_{precision}")
     if not e or e.get("kernel_hash") != kernel_hash():
         return None
     return e.get("bytes_per_launch")
@@ -237,11 +241,11 @@ def roofline(form, pts, micro_ms, copy_gbs):
     return r
 
 
-def run_form(B, torch, form, p, Q, G, steps, warmup, copy_gbs, closure=None, err=None):
+def run_form(B, torch, form, p, Q, G, steps, warmup, copy_gbs, closure=None, err=None, warmup_seconds=WARMUP_SECONDS):
     pf = dict(p)
     pf["precision"] = form
     pts = pf["nx"] * pf["ny"] * pf["nv1"] * pf["nv2"]
-    r = time_form(B, torch, pf, Q, G, steps, warmup, closure)
+    r = time_form(B, torch, pf, Q, G, steps, warmup, closure, warmup_seconds)
     r["value"] = pts * steps / r["seconds"]
     r["ms_per_step"] = 1e3 * r["seconds"] / steps
     r["err_vs_oracle"] = err(pf) if err else None
@@ -272,6 +276,11 @@ def main():
     ap.add_argument("--no-error", action="store_true")
     ap.add_argument("--no-sweep", action="store_true",
                     help="time only the headline workload (no eps sweeps, no 512^2 x 48^2 blast)")
+    ap.add_argument("--warmup-seconds", type=float, default=WARMUP_SECONDS,
+                    help="least time of warm-up steps per form (0 for profiler runs)")
+    ap.add_argument("--workload", default="cavity", choices=("cavity", "blast"),
+                    help="headline workload: the 256^2 x 32^2 cavity box (default) or the 512^2 x 48^2 Gaussian "
+                         "blast (forms fp64 and mixed only; implies --no-sweep)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="first run one plain device-to-device copy of MIB MiB (the reference kernel that "
                          "scales the HBM byte counters of a profiler run)")
@@ -301,7 +310,15 @@ def main():
     def c3_err(eps, closure=None):
         return None if args.no_error else (lambda pf: oracle_error(B, pf, eps, closure=closure))
 
-    p, Q, G = W.cavity2d(seed=0, eps=args.eps)
+    if args.workload == "blast":
+        p, Q, G = W.blast2d(seed=0)
+        args.no_sweep = True
+        args.forms = ",".join(f for f in args.forms.split(",") if f != "closure")
+
+        def c3_err(eps, closure=None):       # noqa: F811 (the blast's own stored checkpoint)
+            return None if args.no_error else (lambda pf: oracle_error_c4(B, pf))
+    else:
+        p, Q, G = W.cavity2d(seed=0, eps=args.eps)
     pts = p["nx"] * p["ny"] * p["nv1"] * p["nv2"]
     forms = {}
     closure = None
@@ -322,12 +339,13 @@ def main():
     for form in [f for f in args.forms.split(",") if f]:
         cl = get_closure() if form == "closure" else None
         try:
-            r = run_form(B, torch, form, p, Q, G, args.steps, args.warmup, copy_gbs, cl, c3_err(args.eps, cl))
+            r = run_form(B, torch, form, p, Q, G, args.steps, args.warmup, copy_gbs, cl, c3_err(args.eps, cl),
+                         args.warmup_seconds)
         except B.MMError as e:
             log(f"form {form}: {e}")
             continue
         if r["roofline"]:
-            r["roofline"]["traffic"] = traffic_entry(form)
+            r["roofline"]["traffic"] = traffic_entry(form, args.workload)
         forms[form] = r
         log(f"{form}: {r['ms_per_step']:.3f} ms/step, {r['value']:.3e} updates/s, micro pass "
             f"{r['micro_ms']:.3f} ms, err {r['err_vs_oracle']}")
@@ -345,7 +363,7 @@ def main():
                     r = forms[form]
                 else:
                     r = run_form(B, torch, form, pe, Qe, Ge, args.steps, args.warmup, copy_gbs,
-                                 err=c3_err(eps))
+                                 err=c3_err(eps), warmup_seconds=args.warmup_seconds)
                 row[form] = summary(r, base.get(eps))
                 if form == "fp64":
                     base[eps] = r
@@ -361,7 +379,7 @@ def main():
                     r = forms["closure"]
                 else:
                     r = run_form(B, torch, "closure", pe, Qe, Ge, args.steps, args.warmup, copy_gbs, cl,
-                                 c3_err(eps, cl))
+                                 c3_err(eps, cl), args.warmup_seconds)
                 row = {"eps": eps, "closure": summary(r, base.get(eps))}
                 sweeps["c5_closure_eps"].append(row)
                 log(f"c5 eps={eps:g}: {r['ms_per_step']:.3f} ms/step, closure cells {r['closure_fraction']}, "
@@ -371,7 +389,8 @@ def main():
         c4 = {}
         for form in ("fp64", "mixed"):
             errf = None if args.no_error else (lambda pf: oracle_error_c4(B, pf))
-            r = run_form(B, torch, form, pb, Qb, Gb, max(10, args.steps // 4), args.warmup, copy_gbs, err=errf)
+            r = run_form(B, torch, form, pb, Qb, Gb, max(10, args.steps // 4), args.warmup, copy_gbs, err=errf,
+                         warmup_seconds=args.warmup_seconds)
             c4[form] = r
             log(f"c4 {form}: {r['ms_per_step']:.3f} ms/step, pass {r['micro_ms']:.3f} ms, err {r['err_vs_oracle']}")
         sweeps["c4_blast"] = {
@@ -397,9 +416,12 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"2D2V cavity box {p['nx']}x{p['ny']} cells x {p['nv1']}x{p['nv2']} velocity "
-                               f"nodes on [-7,7]^2, walls + moving lid u_w=0.2, eps={args.eps:g}, FP64",
-                   "phase_points": pts, "eps": args.eps, "seed": 0},
+        "config": {"workload": (f"2D2V cavity box {p['nx']}x{p['ny']} cells x {p['nv1']}x{p['nv2']} velocity "
+                                f"nodes on [-7,7]^2, walls + moving lid u_w=0.2, eps={args.eps:g}, FP64"
+                                if args.workload == "cavity" else
+                                f"2D2V Gaussian blast {p['nx']}x{p['ny']} cells x {p['nv1']}x{p['nv2']} velocity "
+                                f"nodes on [-8,8]^2, walls, eps={p['eps']:g}, FP64"),
+                   "phase_points": pts, "eps": p["eps"], "seed": 0},
         "roofline": main_form["roofline"],
         "err_vs_oracle": main_form["err_vs_oracle"],
         "forms": {k: summary(v, forms.get("fp64")) for k, v in forms.items()},
@@ -409,7 +431,10 @@ def main():
     if closure is not None:
         out["closure_training"] = {k: closure[k] for k in ("train_seconds", "train_samples", "final_loss")}
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(p)
+        if args.workload == "blast":
+            out["cpu_baseline"] = cpu_baseline(p, seeds=(0,), gen=lambda sd: W.blast2d(seed=sd), one_thread=False)
+        else:
+            out["cpu_baseline"] = cpu_baseline(p)
     print(json.dumps(out), flush=True)
 
 

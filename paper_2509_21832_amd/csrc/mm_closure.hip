@@ -812,7 +812,7 @@ __global__ __launch_bounds__(256) void k_rebuild2d(TS *__restrict__ G, const dou
         const double a11 = o[2] - tr, a12 = o[3], a22 = o[4] - tr;
         const double pre = 1.0 / (2.0 * p * T);
         double s[4] = {0.0, 0.0, 0.0, 0.0};
-        if (lk_step(P.nv1, P.nv2, P.dv2) > 0.0) {
+        if (lk_lanes(P.nv1, P.nv2) == 64) {
             // lane-k layout: lane (k, l0) owns the nodes (k, l0 + L m); the Maxwellian
             // follows e(m+1) = e(m) r(m), r(m+1) = r(m) kappa along them
             const int L = 64 / P.nv1, k = lane % P.nv1, l0 = lane / P.nv1, npt = P.nv / 64;

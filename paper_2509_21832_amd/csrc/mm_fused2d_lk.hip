@@ -1,11 +1,14 @@
 // mm_fused2d_lk.hip -- the fused phase-space pass specialised to velocity grids
-// whose nv1 divides the wavefront width (nv1 in {2, 4, ..., 64}).
+// that map onto a wavefront by whole v1 rows: nv1 divides the wavefront width
+// (nv1 in {2, 4, ..., 64}, all 64 lanes active), or nv1 is 24 or 48 (48 lanes
+// active, the other 16 idle).
 //
 // Same step as mm_fused2d.hip (Sec. 5.3: x-transport, y-transport, G-hat of
 // eqn5-97, relaxation eqn5-98, H of eqn5-99; wall-adjacent cells get G** only
 // and are finished by k_wall_relax2d);
-// what changes is the arithmetic layout.  With node p = lane + 64 m a lane owns
-// one velocity k = lane mod nv1 and the nodes l = l0 + L m (L = 64 / nv1), so
+// what changes is the arithmetic layout.  With A = L nv1 active lanes (L = 64 / nv1,
+// integer division) and node p = lane + A m, a lane owns one velocity
+// k = lane mod nv1 and the nodes l = l0 + L m, so
 //   - v1, the x-upwind weights and w1 = v1 - u1 are per-lane constants;
 //   - every per-node polynomial (projection, the closed form of G-hat) is a
 //     short Horner form in v2 whose coefficients a lane computes once per cell;
@@ -28,7 +31,9 @@ using namespace fused;
 // SYM: the v2 grid is symmetric about 0 with nv2 / 2 a multiple of 64 / nv1, so
 // node m of every lane has v2 < 0 exactly when m < NPT / 2 and the y-upwind side
 // is known when the kernel is compiled (checked on the host at launch)
-template <typename TS, typename TC, int NPT, bool CL, bool SYM>
+// ACT: active lanes (64, or 48 with 16 idle lanes whose loads fall outside the
+// buffer and read 0, whose stores are dropped, and whose sums are masked)
+template <typename TS, typename TC, int NPT, bool CL, bool SYM, int ACT>
 struct PassLK {
     // FP64: cell records are loaded rows ahead into VGPRs (one wavefront per SIMD
     // has the registers); FP32 keeps two wavefronts per SIMD and reads them in place
@@ -49,6 +54,7 @@ struct PassLK {
     static constexpr bool STASH = MM_LK_STASH && sizeof(TC) == 8 && NPT >= 16;
     TC *st;                 // this wavefront's slice: [NPT][64]
     int lane, i, k, l0, L;
+    double act;             // 1 on an active lane, 0 on an idle one
     int row_bytes;          // bytes of one row of cells of g
     int off_c, off_u;       // byte offsets in its row of this lane's value of cell i and of its upwind cell
     double v1d, v2bd, hd;   // v1 of this lane; v2 of node m: v2b + m h
@@ -117,9 +123,9 @@ struct PassLK {
     __device__ __forceinline__ __amdgpu_buffer_rsrc_t row(const TS *base, int r) const
     {
         r = __builtin_amdgcn_readfirstlane(r);
-        return buf_rsrc(base + (size_t)r * P->nx * (64 * NPT), row_bytes);
+        return buf_rsrc(base + (size_t)r * P->nx * (ACT * NPT), row_bytes);
     }
-    static constexpr int NB = 64 * (int)sizeof(TS);   // byte stride of node m
+    static constexpr int NB = ACT * (int)sizeof(TS);   // byte stride of node m
 
     __device__ __forceinline__ void load(__amdgpu_buffer_rsrc_t rs, int off, TC (&out)[NPT]) const
     {
@@ -183,6 +189,12 @@ struct PassLK {
         for (int m = 0; m < NPT; ++m, w += h) {
             const TC pm = (c3 * w + c2) * w + K;
             out[m] = pm * (TC)mq.next() + out[m];
+        }
+        if constexpr (ACT < 64) {
+            if (act == 0.0) {
+#pragma unroll
+                for (int m = 0; m < NPT; ++m) out[m] = (TC)0;
+            }
         }
         return GqS{m0.e, m0.r};
     }
@@ -302,6 +314,11 @@ struct PassLK {
                 S[2] += (tn(m) * tn(m)) * dd;
             }
         }
+        if constexpr (ACT < 64) {
+            S[0] *= act;
+            S[1] *= act;
+            S[2] *= act;
+        }
         double s[4];
         raw4(S, s);
         wave_sum<4>(s, lane);
@@ -325,6 +342,10 @@ struct PassLK {
             T[1] += tn(m) * g;
             T[2] += (tn(m) * tn(m)) * g;
             T[3] += (tn(m) * tn(m) * tn(m)) * g;
+        }
+        if constexpr (ACT < 64) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) T[q] *= act;
         }
         // sum g w2^p with w2 = v2 - u2 = e + t h (e: the lane's centre velocity minus u2)
         const double e = vc() - u2d, e2 = e * e, h2 = hd * hd;
@@ -445,11 +466,11 @@ struct PassLK {
 #endif
 template <typename TC, int NPT>
 struct LKTraits {
-    static constexpr bool big = sizeof(TC) * NPT >= 128;
+    static constexpr bool big = sizeof(TC) * NPT >= 128;   // the same rule picks the launch geometry
     static constexpr int occupancy = big ? MM_LK_OCC64 : 2;
 };
 
-template <typename TS, typename TC, int NPT, bool CL, bool SYM>
+template <typename TS, typename TC, int NPT, bool CL, bool SYM, int ACT>
 __global__ __launch_bounds__(64 * WPG, (LKTraits<TC, NPT>::occupancy)) void k_fused2d_lk(const TS *__restrict__ G, TS *__restrict__ Gn,
                                                             double *__restrict__ H, const double *__restrict__ rec,
                                                             const double *__restrict__ wrec,
@@ -461,7 +482,7 @@ __global__ __launch_bounds__(64 * WPG, (LKTraits<TC, NPT>::occupancy)) void k_fu
     if (t >= geo.ntiles) return;
     const int cg = t % geo.ncg, sg = t / geo.ncg;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform: cell indices live in SGPRs
-    using Pass = PassLK<TS, TC, NPT, CL, SYM>;
+    using Pass = PassLK<TS, TC, NPT, CL, SYM, ACT>;
     Pass ps;
     __shared__ TC s_st[Pass::STASH ? WPG * NPT * 64 : 1];
     ps.st = s_st + (Pass::STASH ? wv * NPT * 64 : 0);
@@ -472,6 +493,7 @@ __global__ __launch_bounds__(64 * WPG, (LKTraits<TC, NPT>::occupancy)) void k_fu
     if (ps.i >= P.nx) return;
     ps.k = ps.lane % P.nv1;
     ps.L = 64 / P.nv1;
+    ps.act = ps.lane < ACT ? 1.0 : 0.0;
     ps.l0 = ps.lane / P.nv1;
     ps.v1d = P.v1_lo + (ps.k + 0.5) * P.dv1;
     ps.v2bd = P.v2_lo + (ps.l0 + 0.5) * P.dv2;
@@ -490,9 +512,11 @@ __global__ __launch_bounds__(64 * WPG, (LKTraits<TC, NPT>::occupancy)) void k_fu
                 iu = ps.i;
             }
         }
-        ps.row_bytes = P.nx * 64 * NPT * (int)sizeof(TS);
-        ps.off_c = (ps.i * 64 * NPT + ps.lane) * (int)sizeof(TS);
-        ps.off_u = (iu * 64 * NPT + ps.lane) * (int)sizeof(TS);
+        ps.row_bytes = P.nx * ACT * NPT * (int)sizeof(TS);
+        ps.off_c = (ps.i * ACT * NPT + ps.lane) * (int)sizeof(TS);
+        ps.off_u = (iu * ACT * NPT + ps.lane) * (int)sizeof(TS);
+        // an idle lane addresses past the row: its loads read 0, its stores are dropped
+        if (ps.lane >= ACT) ps.off_c = ps.off_u = ps.row_bytes;
         ps.zero_nb = ghost && is_open(P.bc[side].kind);
         ps.edge_col = __ballot(ps.zero_nb) != 0;
     }
@@ -538,25 +562,41 @@ __global__ __launch_bounds__(64 * WPG, (LKTraits<TC, NPT>::occupancy)) void k_fu
 }
 
 template <typename TS, typename TC, bool CL, bool SYM>
-bool launch_lk_t(int npt, const void *G, void *Gn, double *H, const double *rec, const double *wrec,
+bool launch_lk_t(int npt, int act, const void *G, void *Gn, double *H, const double *rec, const double *wrec,
                  const Params *Pd, const Geom &geo, const uint8_t *cls, hipStream_t st)
 {
     const dim3 grid(((geo.ntiles + 7) / 8) * 8), block(64 * WPG);
-#define MM_CASE(N)                                                                                          \
-    case N:                                                                                                 \
-        hipLaunchKernelGGL((k_fused2d_lk<TS, TC, N, CL, SYM>), grid, block, 0, st, (const TS *)G, (TS *)Gn,  \
-                           H, rec, wrec, Pd, geo, cls);                                                     \
-        return true;
-    switch (npt) {
-        MM_CASE(1)
-        MM_CASE(2)
-        MM_CASE(4)
-        MM_CASE(8)
-        MM_CASE(16)
-    default:
-        return false;
+#define MM_LAUNCH(N, ACT)                                                                                   \
+    hipLaunchKernelGGL((k_fused2d_lk<TS, TC, N, CL, SYM, ACT>), grid, block, 0, st, (const TS *)G,         \
+                       (TS *)Gn, H, rec, wrec, Pd, geo, cls)
+    if (act == 64) {
+        switch (npt) {
+        case 1: MM_LAUNCH(1, 64); return true;
+        case 2: MM_LAUNCH(2, 64); return true;
+        case 4: MM_LAUNCH(4, 64); return true;
+        case 8: MM_LAUNCH(8, 64); return true;
+        case 16: MM_LAUNCH(16, 64); return true;
+        default: return false;
+        }
     }
-#undef MM_CASE
+    if constexpr (!CL) {
+        if (npt == 12) {
+            MM_LAUNCH(12, 48);
+            return true;
+        }
+        if (npt == 24) {
+            MM_LAUNCH(24, 48);
+            return true;
+        }
+        if constexpr (sizeof(TC) == 4) {
+            if (npt == 48) {
+                MM_LAUNCH(48, 48);
+                return true;
+            }
+        }
+    }
+    return false;
+#undef MM_LAUNCH
 }
 
 // Wall-adjacent cells in the lane-k layout (one wavefront per ring cell, the
@@ -577,7 +617,7 @@ struct GqW {
     }
 };
 
-template <typename TS, int NPT>
+template <typename TS, int NPT, int ACT>
 __global__ __launch_bounds__(256) void k_wall_lk(TS *__restrict__ Gn, double *__restrict__ H,
                                                   const double *__restrict__ rec, const double *__restrict__ wrec,
                                                   Params P, int nring)
@@ -614,31 +654,48 @@ __global__ __launch_bounds__(256) void k_wall_lk(TS *__restrict__ Gn, double *__
     }
     const int bytes = P.nv * (int)sizeof(TS);
     const auto rs = buf_rsrc(Gn + c * (size_t)P.nv, bytes);
-    const int off = lane * (int)sizeof(TS);
-    constexpr int NB = 64 * (int)sizeof(TS);
-    double g[NPT], mup[NPT], es[NPT];
+    // an idle lane (lane >= ACT) addresses past the cell: it reads 0 and writes nothing
+    const int off = lane < ACT ? lane * (int)sizeof(TS) : bytes;
+    const double act = lane < ACT ? 1.0 : 0.0;
+    constexpr int NB = ACT * (int)sizeof(TS);
+    // the upwind Maxwellian difference and the ES term of node m are held between the
+    // two node loops, or (long lanes) recomputed in the second from the recurrences
+    constexpr bool HOLD = NPT <= 16;
+    TS g[NPT];
+    double mup[HOLD ? NPT : 1], es[HOLD ? NPT : 1];
 #pragma unroll
-    for (int m = 0; m < NPT; ++m) g[m] = (double)buf_load(rs, off, NB * m, (TS *)nullptr);
+    for (int m = 0; m < NPT; ++m) g[m] = buf_load(rs, off, NB * m, (TS *)nullptr);
     const double ax = fmin(v1, 0.0) * idx, bx = fmax(v1, 0.0) * idx;
+    auto node = [&](int m, GqW &mq, GqW (&mv)[4], GqW &gv, double &mu, double &e) {
+        const double w = v2b + m * h;
+        const double M = mq.next(), M0 = mv[0].next(), M1 = mv[1].next(), M2 = mv[2].next(), M3 = mv[3].next();
+        mu = (ax * (M1 - M) + bx * (M - M0)) + (fmin(w, 0.0) * (M3 - M) + fmax(w, 0.0) * (M - M2)) * idy;
+        e = es_on ? (gv.next() - M) * ieps : 0.0;
+        return M;
+    };
     double acc[6] = {0, 0, 0, 0, 0, 0};
     {
-        GqW mq = m0;
+        GqW mq = m0, mv[4] = {mn[0], mn[1], mn[2], mn[3]}, gv = gq;
 #pragma unroll
         for (int m = 0; m < NPT; ++m) {
             const double w = v2b + m * h;
-            const double M = mq.next(), M0 = mn[0].next(), M1 = mn[1].next(), M2 = mn[2].next(),
-                         M3 = mn[3].next();
-            mup[m] = (ax * (M1 - M) + bx * (M - M0)) + (fmin(w, 0.0) * (M3 - M) + fmax(w, 0.0) * (M - M2)) * idy;
-            es[m] = es_on ? (gq.next() - M) * ieps : 0.0;
-            const double uz = w * mup[m], ub = w * es[m];
-            acc[0] += mup[m];
+            double mu, e;
+            node(m, mq, mv, gv, mu, e);
+            if constexpr (HOLD) {
+                mup[m] = mu;
+                es[m] = e;
+            }
+            const double uz = w * mu, ub = w * e;
+            acc[0] += mu;
             acc[1] += uz;
             acc[2] += w * uz;
-            acc[3] += es[m];
+            acc[3] += e;
             acc[4] += ub;
             acc[5] += w * ub;
         }
     }
+#pragma unroll
+    for (int q = 0; q < 6; ++q) acc[q] *= act;
     // G-hat = -itau (mup - Pi[mup]) + (es - Pi[es]) (es unprojected in the paper's
     // form) = -itau mup + es + Pi[itau mup - es]: one projection of combined moments
     const double v1s = v1 * v1, eb = discrete ? 1.0 : 0.0;
@@ -651,21 +708,29 @@ __global__ __launch_bounds__(256) void k_wall_lk(TS *__restrict__ Gn, double *__
     const double ra = R[R_A], rb = R[R_B];
     const double a = v1 - u1;
     double h0 = 0.0, h1 = 0.0, h2 = 0.0, h3 = 0.0;
-    GqW mq = m0;
+    GqW mq = m0, mv[4] = {mn[0], mn[1], mn[2], mn[3]}, gv = gq;
 #pragma unroll
     for (int m = 0; m < NPT; ++m) {
-        const double w = v2b + m * h, M = mq.next();
-        const double gh = -itau * mup[m] + es[m] + ((o[3] * w + o[2]) * w + K) * M;
-        const TS gn = (TS)(ra * g[m] + rb * gh);
+        const double w = v2b + m * h;
+        double M, mu, e;
+        if constexpr (HOLD) {
+            M = mq.next();
+            mu = mup[m];
+            e = es[m];
+        } else {
+            M = node(m, mq, mv, gv, mu, e);
+        }
+        const double gh = -itau * mu + e + ((o[3] * w + o[2]) * w + K) * M;
+        const TS gn = (TS)(ra * (double)g[m] + rb * gh);
         buf_store(gn, rs, off, NB * m);
-        const double gv = (double)gn, w2 = w - u2;
-        const double ug = gv * w2, ug2 = ug * w2;
-        h0 += gv;
+        const double gvl = (double)gn, w2 = w - u2;
+        const double ug = gvl * w2, ug2 = ug * w2;
+        h0 += gvl;
         h1 += ug;
         h2 += ug2;
         h3 += ug2 * w2;
     }
-    double hs[4] = {a * a * a * h0, a * a * h1, a * h2, h3};
+    double hs[4] = {act * a * a * a * h0, act * a * a * h1, act * a * h2, act * h3};
     wave_sum<4>(hs, lane);
     if (lane == 0) {
         const double f = P.eps * P.dv1 * P.dv2;
@@ -675,40 +740,62 @@ __global__ __launch_bounds__(256) void k_wall_lk(TS *__restrict__ Gn, double *__
 
 } // namespace
 
-bool lk_supported(const Params &P)
+// nodes per lane of the lane-k layout of P (0: no layout): A = 64 lanes take
+// 1, 2, 4, 8 or 16 nodes each; A = 48 lanes take 12 or 24 (both storage
+// precisions) or 48 (g in FP32 only)
+static int lk_npt(const Params &P, int precision)
 {
-    if (P.nv1 > 64 || 64 % P.nv1 != 0) return false;
-    const int L = 64 / P.nv1;
-    if (P.nv2 % L != 0 || P.nv2 > MAXV) return false;
-    const int npt = P.nv / 64;
+    const int A = lk_lanes(P.nv1, P.nv2);
+    if (A == 0 || P.nv2 > MAXV) return 0;
     // a row of cells of g is addressed with 32-bit byte offsets
-    if ((long long)P.nx * P.nv * 8 >= (1LL << 31)) return false;
-    return npt == 1 || npt == 2 || npt == 4 || npt == 8 || npt == 16;
+    if ((long long)P.nx * P.nv * 8 >= (1LL << 31)) return 0;
+    const int npt = P.nv / A;
+    if (A == 64) return (npt == 1 || npt == 2 || npt == 4 || npt == 8 || npt == 16) ? npt : 0;
+    return (npt == 12 || npt == 24 || (npt == 48 && precision != 0)) ? npt : 0;
 }
+
+bool lk_supported(const Params &P) { return lk_lanes(P.nv1, P.nv2) == 64 && lk_npt(P, 0) != 0; }
 
 bool launch_wall_lk2d(void *Gn, int g_bytes, double *H, const double *rec, const double *wrec, const Params &P,
                       hipStream_t st)
 {
-    if (!lk_supported(P)) return false;
+    const int A = lk_lanes(P.nv1, P.nv2), npt = lk_npt(P, g_bytes == 8 ? 0 : 1);
+    if (npt == 0) return false;
     const int nring = 2 * P.nx + 2 * (P.ny - 2);
     const dim3 grid((nring + 3) / 4), block(256);
-#define MM_CASE(N)                                                                                            \
-    case N:                                                                                                   \
-        if (g_bytes == 8)                                                                                     \
-            hipLaunchKernelGGL((k_wall_lk<double, N>), grid, block, 0, st, (double *)Gn, H, rec, wrec, P, nring); \
-        else                                                                                                  \
-            hipLaunchKernelGGL((k_wall_lk<float, N>), grid, block, 0, st, (float *)Gn, H, rec, wrec, P, nring);   \
-        return true;
-    switch (P.nv / 64) {
-        MM_CASE(1)
-        MM_CASE(2)
-        MM_CASE(4)
-        MM_CASE(8)
-        MM_CASE(16)
-    default:
-        return false;
+#define MM_LAUNCH(N, ACT)                                                                                      \
+    do {                                                                                                       \
+        if (g_bytes == 8)                                                                                      \
+            hipLaunchKernelGGL((k_wall_lk<double, N, ACT>), grid, block, 0, st, (double *)Gn, H, rec, wrec, P,  \
+                               nring);                                                                         \
+        else                                                                                                   \
+            hipLaunchKernelGGL((k_wall_lk<float, N, ACT>), grid, block, 0, st, (float *)Gn, H, rec, wrec, P,    \
+                               nring);                                                                         \
+    } while (0)
+    if (A == 64) {
+        switch (npt) {
+        case 1: MM_LAUNCH(1, 64); return true;
+        case 2: MM_LAUNCH(2, 64); return true;
+        case 4: MM_LAUNCH(4, 64); return true;
+        case 8: MM_LAUNCH(8, 64); return true;
+        case 16: MM_LAUNCH(16, 64); return true;
+        default: return false;
+        }
     }
-#undef MM_CASE
+    if (npt == 12) {
+        MM_LAUNCH(12, 48);
+        return true;
+    }
+    if (npt == 24) {
+        MM_LAUNCH(24, 48);
+        return true;
+    }
+    if (g_bytes == 4) {
+        hipLaunchKernelGGL((k_wall_lk<float, 48, 48>), grid, block, 0, st, (float *)Gn, H, rec, wrec, P, nring);
+        return true;
+    }
+    return false;
+#undef MM_LAUNCH
 }
 
 // The v2 grid is symmetric about 0 and each lane has as many nodes below 0 as
@@ -726,25 +813,29 @@ static bool v2_symmetric_lk(const Params &P)
 bool launch_micro_lk2d(const void *G, void *Gn, double *H, const double *rec, const double *wrec,
                        const Params &P, const Params *Pd, int precision, const uint8_t *cls, hipStream_t st)
 {
-    if (!lk_supported(P)) return false;
-    const int npt = P.nv / 64;
-    const bool one_wave = precision == 0 && 8 * npt >= 128 && MM_LK_OCC64 == 1;
+    const int act = lk_lanes(P.nv1, P.nv2), npt = lk_npt(P, precision);
+    if (npt == 0) return false;
+    // the instances with 128 bytes of g per lane and more run one wavefront per SIMD
+    const bool one_wave = (precision == 0 ? 8 : 4) * npt >= 128 && MM_LK_OCC64 == 1;
     const Geom geo = geometry(P, one_wave ? 1 : 2);
-    if (cls) {   // closure form: g in FP32 only
+    if (cls) {   // closure form: g in FP32 only, 64 active lanes
+        if (act != 64) return false;
         // the solved cells cluster along the walls: short row segments spread a
         // fully solved column over many wavefronts
         Geom gc = geo;
         gc.seg = P.ny < 4 ? P.ny : 4;        // at most 61 (one class bit per lane)
         gc.nseg = (P.ny + gc.seg - 1) / gc.seg;
         gc.ntiles = gc.ncg * gc.nseg;
-        return precision != 0 && launch_lk_t<float, float, true, false>(npt, G, Gn, H, rec, wrec, Pd, gc, cls, st);
+        return precision != 0 &&
+               launch_lk_t<float, float, true, false>(npt, act, G, Gn, H, rec, wrec, Pd, gc, cls, st);
     }
     if (v2_symmetric_lk(P))
         return precision == 0
-                   ? launch_lk_t<double, double, false, true>(npt, G, Gn, H, rec, wrec, Pd, geo, nullptr, st)
-                   : launch_lk_t<float, float, false, true>(npt, G, Gn, H, rec, wrec, Pd, geo, nullptr, st);
-    return precision == 0 ? launch_lk_t<double, double, false, false>(npt, G, Gn, H, rec, wrec, Pd, geo, nullptr, st)
-                          : launch_lk_t<float, float, false, false>(npt, G, Gn, H, rec, wrec, Pd, geo, nullptr, st);
+                   ? launch_lk_t<double, double, false, true>(npt, act, G, Gn, H, rec, wrec, Pd, geo, nullptr, st)
+                   : launch_lk_t<float, float, false, true>(npt, act, G, Gn, H, rec, wrec, Pd, geo, nullptr, st);
+    return precision == 0
+               ? launch_lk_t<double, double, false, false>(npt, act, G, Gn, H, rec, wrec, Pd, geo, nullptr, st)
+               : launch_lk_t<float, float, false, false>(npt, act, G, Gn, H, rec, wrec, Pd, geo, nullptr, st);
 }
 
 } // namespace mm

@@ -70,15 +70,25 @@ enum {
 // (rho / (2 pi T), u1, u2, 1 / (2T))
 enum { WREC = 16 };
 
+// Lanes of a wavefront that the lane-k phase-space pass uses: L = 64 / nv1 lanes
+// (integer division) share each v1 node, A = L nv1 lanes are active, and lane
+// k + nv1 l0 (k < nv1, l0 < L) owns the nodes (k, l0 + L m), m < nv2 / L, i.e. the
+// flat nodes lane + A m.  A layout exists when nv1 <= 64, L divides nv2 and A is 64
+// (nv1 divides 64) or 48 (nv1 = 24 or 48), the two widths built; 0 otherwise.
+__host__ __device__ inline int lk_lanes(int nv1, int nv2)
+{
+    if (nv1 < 1 || nv1 > 64) return 0;
+    const int L = 64 / nv1, A = L * nv1;
+    if ((A != 64 && A != 48) || nv2 < L || nv2 % L != 0) return 0;
+    return A;
+}
+
 // Step in v2 between consecutive nodes of one lane in the lane-k phase-space
-// pass (nv1 divides 64; lane k + nv1 l0 owns the nodes (k, l0 + (64 / nv1) m)),
-// or 0 where that layout does not apply
+// pass (L dv2), or 0 where that layout does not apply
 __host__ __device__ inline double lk_step(int nv1, int nv2, double dv2)
 {
-    if (nv1 > 64 || 64 % nv1 != 0) return 0.0;
-    const int L = 64 / nv1;
-    if (nv2 % L != 0 || nv1 * nv2 < 64) return 0.0;
-    return L * dv2;
+    if (lk_lanes(nv1, nv2) == 0) return 0.0;
+    return (64 / nv1) * dv2;
 }
 
 // Range rule of the 2D solver: the Maxwellian and ES Gaussian exponents, and the

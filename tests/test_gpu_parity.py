@@ -71,6 +71,29 @@ LANE_K = {
 }
 
 
+# 48 active lanes (nv1 = 24 or 48; 16 idle lanes): 12 nodes per lane in both precisions,
+# 48 nodes per lane with g in FP32 (the 512^2 x 48^2 blast's velocity grid)
+LANE_K48 = {
+    "lk48_24x24_walls": (lambda: _velocity(lambda: W.quadrant2d(seed=30, nx=11, ny=13, eps=0.05), 24, 24),
+                         ("fp64", "mixed")),
+    "lk48_24x24_asym_periodic": (lambda: _velocity(lambda: W.smooth2d(seed=31, nx=9, ny=10, eps=0.1), 24, 24,
+                                                   V1=7.0, V2=5.0), ("fp64", "mixed")),
+    "lk48_48x48_blast": (lambda: W.blast2d(seed=32, nx=18, ny=15, eps=0.02, sigma=0.2), ("mixed",)),
+    "lk48_48x48_lid_paper_proj": (lambda: W.cavity2d(seed=33, nx=10, ny=17, nv=48, V=8.0, eps=0.05, amp=0.2,
+                                                     proj_mode="paper"), ("mixed",)),
+    "lk48_48x24_inflow": (lambda: _velocity(lambda: _inflow_box(34), 48, 24, V1=9.0, V2=6.0), ("fp64", "mixed")),
+}
+
+
+@pytest.mark.parametrize("name,precision", [(n, pr) for n in sorted(LANE_K48) for pr in LANE_K48[n][1]])
+def test_lane_k_48_lanes(name, precision):
+    """The lane-k kernel with 48 active lanes on its velocity grids, against the oracle
+    (walls go through the wall-ring kernel of the same layout)."""
+    p, Q, G = LANE_K48[name][0]()
+    p["precision"] = precision
+    parity(p, Q, G, 20, label=f"{name}_{precision}")
+
+
 def _asym_v2():
     p, Q, G = W.cavity2d(seed=27, nx=9, ny=21, nv=32, eps=0.05, amp=0.2)
     p["v2"] = (-6.0, 8.0)
