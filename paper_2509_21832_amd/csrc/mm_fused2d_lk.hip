@@ -52,12 +52,20 @@ struct PassLK {
 #define MM_LK_STASH 1
 #endif
     static constexpr bool STASH = MM_LK_STASH && sizeof(TC) == 8 && NPT >= 16;
+#ifndef MM_LK_WPROJ
+#define MM_LK_WPROJ 1
+#endif
+#ifndef MM_LK_ESFOLD
+#define MM_LK_ESFOLD 1
+#endif
     TC *st;                 // this wavefront's slice: [NPT][64]
     int lane, i, k, l0, L;
     double act;             // 1 on an active lane, 0 on an idle one
     int row_bytes;          // bytes of one row of cells of g
     int off_c, off_u;       // byte offsets in its row of this lane's value of cell i and of its upwind cell
     double v1d, v2bd, hd;   // v1 of this lane; v2 of node m: v2b + m h
+    double cxd;             // |v1| / dx
+    int pe_src;             // 4 x the record field that holds this lane's entry of the composite map
     TC v1, cx, v2b, h, idy;
 
     // The node loops step v2 along the lane, w <- w + h from v2b: one add per
@@ -78,6 +86,23 @@ struct PassLK {
         s[1] = v1d * S[0];
         s[2] = c * S[0] + hd * S[1];
         s[3] = (v1d * v1d + c * c) * S[0] + (2.0 * c * hd) * S[1] + (hd * hd) * S[2];
+    }
+
+    // raw moments s (per lane) -> projection coefficients o (wave-uniform): the
+    // wavefront sum and the record's composite map, applied across lanes
+    // (wave_proj4).  Each lane takes its entry of the map from the record's lanes
+    // by a permute (FP64: record held one field per lane) or by a load of its own
+    // (FP32: record in memory).  MM_LK_WPROJ=0 builds the lane-by-lane product.
+    __device__ __forceinline__ void sum_proj(double (&s)[4], const Rec &R, double (&o)[4]) const
+    {
+        if constexpr (std::is_same<Rec, RecV>::value && MM_LK_WPROJ) {
+            wave_proj4(s, lane_read(R.v, pe_src), o);
+        } else if constexpr (MM_LK_WPROJ == 1) {
+            wave_proj4(s, R.p[pe_src >> 2], o);
+        } else {
+            wave_sum<4>(s, lane);
+            proj_raw(R, s, o);
+        }
     }
 
     // A Gaussian of the cell along this lane's nodes, e(m) = exp(quadratic in m),
@@ -171,15 +196,14 @@ struct PassLK {
             S[1] += tn(m) * dd;
             S[2] += (tn(m) * tn(m)) * dd;
         }
-        const double cxd = fabs(v1d) / P->dx;      // sums of Z = cx d
+        // sums of Z = cx d
         S[0] *= cxd;
         S[1] *= cxd;
         S[2] *= cxd;
         double s[4];
         raw4(S, s);
-        wave_sum<4>(s, lane);
         double o[4];
-        proj_raw(R, s, o);
+        sum_proj(s, R, o);
         const double dtd = P->dt;
         const TC c2 = (TC)(dtd * o[2]), c3 = (TC)(dtd * o[3]), K = (TC)(dtd * (o[0] + (o[1] + o[3] * v1d) * v1d));
         const Gq m0 = maxw_q(R);
@@ -208,19 +232,20 @@ struct PassLK {
     }
 
     // y-transport of node m: v2 (G(j) - G(j -/+ 1)) / dy upwind, written as
-    // |v2| / dy (G(j) - G(upwind)) (the same value)
-    __device__ __forceinline__ TC zy(int m, TC w, const TC (&lo)[NPT], const TC (&ce)[NPT], const TC (&hi)[NPT]) const
+    // |v2| / dy (G(j) - G(upwind)) (the same value); wy = v2 / dy of the node,
+    // stepped along the lane (wy <- wy + h / dy) by the node loops
+    __device__ __forceinline__ TC zy(int m, TC wy, const TC (&lo)[NPT], const TC (&ce)[NPT], const TC (&hi)[NPT]) const
     {
         if constexpr (SYM) {
             const TC up = m < NPT / 2 ? hi[m] : lo[m];
-            const TC aw = m < NPT / 2 ? -w : w;
+            const TC aw = m < NPT / 2 ? -wy : wy;
             TC d = ce[m] - up;
             // FP64: pin the difference where it is used; left free, the compiler
             // forms the row's differences early and needs more than 256 VGPRs
             if constexpr (sizeof(TC) == 8) asm volatile("" : "+v"(d));
-            return (aw * idy) * d;
+            return aw * d;
         } else {
-            return (fabs(w) * idy) * (ce[m] - (w < (TC)0 ? hi[m] : lo[m]));
+            return fabs(wy) * (ce[m] - (wy < (TC)0 ? hi[m] : lo[m]));
         }
     }
 
@@ -231,10 +256,11 @@ struct PassLK {
     {
         TC Zy[NPT];
         double S[3] = {0.0, 0.0, 0.0};
-        TC wz = v2b;
+        TC wy = v2b * idy;
+        const TC hy = h * idy;
 #pragma unroll
-        for (int m = 0; m < NPT; ++m, wz += h) {
-            Zy[m] = zy(m, wz, lo, ce, hi);
+        for (int m = 0; m < NPT; ++m, wy += hy) {
+            Zy[m] = zy(m, wy, lo, ce, hi);
             const double z = (double)Zy[m];
             S[0] += z;
             S[1] += tn(m) * z;
@@ -242,9 +268,8 @@ struct PassLK {
         }
         double s[4];
         raw4(S, s);
-        wave_sum<4>(s, lane);
         double o[4];
-        proj_raw(R, s, o);
+        sum_proj(s, R, o);
         const TC c2 = (TC)o[2], c3 = (TC)o[3], Kz = (TC)(o[0] + (o[1] + o[3] * v1d) * v1d), dt = (TC)P->dt;
         const auto ws = row(Gn, jr);
         Gq mq = MQ_RING ? Gq{ms.e, ms.r, R[R_KM]} : maxw_q(R);
@@ -294,16 +319,24 @@ struct PassLK {
         const TC rbp = discrete ? (TC)rbd : (TC)0, rbq = discrete ? (TC)0 : (TC)rbd;
         TC part[STASH ? 1 : NPT];
         double S[3] = {0.0, 0.0, 0.0};
+        // FP64: the ES term's -M / eps joins the cubic's constant, so the node value
+        // is M (cubic - 1/eps) + calG / eps (rounding of the same order as forming
+        // calG - M first); FP32 forms calG - M in FP64 before the conversion
+        constexpr bool ESFOLD = sizeof(TC) == 8 && MM_LK_ESFOLD;
+        if constexpr (ESFOLD) C[0] -= (TC)iepsd;
         {
             Gq mq = mq0;
-            TC w = v2b;
+            TC w2 = v2b - u2, wy = v2b * idy;
+            const TC hy = h * idy;
 #pragma unroll
-            for (int m = 0; m < NPT; ++m, w += h) {
-                const TC w2 = w - u2;
-                const TC zv = zy(m, w, lo, ce, hi);
+            for (int m = 0; m < NPT; ++m, w2 += h, wy += hy) {
+                const TC zv = zy(m, wy, lo, ce, hi);
                 const double Md = mq.next();
-                const TC M = (TC)Md, es = (TC)((gq.next() - Md) * iepsd);
-                const TC bv = M * (((C[3] * w2 + C[2]) * w2 + C[1]) * w2 + C[0]) + es;
+                const TC M = (TC)Md;
+                const TC cub = ((C[3] * w2 + C[2]) * w2 + C[1]) * w2 + C[0];
+                TC bv;
+                if constexpr (ESFOLD) bv = M * cub + (TC)iepsd * (TC)gq.next();
+                else bv = M * cub + (TC)((gq.next() - Md) * iepsd);
                 const TC d = radt * zv - rbp * bv;
                 const TC pv = ra * ce[m] + (rbq * bv - d);
                 if constexpr (STASH) st[m * 64 + lane] = pv;
@@ -321,9 +354,8 @@ struct PassLK {
         }
         double s[4];
         raw4(S, s);
-        wave_sum<4>(s, lane);
         double o[4];
-        proj_raw(R, s, o);
+        sum_proj(s, R, o);
         const TC q3 = (TC)o[3], q2 = (TC)o[2], q0 = (TC)(o[0] + (o[1] + o[3] * v1d) * v1d);
         const auto ws = row(Gn, jr);
         // recompute the node values below rather than hold all NPT of them from the first loop
@@ -499,7 +531,15 @@ __global__ __launch_bounds__(64 * WPG, (LKTraits<TC, NPT>::occupancy)) void k_fu
     ps.v2bd = P.v2_lo + (ps.l0 + 0.5) * P.dv2;
     ps.hd = ps.L * P.dv2;
     ps.v1 = (TC)ps.v1d;
-    ps.cx = (TC)(fabs(ps.v1d) / P.dx);
+    ps.cxd = fabs(ps.v1d) / P.dx;
+    {
+        // lane 16 r + c (c < 4) takes entry (c, r) of the record's composite map; the
+        // other lanes take field R_PM + 10, which the preparation kernel sets to 0
+        static_assert(R_PM + 10 < REC, "a zero field follows the composite map");
+        const int r = ps.lane >> 4, c = ps.lane & 15;
+        ps.pe_src = 4 * (c < 4 ? R_PM + sym4(c, r) : R_PM + 10);
+    }
+    ps.cx = (TC)ps.cxd;
     {
         const bool pos = ps.v1d > 0.0;
         const int side = pos ? 0 : 1;

@@ -106,6 +106,34 @@ __device__ __forceinline__ void wave_sum(double (&v)[N], int lane)
     }
 }
 
+// Wavefront sum of four per-lane values s followed by the symmetric 4x4 map
+// o = Pm s, with the map applied across lanes instead of by every lane: after the
+// folds of wave_sum<4>, row r of the wavefront holds the total s_r in all its
+// lanes; lane 16 r + c multiplies it by its entry pe = Pm[c][r] (c < 4; pe = 0 on
+// the other lanes), a fold over the four rows sums the products, and lane c then
+// holds o_c, read out as a scalar.  (A lane-by-lane product would read the ten
+// entries and the four totals as scalars and issue 16 FMAs with two scalar
+// operands each.)  The combination order is fixed.
+__device__ __forceinline__ void wave_proj4(const double (&s)[4], double pe, double (&o)[4])
+{
+    const double a0 = fold_swap<5>(s[0], s[2]);
+    const double a1 = fold_swap<5>(s[1], s[3]);
+    double x = row_sum(fold_swap<4>(a0, a1)) * pe;
+    x = fold_swap<5>(x, x);
+    x = fold_swap<4>(x, x);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) o[c] = bcast(x, c);
+}
+
+// value of lane src_byte / 4 of v, in every lane (cross-lane permute through the
+// LDS unit; no LDS memory)
+__device__ __forceinline__ double lane_read(double v, int src_byte)
+{
+    const int lo = __builtin_amdgcn_ds_bpermute(src_byte, __double2loint(v));
+    const int hi = __builtin_amdgcn_ds_bpermute(src_byte, __double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+
 __device__ __forceinline__ float t_exp(float x) { return expf(x); }
 __device__ __forceinline__ double t_exp(double x) { return exp(x); }
 __device__ __forceinline__ float t_expm1(float x) { return expm1f(x); }
