@@ -68,10 +68,10 @@ __device__ __forceinline__ double trbdf2_W(double eps, double tau, double nu, do
 // collision half step on the pressure tensor of one cell (macro2d-split1/4)
 __device__ __forceinline__ void collide(const Params &P, double q[6])
 {
-    const double rho = q[0], u1 = q[1] / rho, u2 = q[2] / rho;
+    const double rho = q[0], ir = 1.0 / rho, u1 = q[1] * ir, u2 = q[2] * ir;
     const double P11 = q[3] - q[1] * u1, P12 = q[4] - q[1] * u2, P22 = q[5] - q[2] * u2;
     const double p = 0.5 * (P11 + P22);
-    const double W = trbdf2_W(P.eps, tau_of(P, rho, p, p / rho), P.nu, P.dt);
+    const double W = trbdf2_W(P.eps, tau_of(P, rho, p, p * ir), P.nu, P.dt);
     const double n11 = 0.5 * ((1.0 + W) * P11 + (1.0 - W) * P22);
     const double n12 = 0.5 * (2.0 * W * P12);
     const double n22 = 0.5 * ((1.0 - W) * P11 + (1.0 + W) * P22);
@@ -85,16 +85,18 @@ __device__ __forceinline__ void collide(const Params &P, double q[6])
 // F = 1/2 (sgn a J + (1 + sgn b) K) with a, b, J, K of (flux-2D-1/2).
 __device__ __forceinline__ void kfvs_half(const double q[6], int d, double sgn, double F[6])
 {
-    const double rho = q[0], u1 = q[1] / rho, u2 = q[2] / rho;
+    // one reciprocal each of rho and of the normal pressure instead of a division per use
+    const double rho = q[0], ir = 1.0 / rho, u1 = q[1] * ir, u2 = q[2] * ir;
     const double P11 = q[3] - q[1] * u1, P12 = q[4] - q[1] * u2, P22 = q[5] - q[2] * u2;
     double a, b, J[6], K[6];
     if (d == 0) {
-        a = sqrt(2.0 * P11 / (MM_PI * rho)) * exp(-rho * u1 * u1 / (2.0 * P11));
-        b = erf(u1 * sqrt(rho / (2.0 * P11)));
+        const double iP = 1.0 / P11;
+        a = sqrt((2.0 / MM_PI) * P11 * ir) * exp(-0.5 * rho * u1 * u1 * iP);
+        b = erf(u1 * sqrt(0.5 * rho * iP));
         J[0] = rho; J[1] = rho * u1; J[2] = rho * u2;
         J[3] = rho * u1 * u1 + 2.0 * P11;
         J[4] = rho * u1 * u2 + 2.0 * P12;
-        J[5] = rho * u2 * u2 + P22 + P12 * P12 / P11;
+        J[5] = rho * u2 * u2 + P22 + P12 * P12 * iP;
         K[0] = rho * u1;
         K[1] = rho * u1 * u1 + P11;
         K[2] = rho * u1 * u2 + P12;
@@ -102,10 +104,11 @@ __device__ __forceinline__ void kfvs_half(const double q[6], int d, double sgn, 
         K[4] = rho * u1 * u1 * u2 + u2 * P11 + 2.0 * u1 * P12;
         K[5] = rho * u1 * u2 * u2 + u1 * P22 + 2.0 * u2 * P12;
     } else {
-        a = sqrt(2.0 * P22 / (MM_PI * rho)) * exp(-rho * u2 * u2 / (2.0 * P22));
-        b = erf(u2 * sqrt(rho / (2.0 * P22)));
+        const double iP = 1.0 / P22;
+        a = sqrt((2.0 / MM_PI) * P22 * ir) * exp(-0.5 * rho * u2 * u2 * iP);
+        b = erf(u2 * sqrt(0.5 * rho * iP));
         J[0] = rho; J[1] = rho * u1; J[2] = rho * u2;
-        J[3] = rho * u1 * u1 + P11 + P12 * P12 / P22;
+        J[3] = rho * u1 * u1 + P11 + P12 * P12 * iP;
         J[4] = rho * u1 * u2 + 2.0 * P12;
         J[5] = rho * u2 * u2 + 2.0 * P22;
         K[0] = rho * u2;

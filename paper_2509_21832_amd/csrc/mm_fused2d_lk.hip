@@ -148,7 +148,12 @@ struct PassLK {
     __device__ __forceinline__ __amdgpu_buffer_rsrc_t row(const TS *base, int r) const
     {
         r = __builtin_amdgcn_readfirstlane(r);
-        return buf_rsrc(base + (size_t)r * P->nx * (ACT * NPT), row_bytes);
+        // the address and extent are stated wave-uniform as well (where the compiler
+        // merges paths it can lose track of that)
+        const uint64_t a = (uint64_t)(base + (size_t)r * P->nx * (ACT * NPT));
+        const uint64_t au = (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)a) |
+                            ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(a >> 32)) << 32);
+        return buf_rsrc((const TS *)au, __builtin_amdgcn_readfirstlane(row_bytes));
     }
     static constexpr int NB = ACT * (int)sizeof(TS);   // byte stride of node m
 

@@ -49,15 +49,21 @@ __device__ __forceinline__ bool wall_cell(const Params &P, int i, int j)
            (j == 0 && is_open(P.bc[2].kind)) || (j == P.ny - 1 && is_open(P.bc[3].kind));
 }
 
-// inverse of a symmetric positive definite 4x4 matrix (Cholesky); out packed by sym4
+// inverse of a symmetric positive definite 4x4 matrix (Cholesky); out packed by
+// sym4.  The four diagonal factors are inverted once and the solves multiply.
 __device__ __forceinline__ void spd_inverse4(const double A[4][4], double scale, double *out)
 {
-    double L[4][4] = {};
+    double L[4][4] = {}, iL[4];
     for (int r = 0; r < 4; ++r) {
         for (int s = 0; s <= r; ++s) {
             double v = A[r][s];
             for (int t = 0; t < s; ++t) v -= L[r][t] * L[s][t];
-            L[r][s] = (r == s) ? sqrt(v) : v / L[s][s];
+            if (r == s) {
+                L[r][r] = sqrt(v);
+                iL[r] = 1.0 / L[r][r];
+            } else {
+                L[r][s] = v * iL[s];
+            }
         }
     }
     // inverse columns: solve L L^T x = e_c
@@ -67,12 +73,12 @@ __device__ __forceinline__ void spd_inverse4(const double A[4][4], double scale,
         for (int r = 0; r < 4; ++r) {
             double v = (r == col) ? 1.0 : 0.0;
             for (int t = 0; t < r; ++t) v -= L[r][t] * y[t];
-            y[r] = v / L[r][r];
+            y[r] = v * iL[r];
         }
         for (int r = 3; r >= 0; --r) {
             double v = y[r];
             for (int t = r + 1; t < 4; ++t) v -= L[t][r] * X[t][col];
-            X[r][col] = v / L[r][r];
+            X[r][col] = v * iL[r];
         }
     }
     for (int a = 0; a < 4; ++a)
@@ -239,6 +245,17 @@ __global__ __launch_bounds__(4 * PREP_CELLS) void k_prep2d(const double *__restr
         gauss_sums(P.v1_lo - s.u1, P.dv1, P.nv1, 1.0 / (2.0 * s.T), S1);
     }
     __syncthreads();
+    const int ncopy = (ncell - c0 < PREP_CELLS ? ncell - c0 : PREP_CELLS) * REC;
+    double *dst = rec + (size_t)c0 * REC;
+    // while wavefront 2 forms the projection matrices, the other three write out
+    // every other field of the block's records
+    if (role != 2) {
+        const int t0 = (role == 3 ? 2 : role) * PREP_CELLS + cl;
+        for (int t = t0; t < ncopy; t += 3 * PREP_CELLS) {
+            const int f = t % REC;
+            if ((f < R_P0 || f >= R_P0 + 10) && (f < R_PM || f >= R_PM + 10)) dst[t] = s_rec[t];
+        }
+    }
     if (role == 2 && c < ncell) {
         const CellPrim s = prim_of(Q + 6 * (size_t)c);
         {
@@ -251,19 +268,19 @@ __global__ __launch_bounds__(4 * PREP_CELLS) void k_prep2d(const double *__restr
                 double S2r[5];
                 for (int q = 0; q < 5; ++q) S2r[q] = s_s2[q][cl];
                 auto mm = [&](int p, int q) { return S1[p] * S2r[q]; };
-                const double c0 = dA * s.rho / (2.0 * MM_PI * s.T);
-                const double T = s.T, rT = sqrt(T);
+                const double T = s.T, iT = 1.0 / T, irT = sqrt(iT), i2T = 0.5 * iT;
+                const double c0 = dA * s.rho * (0.5 / MM_PI) * iT;
                 double A[4][4];
                 A[0][0] = c0 * mm(0, 0);
-                A[0][1] = c0 * mm(1, 0) / rT;
-                A[0][2] = c0 * mm(0, 1) / rT;
-                A[0][3] = c0 * ((mm(2, 0) + mm(0, 2)) / (2.0 * T) - mm(0, 0));
-                A[1][1] = c0 * mm(2, 0) / T;
-                A[1][2] = c0 * mm(1, 1) / T;
-                A[1][3] = c0 * ((mm(3, 0) + mm(1, 2)) / (2.0 * T) - mm(1, 0)) / rT;
-                A[2][2] = c0 * mm(0, 2) / T;
-                A[2][3] = c0 * ((mm(2, 1) + mm(0, 3)) / (2.0 * T) - mm(0, 1)) / rT;
-                A[3][3] = c0 * ((mm(4, 0) + 2.0 * mm(2, 2) + mm(0, 4)) / (4.0 * T * T) - (mm(2, 0) + mm(0, 2)) / T + mm(0, 0));
+                A[0][1] = c0 * mm(1, 0) * irT;
+                A[0][2] = c0 * mm(0, 1) * irT;
+                A[0][3] = c0 * ((mm(2, 0) + mm(0, 2)) * i2T - mm(0, 0));
+                A[1][1] = c0 * mm(2, 0) * iT;
+                A[1][2] = c0 * mm(1, 1) * iT;
+                A[1][3] = c0 * ((mm(3, 0) + mm(1, 2)) * i2T - mm(1, 0)) * irT;
+                A[2][2] = c0 * mm(0, 2) * iT;
+                A[2][3] = c0 * ((mm(2, 1) + mm(0, 3)) * i2T - mm(0, 1)) * irT;
+                A[3][3] = c0 * ((mm(4, 0) + 2.0 * mm(2, 2) + mm(0, 4)) * (i2T * i2T) - (mm(2, 0) + mm(0, 2)) * iT + mm(0, 0));
                 for (int a = 0; a < 4; ++a)
                     for (int b = 0; b < a; ++b) A[a][b] = A[b][a];
                 spd_inverse4(A, dA, R + R_P0);
@@ -291,9 +308,12 @@ __global__ __launch_bounds__(4 * PREP_CELLS) void k_prep2d(const double *__restr
         }
     }
     __syncthreads();
-    const int ncopy = (ncell - c0 < PREP_CELLS ? ncell - c0 : PREP_CELLS) * REC;
-    double *dst = rec + (size_t)c0 * REC;
-    for (int t = threadIdx.x; t < ncopy; t += 4 * PREP_CELLS) dst[t] = s_rec[t];
+    // then the two matrices (10 packed entries each) of every cell
+    const int nmat = ncopy / REC * 20;
+    for (int t = threadIdx.x; t < nmat; t += 4 * PREP_CELLS) {
+        const int cc = t / 20, f = t % 20, q = cc * REC + (f < 10 ? R_P0 + f : R_PM + f - 10);
+        dst[q] = s_rec[q];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -587,7 +607,7 @@ __global__ __launch_bounds__(256) void k_macro2d(const double *__restrict__ Qin,
     }
     double qo[6];
     for (int m = 0; m < 6; ++m) qo[m] = qc[m] - P.dt / h * (FR[m] - FL[m]);
-    for (int a = 0; a < 3; ++a) qo[3 + a] -= P.dt * (HR[a] - HL[a]) / h;
+    for (int a = 0; a < 3; ++a) qo[3 + a] -= P.dt / h * (HR[a] - HL[a]);
     if (DIR == 1) {
         if (msrc)
             for (int m = 0; m < 6; ++m) qo[m] += P.dt * msrc[6 * (size_t)c + m];
@@ -693,7 +713,7 @@ __global__ __launch_bounds__(MACRO_THREADS) void k_macro_line(const double *__re
         }
         double qo[6];
         for (int m = 0; m < 6; ++m) qo[m] = qc[m] - P.dt / h * (FR[m] - FL[m]);
-        for (int a = 0; a < 3; ++a) qo[3 + a] -= P.dt * (HR[a] - HL[a]) / h;
+        for (int a = 0; a < 3; ++a) qo[3 + a] -= P.dt / h * (HR[a] - HL[a]);
         if (DIR == 1) {
             if (msrc)
                 for (int m = 0; m < 6; ++m) qo[m] += P.dt * msrc[6 * (size_t)c + m];
