@@ -60,10 +60,29 @@ __device__ __forceinline__ f32x16 zero16()
     return z;
 }
 
-__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+// erf without branches: erf(t) = 1 - exp(-t P(t)) for t = |x| >= 0 (odd extension), P
+// the degree-9 least-squares Chebyshev fit of -log(erfc(t)) / t on [0, 4] (fit_erf.py;
+// beyond 4 the fit is held at 4 and erf rounds to 1).  Within 4e-7 relative and 8e-8
+// absolute of erf, far below the bf16 rounding of the activations; the library erff
+// takes a divergent branch at |x| = 1 and costs about twice as many instructions.
+__device__ __forceinline__ float erf_fit(float x)
+{
+    constexpr float c[10] = {1.128379464e+00f, 6.366103888e-01f, 1.028422564e-01f, -1.933863945e-02f,
+                             1.000994671e-04f, 1.479538158e-03f, -5.703387433e-04f, 1.147649891e-04f,
+                             -1.261705529e-05f, 5.963064496e-07f};
+    const float t = fabsf(x), tc = fminf(t, 4.0f);
+    float p = c[9];
+#pragma unroll
+    for (int k = 8; k >= 0; --k) p = fmaf(p, tc, c[k]);
+    const float e = __builtin_amdgcn_exp2f(-1.44269504088896341f * t * p);
+    return copysignf(1.0f - e, x);
+}
+
+__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erf_fit(z * 0.70710678118654752f)); }
 __device__ __forceinline__ float gelu_d(float z)
 {
-    return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * expf(-0.5f * z * z) * 0.39894228040143268f;
+    return 0.5f * (1.0f + erf_fit(z * 0.70710678118654752f)) +
+           z * __builtin_amdgcn_exp2f(-0.72134752044448170f * z * z) * 0.39894228040143268f;
 }
 
 // Weights of the network in LDS (bf16): W1 [64][32] (inputs 21..31 zero),
@@ -238,15 +257,17 @@ __device__ __forceinline__ void mlp_eval(const MlpRegs &R, const float *b1, cons
 __global__ __launch_bounds__(256) void k_mlp_forward(const float *__restrict__ X, int n, MlpDev w,
                                                      float *__restrict__ Y, int accumulate, float scale)
 {
-    __shared__ float sb[NH + NH + 16 + NNORM];
+    __shared__ float sb[NH + NH + 16 + NNORM + NF];
     for (int t = threadIdx.x; t < NH; t += blockDim.x) {
         sb[t] = w.b1[t];
         sb[NH + t] = w.b2[t];
     }
     for (int t = threadIdx.x; t < 16; t += blockDim.x) sb[2 * NH + t] = t < NO ? w.b3[t] : 0.0f;
     for (int t = threadIdx.x; t < NNORM; t += blockDim.x) sb[2 * NH + 16 + t] = w.norm[t];
+    // reciprocals of the input scales, once per workgroup (the inputs are then multiplied)
+    for (int t = threadIdx.x; t < NF; t += blockDim.x) sb[2 * NH + 16 + NNORM + t] = 1.0f / w.norm[NF + t];
     __syncthreads();
-    const float *b1 = sb, *b2 = sb + NH, *b3 = sb + 2 * NH, *nrm = sb + 2 * NH + 16;
+    const float *b1 = sb, *b2 = sb + NH, *b3 = sb + 2 * NH, *nrm = sb + 2 * NH + 16, *isd = nrm + NNORM;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     MlpRegs R;
     mlp_regs(w.Wp, lane, R);
@@ -255,7 +276,7 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const float *__restrict__ X
         const int s = tile * 32 + (lane & 31);
         float x[NF];
 #pragma unroll
-        for (int f = 0; f < NF; ++f) x[f] = s < n ? (X[(size_t)s * NF + f] - nrm[f]) / nrm[NF + f] : 0.0f;
+        for (int f = 0; f < NF; ++f) x[f] = s < n ? (X[(size_t)s * NF + f] - nrm[f]) * isd[f] : 0.0f;
         float yh[4];
         mlp_eval(R, b1, b2, b3, x, lane, yh);
         if (s < n) {
@@ -528,9 +549,9 @@ __global__ __launch_bounds__(256) void k_mlp_norm(const float *__restrict__ X, c
 
 __device__ __forceinline__ void prim(const double *q, double *w)
 {
-    const double rho = q[0], u1 = q[1] / rho, u2 = q[2] / rho;
+    const double rho = q[0], ir = 1.0 / rho, u1 = q[1] * ir, u2 = q[2] * ir;
     const double P11 = q[3] - rho * u1 * u1, P12 = q[4] - rho * u1 * u2, P22 = q[5] - rho * u2 * u2;
-    w[0] = rho; w[1] = u1; w[2] = u2; w[3] = 0.5 * (P11 + P22) / rho;
+    w[0] = rho; w[1] = u1; w[2] = u2; w[3] = 0.5 * (P11 + P22) * ir;
     w[4] = P11; w[5] = P12; w[6] = P22;
 }
 
@@ -554,16 +575,18 @@ __device__ __forceinline__ void cell_features(const double *__restrict__ Q, cons
     prim(Q + 6 * (size_t)(jm * P.nx + i), wym);
     prim(Q + 6 * (size_t)(jp * P.nx + i), wyp);
     double f[NF];
+    // reciprocal spacings: one division each instead of one per feature
+    const double idx = 1.0 / P.dx, idy = 1.0 / P.dy;
 #pragma unroll
     for (int a = 0; a < 7; ++a) {
         f[a] = w0[a];
-        f[7 + a] = (hm && hp) ? (wxp[a] - wxm[a]) / (2.0 * P.dx)
-                   : hp        ? (wxp[a] - w0[a]) / P.dx
-                   : hm        ? (w0[a] - wxm[a]) / P.dx
+        f[7 + a] = (hm && hp) ? (wxp[a] - wxm[a]) * (0.5 * idx)
+                   : hp        ? (wxp[a] - w0[a]) * idx
+                   : hm        ? (w0[a] - wxm[a]) * idx
                                : 0.0;
-        f[14 + a] = (vm && vp) ? (wyp[a] - wym[a]) / (2.0 * P.dy)
-                    : vp        ? (wyp[a] - w0[a]) / P.dy
-                    : vm        ? (w0[a] - wym[a]) / P.dy
+        f[14 + a] = (vm && vp) ? (wyp[a] - wym[a]) * (0.5 * idy)
+                    : vp        ? (wyp[a] - w0[a]) * idy
+                    : vm        ? (w0[a] - wym[a]) * idy
                                 : 0.0;
     }
 #pragma unroll
@@ -660,7 +683,7 @@ __global__ __launch_bounds__(256) void k_cells2d(const double *__restrict__ Q, P
                                                  double *__restrict__ H, unsigned long long *__restrict__ nclosure,
                                                  int *__restrict__ nrebuild)
 {
-    __shared__ float sb[NH + NH + 16 + NNORM];
+    __shared__ float sb[NH + NH + 16 + NNORM + NF];
     __shared__ int wcount[4];
     if (blockIdx.x == 0 && threadIdx.x == 0) *nrebuild = 0;     // the list of k_need2d starts empty
     const int n = P.nx * P.ny;
@@ -672,9 +695,10 @@ __global__ __launch_bounds__(256) void k_cells2d(const double *__restrict__ Q, P
         }
         for (int t = threadIdx.x; t < 16; t += blockDim.x) sb[2 * NH + t] = t < NO ? w.b3[t] : 0.0f;
         for (int t = threadIdx.x; t < NNORM; t += blockDim.x) sb[2 * NH + 16 + t] = w.norm[t];
+        for (int t = threadIdx.x; t < NF; t += blockDim.x) sb[2 * NH + 16 + NNORM + t] = 1.0f / w.norm[NF + t];
         __syncthreads();
     }
-    const float *b1 = sb, *b2 = sb + NH, *b3 = sb + 2 * NH, *nrm = sb + 2 * NH + 16;
+    const float *b1 = sb, *b2 = sb + NH, *b3 = sb + 2 * NH, *nrm = sb + 2 * NH + 16, *isd = nrm + NNORM;
     const int c = (blockIdx.x * 4 + wv) * 32 + (lane & 31);
     const bool valid = c < n;
     float f[NF];
@@ -700,7 +724,7 @@ __global__ __launch_bounds__(256) void k_cells2d(const double *__restrict__ Q, P
         mlp_regs(w.Wp, lane, R);
         float x[NF];
 #pragma unroll
-        for (int a = 0; a < NF; ++a) x[a] = (f[a] - nrm[a]) / nrm[NF + a];
+        for (int a = 0; a < NF; ++a) x[a] = (f[a] - nrm[a]) * isd[a];
         float yh[4];
         mlp_eval(R, b1, b2, b3, x, lane, yh);
         const float scale = residual == 2 ? (float)P.eps : 1.0f;
