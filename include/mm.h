@@ -250,33 +250,39 @@ int mm_device_ptrs(mm_ctx *ctx, void **q, void **g, void **h, int *g_bytes);
  * Learned closure (2D).  Not part of the paper; built on its macro system:
  * the macro update of Sec. 5.4 needs from the micro part only the heat-flux
  * tensor H (eq5-41).  In near-continuum cells a network predicts, from the
- * local macro state, the heat-flux vector q and the stress deviation S of
- * eps g, and H is taken in the isotropic form
- *   H_abc = (q_a d_bc + q_b d_ac + q_c d_ab) / 2,
+ * local macro state, the heat-flux vector q, the stress deviation S and the
+ * traceless third moments t of eps g, and H is rebuilt from q and t:
+ *   H_abc = (q_a d_bc + q_b d_ac + q_c d_ab) / 2 + (traceless part of t),
+ *   H111 = 3/2 q1 + t1/4, H112 = q2/2 + t2/4, H122 = q1/2 - t1/4,
+ *   H222 = 3/2 q2 - t2/4,
  * whose contraction (H111 + H122, H112 + H222) / 2 is the heat-flux vector h
- * of Sec. 6.3.
+ * of Sec. 6.3 and whose traceless combinations are t = (H111 - 3 H122,
+ * 3 H112 - H222); t = 0 is the isotropic (Grad) form.
  *
  * Features of a cell (21, FP32): (rho, u1, u2, T, P11, P12, P22) and their
  * centred x and y differences (one-sided next to a non-periodic side), in that
- * order.  Targets (5, FP32): (q1, q2, S11, S12, S22) / eps with
- *   q = (H111 + H122, H112 + H222) / 2,  S = eps dv sum (w w^T) g.
+ * order.  Targets (7, FP32): (q1, q2, S11, S12, S22, t1, t2) / eps with
+ *   q = (H111 + H122, H112 + H222) / 2,  S = eps dv sum (w w^T) g,
+ *   t = (H111 - 3 H122, 3 H112 - H222).
  * Local Knudsen indicator:
  *   kn = (eps sqrt(T) / tau) max(|grad rho| / rho, |grad T| / T, |grad u|_F / sqrt(T)).
  * A step of an MM_CLOSURE context solves the micro part (as MM_MIXED) in cells
  * next to a non-periodic side and where kn > kn_max; elsewhere H comes from
  * the closure.  Micro parts of closure cells that a solved cell needs (its
  * 3 x 3 neighbourhood) are rebuilt, when not current, as
- *   g = M / (2 p T) [S' : w w^T + (q . w)(|w|^2 / (2T) - 2)],  then (I - Pi) g
- * (S' the traceless part of S), which under M has exactly the moments q, S.
+ *   g = M / (2 p T) [S' : w w^T + (q . w)(|w|^2 / (2T) - 2)]
+ *       + M / (24 p T^2) [t1 (w1^3 - 3 w1 w2^2) + t2 (3 w1^2 w2 - w2^3)],
+ * then (I - Pi) g (S' the traceless part of S), which under M has exactly the
+ * moments q, S, t.
  * G of closure cells is not kept current: mm_get_g and the g-moments of
  * mm_moments are meaningful only in solved cells.
  * ===================================================================== */
 
-/* the network: 21 -> 64 -> 64 -> 5, GELU (erf form), bf16 weights and
+/* the network: 21 -> 64 -> 64 -> 7, GELU (erf form), bf16 weights and
  * activations on the matrix cores with FP32 accumulation, FP32 master weights */
 typedef struct mm_mlp mm_mlp;
-#define MM_MLP_NPARAM 5893   /* W1[64][21], b1[64], W2[64][64], b2[64], W3[5][64], b3[5] */
-#define MM_MLP_NNORM 52      /* in_mean[21], in_std[21], out_mean[5], out_std[5]         */
+#define MM_MLP_NPARAM 6023   /* W1[64][21], b1[64], W2[64][64], b2[64], W3[7][64], b3[7] */
+#define MM_MLP_NNORM 56      /* in_mean[21], in_std[21], out_mean[7], out_std[7]         */
 
 /* mm_mlp_create -- a network on `device` with Glorot-uniform weights drawn
  * from `seed` (SplitMix64), zero biases and identity normalisation; stream as
@@ -285,7 +291,7 @@ int mm_mlp_create(int device, void *stream, unsigned long long seed, mm_mlp **ou
 void mm_mlp_free(mm_mlp *net);
 
 /* mm_mlp_fit_norm -- set the normalisation to the mean and standard deviation
- * of the n rows of x_dev [n][21] and y_dev [n][5] (device FP32). */
+ * of the n rows of x_dev [n][21] and y_dev [n][7] (device FP32). */
 int mm_mlp_fit_norm(mm_mlp *net, const float *x_dev, const float *y_dev, int n);
 
 /* mm_mlp_get / mm_mlp_set -- FP32 parameters [MM_MLP_NPARAM] and normalisation
@@ -294,12 +300,12 @@ int mm_mlp_fit_norm(mm_mlp *net, const float *x_dev, const float *y_dev, int n);
 int mm_mlp_get(mm_mlp *net, float *params, float *norm);
 int mm_mlp_set(mm_mlp *net, const float *params, const float *norm);
 
-/* mm_mlp_forward -- raw outputs y_dev [n][5] of raw features x_dev [n][21]:
+/* mm_mlp_forward -- raw outputs y_dev [n][7] of raw features x_dev [n][21]:
  * y = MLP((x - in_mean) / in_std) * out_std + out_mean (device FP32). */
 int mm_mlp_forward(mm_mlp *net, const float *x_dev, int n, float *y_dev);
 
 /* mm_mlp_grad -- gradient (host FP32 [MM_MLP_NPARAM], parameter order above)
- * and value (host) of L = mean over the n samples and 5 outputs of
+ * and value (host) of L = mean over the n samples and 7 outputs of
  * (MLP(xn) - (y - out_mean) / out_std)^2; no parameter changes. */
 int mm_mlp_grad(mm_mlp *net, const float *x_dev, const float *y_dev, int n, float *grad, double *loss);
 
@@ -315,9 +321,10 @@ int mm_mlp_train(mm_mlp *net, const float *x_dev, const float *y_dev, int n, int
  *       q = -eps (2 p / tau) grad T,  S = -eps (p / tau) sigma + nu (P - p I)
  *     (sigma = grad u + grad u^T - (div u) I), the moments of the first-order
  *     micro part G-hat (eqn5-97);
- *   net, residual = 0: (q, S) / eps = the network's outputs;
- *   net, residual = 1: (q, S) / eps = the NSF values plus the network's outputs;
- *   net, residual = 2: (q, S) / eps = the NSF values plus eps times the
+ *     and t = 0 (G-hat's third moments are of the isotropic form);
+ *   net, residual = 0: (q, S, t) / eps = the network's outputs;
+ *   net, residual = 1: (q, S, t) / eps = the NSF values plus the network's outputs;
+ *   net, residual = 2: (q, S, t) / eps = the NSF values plus eps times the
  *     network's outputs (networks trained on snapshots of the same residual
  *     kind, see mm_closure_snapshot).
  * The network is kept by pointer: it must outlive its use and not be trained
@@ -334,7 +341,7 @@ int mm_closure_cells(mm_ctx *ctx, long long *n_closure, unsigned char *cls_host)
  * MM_MIXED context): the features of the current state, one step, the targets
  * of the new micro part (residual = 1: minus the NSF values of the cell).
  * Rows of cells with kn <= kn_max that are not next to a non-periodic side are
- * appended in cell order to x_dev [capacity][21] and y_dev [capacity][5]
+ * appended in cell order to x_dev [capacity][21] and y_dev [capacity][7]
  * (device FP32) from row *count on; *count is updated (at most capacity rows
  * are written). */
 int mm_closure_snapshot(mm_ctx *ctx, double kn_max, int residual, float *x_dev, float *y_dev, int capacity,
@@ -346,8 +353,8 @@ int mm_closure_snapshot(mm_ctx *ctx, double kn_max, int residual, float *x_dev, 
 int mm_closure_features(mm_ctx *ctx, float *feat_host, float *kn_host, unsigned char *edge_host);
 
 /* mm_closure_rebuild -- replace the current G of the cells with mask[c] != 0
- * (host [ny][nx]) by the micro part rebuilt from out_host [ny][nx][5] =
- * (q1, q2, S11, S12, S22) / eps of each cell, as a closure step does. */
+ * (host [ny][nx]) by the micro part rebuilt from out_host [ny][nx][7] =
+ * (q1, q2, S11, S12, S22, t1, t2) / eps of each cell, as a closure step does. */
 int mm_closure_rebuild(mm_ctx *ctx, const float *out_host, const unsigned char *mask);
 
 /* =====================================================================

@@ -98,10 +98,10 @@ def lib():
         L.o_gelu_d.restype = C.c_double
         L.o_bf16.argtypes = [C.c_double]
         L.o_bf16.restype = C.c_double
-        L.o_closure_H.argtypes = [dp, dp]
+        L.o_closure_H.argtypes = [dp, dp, dp]
         L.o_closure_H.restype = None
-        L.o_closure_grec.argtypes = [cp, dp, dp, dp, dp]
-        L.o_nsf_closure.argtypes = [cp, dp, dp, dp]
+        L.o_closure_grec.argtypes = [cp, dp, dp, dp, dp, dp]
+        L.o_nsf_closure.argtypes = [cp, dp, dp, dp, dp]
         L.o_nsf_closure.restype = None
         _lib = L
     return _lib
@@ -291,7 +291,7 @@ def wall_R(u, Taa, T_wall, sign):
 
 # ---------------------------------------------------------------- closure form
 
-N_FEAT, N_HID, N_OUT = 21, 64, 5
+N_FEAT, N_HID, N_OUT = 21, 64, 7
 
 
 def mlp_nparam():
@@ -316,8 +316,9 @@ def _norm(norm):
 
 
 def mlp_forward(params, norm, X, bf16=False):
-    """Raw outputs [n, 5] of the closure network for raw features X [n, 21];
-    norm: dict of in_mean, in_std (21), out_mean, out_std (5)."""
+    """Raw outputs [n, 7] of the closure network for raw features X [n, 21]:
+    (q1, q2, S11, S12, S22, t1, t2) / eps; norm: dict of in_mean, in_std (21),
+    out_mean, out_std (7)."""
     X = _f64(X).reshape(-1, N_FEAT)
     Y = np.zeros((X.shape[0], N_OUT))
     lib().o_mlp_forward(_dp(_f64(params)), _dp(_norm(norm)), _dp(X), X.shape[0], int(bf16), _dp(Y))
@@ -347,22 +348,27 @@ def bf16(x):
     return lib().o_bf16(float(x))
 
 
-def closure_H(q):
+def closure_H(q, t=None):
+    """(H111, H112, H122, H222) from the heat flux q and the traceless part t
+    (t = 0: the isotropic form)."""
     H = np.zeros(4)
-    lib().o_closure_H(_dp(_f64(q)), _dp(H))
+    lib().o_closure_H(_dp(_f64(q)), None if t is None else _dp(_f64(t)), _dp(H))
     return H
 
 
-def closure_grec(p, q, qt, St):
+def closure_grec(p, q, qt, St, tt=None):
     g = np.zeros(p["nv1"] * p["nv2"])
-    rc = lib().o_closure_grec(C.byref(cfg(p)), _dp(_f64(q)), _dp(_f64(qt)), _dp(_f64(St)), _dp(g))
+    rc = lib().o_closure_grec(C.byref(cfg(p)), _dp(_f64(q)), _dp(_f64(qt)), _dp(_f64(St)),
+                              None if tt is None else _dp(_f64(tt)), _dp(g))
     if rc:
         raise ValueError(rc)
     return g
 
 
 def nsf_closure(p, f):
+    """Navier-Stokes-Fourier (qt, St, tt) of one cell from its features."""
     qt = np.zeros(2)
     St = np.zeros(3)
-    lib().o_nsf_closure(C.byref(cfg(p)), _dp(_f64(f)), _dp(qt), _dp(St))
-    return qt, St
+    tt = np.zeros(2)
+    lib().o_nsf_closure(C.byref(cfg(p)), _dp(_f64(f)), _dp(qt), _dp(St), _dp(tt))
+    return qt, St, tt

@@ -6,13 +6,16 @@
  *     of the macro vector of Sec. 5.1 and its centred x / y differences;
  *   - the local Knudsen indicator that decides where the closure may replace
  *     the micro solve;
- *   - a 21 -> 64 -> 64 -> 5 perceptron with exact (erf) GELU, its loss and its
+ *   - a 21 -> 64 -> 64 -> 7 perceptron with exact (erf) GELU, its loss and its
  *     gradient by reverse accumulation;
- *   - the heat-flux tensor H of the closed macro system (eq5-41) rebuilt from a
- *     heat-flux vector q in the isotropic (Grad) form, whose contraction
- *     h = (H111 + H122, H112 + H222) / 2 of Sec. 6.3 returns q;
- *   - the micro part rebuilt from (q, S) with the Hermite form that has exactly
- *     these moments under the Maxwellian, projected with the discrete projector;
+ *   - the heat-flux tensor H of the closed macro system (eq5-41), four third
+ *     moments in 2D, rebuilt from its two contractions (the heat-flux vector q,
+ *     h = (H111 + H122, H112 + H222) / 2 of Sec. 6.3) and its two traceless
+ *     combinations t = (H111 - 3 H122, 3 H112 - H222), zero in the isotropic
+ *     (Grad) form;
+ *   - the micro part rebuilt from (q, S, t) with the Hermite form that has
+ *     exactly these moments under the Maxwellian, projected with the discrete
+ *     projector;
  *   - the Navier-Stokes-Fourier values of (q, S) from the Chapman-Enskog
  *     expansion (eqn:NSF-sigma-q and the ES-BGK transport coefficients of
  *     Sec. 2.2), the closure the network is measured against.
@@ -52,7 +55,7 @@ int o_project2d(const void *cfg, const double *q, const double *F, double *PF);
 
 #define NF 21
 #define NH 64
-#define NO 5
+#define NO 7   /* (q1, q2, S11, S12, S22, t1, t2) / eps */
 #define NPARAM (NH * NF + NH + NH * NH + NH + NO * NH + NO)
 
 int o_mlp_nparam(void) { return NPARAM; }
@@ -157,7 +160,7 @@ double o_bf16(double x)
     return ldexp(r, e - 8);
 }
 
-/* parameter block: W1[64][21], b1[64], W2[64][64], b2[64], W3[5][64], b3[5] */
+/* parameter block: W1[64][21], b1[64], W2[64][64], b2[64], W3[7][64], b3[7] */
 typedef struct {
     const double *W1, *b1, *W2, *b2, *W3, *b3;
 } mlp_view;
@@ -170,7 +173,7 @@ static mlp_view view(const double *p)
 }
 
 /* one sample: normalised input xh[21] -> pre-activations z1, z2, activations a1,
- * a2 and the normalised output yh[5].  With bf16 != 0 every matrix-product input
+ * a2 and the normalised output yh[7].  With bf16 != 0 every matrix-product input
  * (xh, a1, a2) is rounded to bfloat16 first, as the GPU kernels feed them to the
  * matrix cores; sums and everything else stay FP64. */
 static void forward1(const mlp_view *v, const double *xh_in, int bf16, double *z1, double *a1, double *z2, double *a2,
@@ -282,15 +285,19 @@ int o_mlp_grad(const double *params, const double *norm, const double *X, const 
 
 /* ---------------------------------------------- closure moments and g */
 
-/* H (H111, H112, H122, H222) of a heat-flux vector q in the isotropic form
- * H_abc = (q_a d_bc + q_b d_ac + q_c d_ab) / 2 (2D: the contraction over b = c
- * gives (d_v + 2) / 2 q_a = 2 q_a, i.e. h = q) */
-void o_closure_H(const double *q, double *H)
+/* H (H111, H112, H122, H222) from its contractions q (the heat-flux vector,
+ * q_a = (H_a11 + H_a22) / 2) and its traceless part t = (H111 - 3 H122,
+ * 3 H112 - H222): the isotropic form H_abc = (q_a d_bc + q_b d_ac + q_c d_ab) / 2
+ * (2D: the contraction over b = c gives (d_v + 2) / 2 q_a = 2 q_a, i.e. h = q)
+ * has t = 0, and t adds (t1 / 4)(1, 0, -1, 0) + (t2 / 4)(0, 1, 0, -1), which has
+ * zero contractions.  t may be NULL (t = 0). */
+void o_closure_H(const double *q, const double *t, double *H)
 {
-    H[0] = 1.5 * q[0];
-    H[1] = 0.5 * q[1];
-    H[2] = 0.5 * q[0];
-    H[3] = 1.5 * q[1];
+    const double t1 = t ? t[0] : 0.0, t2 = t ? t[1] : 0.0;
+    H[0] = 1.5 * q[0] + 0.25 * t1;
+    H[1] = 0.5 * q[1] + 0.25 * t2;
+    H[2] = 0.5 * q[0] - 0.25 * t1;
+    H[3] = 1.5 * q[1] - 0.25 * t2;
 }
 
 /*
@@ -298,12 +305,18 @@ void o_closure_H(const double *q, double *H)
  * St = (S11, S12, S22) / eps with S the stress deviation eps dv sum (w w^T) g.
  * With p = rho T and the traceless part S' of St,
  *   g = M / (2 p T) [ S' : (w w^T) + (qt . w) (|w|^2 / (2T) - 2) ]
+ *       + M / (24 p T^2) [ tt1 (w1^3 - 3 w1 w2^2) + tt2 (3 w1^2 w2 - w2^3) ]
  * has, under the Maxwellian M of the cell, zero (1, v, |v|^2) moments, stress
- * deviation eps S' and heat flux eps qt; on the velocity grid it is then
- * projected with the discrete projector, so its discrete conserved moments
- * vanish to round-off.  q is the cell's conserved state (6).
+ * deviation eps S', heat flux eps qt and traceless third moments eps tt (the
+ * cubic harmonics have zero moments of order below three and zero contractions;
+ * under M, int (w1^3 - 3 w1 w2^2) w1^3 M = 6 rho T^3 and
+ * int (w1^3 - 3 w1 w2^2) w1 w2^2 M = -6 rho T^3, so tt1 = 24 rho T^3 / (24 p T^2) tt1);
+ * on the velocity grid it is then projected with the discrete projector, so its
+ * discrete conserved moments vanish to round-off.  q is the cell's conserved
+ * state (6); tt may be NULL (tt = 0).
  */
-int o_closure_grec(const void *cfgp, const double *q, const double *qt, const double *St, double *g)
+int o_closure_grec(const void *cfgp, const double *q, const double *qt, const double *St, const double *tt,
+                   double *g)
 {
     const c_cfg *c = (const c_cfg *)cfgp;
     const int nv1 = c->nv1, nv2 = c->nv2;
@@ -322,7 +335,10 @@ int o_closure_grec(const void *cfgp, const double *q, const double *qt, const do
             const double M = rho / (2.0 * 3.14159265358979323846 * T) * exp(-ww / (2.0 * T));
             const double herm = a11 * w1 * w1 + 2.0 * a12 * w1 * w2 + a22 * w2 * w2 +
                                 (qt[0] * w1 + qt[1] * w2) * (ww / (2.0 * T) - 2.0);
-            raw[l * nv1 + k] = M / (2.0 * p * T) * herm;
+            const double cub = tt ? tt[0] * (w1 * w1 * w1 - 3.0 * w1 * w2 * w2) +
+                                        tt[1] * (3.0 * w1 * w1 * w2 - w2 * w2 * w2)
+                                  : 0.0;
+            raw[l * nv1 + k] = M / (2.0 * p * T) * herm + M / (24.0 * p * T * T) * cub;
         }
     /* g = (I - Pi) raw with the projector of the configured mode */
     double *pr = malloc(sizeof(double) * (size_t)nv1 * nv2);
@@ -340,9 +356,11 @@ int o_closure_grec(const void *cfgp, const double *q, const double *qt, const do
  *   qt = -(2 p / tau) grad T                    (kappa = (d_v + 2) p / (2 tau))
  *   St = -(p / tau) sigma + nu (P - p I) / eps   (the stress of the first-order
  * micro part G-hat: its B : sigma term, plus the ES term (G - M) / eps)
- * with sigma = grad u + grad u^T - (div u) I.  Returns qt[2], St[3].
+ * with sigma = grad u + grad u^T - (div u) I.  Returns qt[2], St[3] and the
+ * traceless third moments tt[2], which are zero to first order (the cubic
+ * harmonics are orthogonal to the first-order micro part), if tt is not NULL.
  */
-void o_nsf_closure(const void *cfgp, const double *f, double *qt, double *St)
+void o_nsf_closure(const void *cfgp, const double *f, double *qt, double *St, double *tt)
 {
     const c_cfg *c = (const c_cfg *)cfgp;
     const double rho = f[0], T = f[3], p = rho * T, tau = tau_of(c, rho, T);
@@ -353,4 +371,5 @@ void o_nsf_closure(const void *cfgp, const double *f, double *qt, double *St)
     St[0] = -(p / tau) * s11 + c->nu * (f[4] - p) / c->eps;
     St[1] = -(p / tau) * s12 + c->nu * f[5] / c->eps;
     St[2] = (p / tau) * s11 + c->nu * (f[6] - p) / c->eps;
+    if (tt) tt[0] = tt[1] = 0.0;
 }

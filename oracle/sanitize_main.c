@@ -14,9 +14,10 @@ int o_mlp_nparam(void);
 int o_mlp_forward(const double *params, const double *norm, const double *X, int n, int bf16, double *Y);
 int o_mlp_grad(const double *params, const double *norm, const double *X, const double *Y, int n, int bf16,
                double *grad, double *loss);
-void o_closure_H(const double *q, double *H);
-int o_closure_grec(const void *cfgp, const double *q, const double *qt, const double *St, double *g);
-void o_nsf_closure(const void *cfgp, const double *f, double *qt, double *St);
+void o_closure_H(const double *q, const double *t, double *H);
+int o_closure_grec(const void *cfgp, const double *q, const double *qt, const double *St, const double *tt,
+                   double *g);
+void o_nsf_closure(const void *cfgp, const double *f, double *qt, double *St, double *tt);
 
 static int fails = 0;
 #define CHECK(x) do { if (!(x)) { fprintf(stderr, "check failed: %s (line %d)\n", #x, __LINE__); ++fails; } } while (0)
@@ -127,15 +128,15 @@ int main(void)
         state2d(&c, Q);
         CHECK(o_features2d(&c, Q, F, kn, edge) == 0);
         const int np = o_mlp_nparam();
-        double *par = calloc(np, sizeof(double)), *gr = malloc(sizeof(double) * np), norm[52], Y[5 * 20], loss;
+        double *par = calloc(np, sizeof(double)), *gr = malloc(sizeof(double) * np), norm[56], Y[7 * 20], loss;
         for (int k = 0; k < np; ++k) par[k] = 0.01 * sin(0.37 * k);
-        for (int k = 0; k < 52; ++k) norm[k] = (k >= 21 && k < 42) || k >= 47 ? 1.0 : 0.0;
+        for (int k = 0; k < 56; ++k) norm[k] = (k >= 21 && k < 42) || k >= 49 ? 1.0 : 0.0;
         CHECK(o_mlp_forward(par, norm, F, 20, 1, Y) == 0);
         CHECK(o_mlp_grad(par, norm, F, Y, 20, 0, gr, &loss) == 0);
-        double qt[2] = {0.1, -0.05}, St[3] = {0.02, 0.01, -0.02}, Hc[4], g[64];
-        o_closure_H(qt, Hc);
-        CHECK(o_closure_grec(&c, Q, qt, St, g) == 0);
-        o_nsf_closure(&c, F, qt, St);
+        double qt[2] = {0.1, -0.05}, St[3] = {0.02, 0.01, -0.02}, tt[2] = {0.03, -0.01}, Hc[4], g[64];
+        o_closure_H(qt, tt, Hc);
+        CHECK(o_closure_grec(&c, Q, qt, St, tt, g) == 0);
+        o_nsf_closure(&c, F, qt, St, tt);
         free(par); free(gr);
     }
     /* scalar helpers */

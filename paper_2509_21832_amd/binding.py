@@ -28,9 +28,9 @@ EXPORTS = ("mm_init", "mm_step", "mm_step_async", "mm_sync", "mm_moments", "mm_g
            "mm_closure_snapshot", "mm_closure_features", "mm_closure_rebuild", "mm_step2d_noalloc",
            "mm_set_source")
 
-MLP_NPARAM = 5893
-MLP_NNORM = 52
-N_FEAT, N_OUT = 21, 5
+MLP_NPARAM = 6023
+MLP_NNORM = 56
+N_FEAT, N_OUT = 21, 7
 
 
 class MMError(RuntimeError):
@@ -63,6 +63,10 @@ def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
                           "(hipcc --offload-arch=gfx950); there is no CPU fallback")
+    # torch ships its own HIP runtime: load it first, so that this library binds to
+    # the runtime that owns the device tensors it is handed (loaded the other way
+    # round, the process holds two runtimes and mm_init fails)
+    import torch  # noqa: F401
     L = C.CDLL(LIB_PATH)
     dp = C.POINTER(C.c_double)
     vp = C.c_void_p
@@ -350,7 +354,7 @@ class Solver:
         return n.value, cls
 
     def closure_snapshot(self, kn_max, X, Y, count, residual=0):
-        """Append training rows to the device tensors X [cap, 21], Y [cap, 5]; returns the new count."""
+        """Append training rows to the device tensors X [cap, 21], Y [cap, 7]; returns the new count."""
         cap = X.shape[0]
         if Y.shape[0] != cap:
             raise ValueError("X and Y capacities differ")

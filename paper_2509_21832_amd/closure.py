@@ -4,7 +4,7 @@ the library's kernels (mm_closure_snapshot, mm_mlp_fit_norm, mm_mlp_train);
 this module only chooses the runs and marshals device buffers.
 
 The network learns residual kind 2: the correction of the micro solve's
-(q, S) / eps to the Navier-Stokes-Fourier values, divided by eps (the leading
+(q, S, t) / eps to the Navier-Stokes-Fourier values, divided by eps (the leading
 correction is first order in eps, so the target is nearly eps-independent and
 the features carry no eps).
 """
@@ -27,7 +27,7 @@ def training_runs(eps_list=(1e-3, 2e-3, 5e-3, 1e-2), nx=64, nv=16, seed0=20):
 
 
 def snapshots(runs, steps=160, first=40, every=6, kn_max=KN_TRAIN, residual=RESIDUAL, cap=4_000_000):
-    """Training rows (device tensors X [n, 21], Y [n, 5]) from full micro solves with g in
+    """Training rows (device tensors X [n, 21], Y [n, 7]) from full micro solves with g in
     FP32: a snapshot every `every` steps from step `first` on (the first steps relax g from
     its zero initial value)."""
     import torch

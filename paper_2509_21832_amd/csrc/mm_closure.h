@@ -10,8 +10,9 @@ namespace closure {
 
 constexpr int NF = 21;      // features: (rho, u1, u2, T, P11, P12, P22), d/dx, d/dy
 constexpr int NH = 64;      // hidden width (two layers)
-constexpr int NO = 5;       // outputs: (q1, q2, S11, S12, S22) / eps
-constexpr int NPARAM = NH * NF + NH + NH * NH + NH + NO * NH + NO;   // 5893
+constexpr int NO = 7;       // outputs: (q1, q2, S11, S12, S22, t1, t2) / eps
+constexpr int NPARAM = NH * NF + NH + NH * NH + NH + NO * NH + NO;   // 6023
+static_assert(NO <= 8, "the output layer keeps outputs 4 g + v (g < 2, v < 4) per lane half");
 constexpr int NNORM = 2 * NF + 2 * NO;   // in_mean, in_std, out_mean, out_std
 
 // bf16 weights (W1 [64][32], W2 [64][64], W3 [32][64], zero padded, row-major:

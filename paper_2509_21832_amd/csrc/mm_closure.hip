@@ -3,14 +3,15 @@
 // The macro system of Sec. 5.1 is closed by the heat-flux tensor H of the micro
 // part (eq5-41).  In near-continuum cells the closure form replaces the micro
 // solve by a small network that predicts, from the local macro state and its
-// centred differences, the heat-flux vector q and the stress deviation S of
-// eps g (scaled by 1/eps).  H follows from q in the isotropic form
-// H_abc = (q_a d_bc + q_b d_ac + q_c d_ab) / 2, whose contraction is the
-// heat-flux vector h of Sec. 6.3.  Cells next to a non-periodic side, and cells
+// centred differences, the heat-flux vector q, the stress deviation S and the
+// traceless third moments t = (H111 - 3 H122, 3 H112 - H222) of eps g (scaled
+// by 1/eps).  H is rebuilt from its contraction q (the heat-flux vector h of
+// Sec. 6.3) and t: the isotropic form H_abc = (q_a d_bc + q_b d_ac + q_c d_ab) / 2
+// plus t's traceless part.  Cells next to a non-periodic side, and cells
 // whose local Knudsen indicator exceeds the threshold, keep the full micro
-// solve; their neighbours' micro parts are rebuilt from (q, S) when needed.
+// solve; their neighbours' micro parts are rebuilt from (q, S, t) when needed.
 //
-// The network: 21 -> 64 -> 64 -> 5, exact (erf) GELU, bf16 weights and
+// The network: 21 -> 64 -> 64 -> 7, exact (erf) GELU, bf16 weights and
 // activations on the matrix cores (v_mfma_f32_32x32x16_bf16) with FP32
 // accumulation, FP32 master weights and Adam moments.  Every matrix product of
 // the forward and backward passes runs on a 32-sample tile per wavefront, with
@@ -126,7 +127,7 @@ struct SmemBwd {
 
 // Forward pass of one tile: samples s0 .. s0+31 (rows idx[s] of X when idx is
 // given), normalised outputs yh[o] of sample (lane & 31) for o = 4 (lane >> 5) + v,
-// v < 4 (o < 5 only).  With bw, gelu'(z) is kept for the backward pass.
+// v < 4 (o < 7 only).  With bw, gelu'(z) is kept for the backward pass.
 template <bool TRAIN>
 __device__ void forward_tile(const SmemW &W, SmemFwd &F, SmemBwd *Bw, const float *__restrict__ X,
                              const int *__restrict__ idx, int s0, int n, int lane, float (&yh)[4])
@@ -176,7 +177,7 @@ __device__ void forward_tile(const SmemW &W, SmemFwd &F, SmemBwd *Bw, const floa
         }
     }
     wave_sync();
-    // layer 3: Yh^T (rows 0..4 of 32) = W3 (32 x 64, rows >= 5 zero) A2
+    // layer 3: Yh^T (rows 0..6 of 32) = W3 (32 x 64, rows >= 7 zero) A2
     f32x16 acc = zero16();
 #pragma unroll
     for (int kb = 0; kb < 4; ++kb) mma(acc, W.W3 + 16 * kb, NH, 1, F.A2 + 16 * kb * 32, 32, 1, lane);
@@ -209,7 +210,7 @@ __device__ __forceinline__ void mlp_regs(const __bf16 *__restrict__ Wp, int lane
 // Forward pass of the 32 samples of a wavefront with no LDS traffic: lane
 // (r, g) holds sample r's normalised inputs x; every layer's accumulator slots
 // are the next layer's B operand (the packed weights carry the matching
-// column order).  Returns the normalised outputs o = 4 g + v (v < 4, o < 5).
+// column order).  Returns the normalised outputs o = 4 g + v (v < 4, o < 7).
 __device__ __forceinline__ void mlp_eval(const MlpRegs &R, const float *b1, const float *b2, const float *b3,
                                          const float (&x)[NF], int lane, float (&yh)[4])
 {
@@ -295,7 +296,7 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const float *__restrict__ X
 // ------------------------------------------------------------- training
 
 // Gradient of the normalised mean-square loss over `count` samples idx[first ..
-// first + count) (mean over samples and outputs: scale = 1 / (5 count)).  Each
+// first + count) (mean over samples and outputs: scale = 1 / (7 count)).  Each
 // wavefront works on tiles tile0 + w, tile0 + w + nw, ... and writes its
 // partial gradient (parameter layout of the oracle) and loss to part[wave].
 __global__ __launch_bounds__(128) void k_mlp_grad(const float *__restrict__ X, const float *__restrict__ Yt,
@@ -318,14 +319,14 @@ __global__ __launch_bounds__(128) void k_mlp_grad(const float *__restrict__ X, c
     for (int q = 0; q < 2; ++q) gW1[q] = gW3[q] = zero16();
 #pragma unroll
     for (int q = 0; q < 4; ++q) gW2[q] = zero16();
-    float gb1 = 0.f, gb2 = 0.f, gb3 = 0.f, loss = 0.f;   // lane l: bias sums of unit l (outputs: l < 5)
+    float gb1 = 0.f, gb2 = 0.f, gb3 = 0.f, loss = 0.f;   // lane l: bias sums of unit l (outputs: l < 7)
     const float *Xt = idx ? X : X + (size_t)first * NF;   // tile rows: idx[first + s], or first + s
 
     for (int tile = gw; tile < ntile; tile += nw) {
         const int s0 = tile * 32;
         float yh[4];
         forward_tile<true>(W, Fw, &B, Xt, idx ? idx + first : nullptr, s0, count, lane, yh);
-        // output error dY (bf16), rows >= 5 zero
+        // output error dY (bf16), rows >= 7 zero
         for (int t = lane; t < 32 * 32; t += 64) B.dY[t] = (__bf16)0.0f;
         wave_sync();
         {
@@ -390,7 +391,7 @@ __global__ __launch_bounds__(128) void k_mlp_grad(const float *__restrict__ X, c
             for (int kb = 0; kb < 2; ++kb)
                 mma(gW1[mt], B.dZ1 + 32 * mt * 32 + 16 * kb, 32, 1, Fw.X + 16 * kb, 1, 32, lane);
         // bias gradients: sums over the tile's samples of the (bf16) errors;
-        // lane l owns hidden unit l and, for l < 5, output l
+        // lane l owns hidden unit l and, for l < 7, output l
         for (int jj = 0; jj < 32; ++jj) {
             gb1 += (float)B.dZ1[lane * 32 + jj];
             gb2 += (float)B.dZ2[lane * 32 + jj];
@@ -616,10 +617,10 @@ __global__ void k_features2d(const double *__restrict__ Q, Params P, float *__re
     edge[c] = e;
 }
 
-// Navier-Stokes-Fourier values of (q, S) / eps from the features of a cell:
-// q = -(2 p / tau) grad T and S = -(p / tau) sigma + nu (P - p I) / eps, the
-// moments of the first-order micro part G-hat (eqn5-97) with the ES term
-__device__ __forceinline__ void nsf5(const float *f, const Params &P, double o[NO])
+// Navier-Stokes-Fourier values of (q, S, t) / eps from the features of a cell:
+// q = -(2 p / tau) grad T, S = -(p / tau) sigma + nu (P - p I) / eps and t = 0,
+// the moments of the first-order micro part G-hat (eqn5-97) with the ES term
+__device__ __forceinline__ void nsf_out(const float *f, const Params &P, double o[NO])
 {
     const double rho = f[0], T = f[3], p = rho * T, tau = tau_of(P, rho, p, T);
     const double s11 = (double)f[8] - f[16], s12 = (double)f[15] + f[9];
@@ -628,6 +629,18 @@ __device__ __forceinline__ void nsf5(const float *f, const Params &P, double o[N
     o[2] = -(p / tau) * s11 + P.nu * (f[4] - p) / P.eps;
     o[3] = -(p / tau) * s12 + P.nu * f[5] / P.eps;
     o[4] = (p / tau) * s11 + P.nu * (f[6] - p) / P.eps;
+    o[5] = 0.0;
+    o[6] = 0.0;
+}
+
+// H (H111, H112, H122, H222) of a closure cell from q and the traceless part
+// t = (H111 - 3 H122, 3 H112 - H222): the isotropic form of q plus t's part
+__device__ __forceinline__ void closure_H(double q1, double q2, double t1, double t2, double *H)
+{
+    H[0] = 1.5 * q1 + 0.25 * t1;
+    H[1] = 0.5 * q2 + 0.25 * t2;
+    H[2] = 0.5 * q1 - 0.25 * t1;
+    H[3] = 1.5 * q2 - 0.25 * t2;
 }
 
 __global__ void k_nsf2d(const float *__restrict__ feat, int n, Params P, float *__restrict__ out)
@@ -635,13 +648,13 @@ __global__ void k_nsf2d(const float *__restrict__ feat, int n, Params P, float *
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= n) return;
     double o[NO];
-    nsf5(feat + (size_t)c * NF, P, o);
+    nsf_out(feat + (size_t)c * NF, P, o);
 #pragma unroll
     for (int k = 0; k < NO; ++k) out[(size_t)c * NO + k] = (float)o[k];
 }
 
 // Cell classes: micro (1) next to a non-periodic side or where kn > kn_max,
-// closure (0) elsewhere; closure cells get H = eps * (isotropic form of q).
+// closure (0) elsewhere; closure cells get H of eps (q, t).
 __global__ void k_classify2d(const float *__restrict__ kn, const uint8_t *__restrict__ edge,
                              const float *__restrict__ out, int n, float kn_max, double eps,
                              uint8_t *__restrict__ cls, double *__restrict__ H,
@@ -655,11 +668,8 @@ __global__ void k_classify2d(const float *__restrict__ kn, const uint8_t *__rest
         cls[c] = micro ? 1 : 0;
         closure = !micro;
         if (closure) {
-            const double q1 = eps * out[(size_t)c * NO], q2 = eps * out[(size_t)c * NO + 1];
-            H[4 * (size_t)c + 0] = 1.5 * q1;
-            H[4 * (size_t)c + 1] = 0.5 * q2;
-            H[4 * (size_t)c + 2] = 0.5 * q1;
-            H[4 * (size_t)c + 3] = 1.5 * q2;
+            const float *o = out + (size_t)c * NO;
+            closure_H(eps * o[0], eps * o[1], eps * o[5], eps * o[6], H + 4 * (size_t)c);
         }
     }
     // count of closure cells: per-wavefront ballots, one atomic per workgroup
@@ -675,7 +685,7 @@ __global__ void k_classify2d(const float *__restrict__ kn, const uint8_t *__rest
 
 // The closure part of a step for 32 cells per wavefront: features and
 // indicator (both lane halves of a cell compute them), classes, the closure
-// values out = (q, S) / eps (NSF; the network; or NSF plus scale x network)
+// values out = (q, S, t) / eps (NSF; the network; or NSF plus scale x network)
 // and H of the closure cells.  Lane half g holds outputs o = 4 g + v.
 template <bool NET>
 __global__ __launch_bounds__(256) void k_cells2d(const double *__restrict__ Q, Params P, MlpDev w, int residual,
@@ -712,7 +722,7 @@ __global__ __launch_bounds__(256) void k_cells2d(const double *__restrict__ Q, P
     double o4[4] = {0.0, 0.0, 0.0, 0.0};
     if (!NET || residual) {
         double b[NO];
-        nsf5(f, P, b);
+        nsf_out(f, P, b);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int o = 4 * g + v;
@@ -741,6 +751,8 @@ __global__ __launch_bounds__(256) void k_cells2d(const double *__restrict__ Q, P
 #pragma unroll
         for (int v = 0; v < 4; ++v) o4[v] = (double)(float)o4[v];
     }
+    // t = outputs 5, 6: slots 1, 2 of the other lane half
+    const double t1 = __shfl_xor(o4[1], 32, 64), t2 = __shfl_xor(o4[2], 32, 64);
     if (valid) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
@@ -749,13 +761,9 @@ __global__ __launch_bounds__(256) void k_cells2d(const double *__restrict__ Q, P
         }
         if (g == 0) {
             cls[c] = micro ? 1 : 0;
-            if (!micro) {
-                const double q1 = P.eps * (double)(float)o4[0], q2 = P.eps * (double)(float)o4[1];
-                H[4 * (size_t)c + 0] = 1.5 * q1;
-                H[4 * (size_t)c + 1] = 0.5 * q2;
-                H[4 * (size_t)c + 2] = 0.5 * q1;
-                H[4 * (size_t)c + 3] = 1.5 * q2;
-            }
+            if (!micro)
+                closure_H(P.eps * (double)(float)o4[0], P.eps * (double)(float)o4[1], P.eps * (double)(float)t1,
+                          P.eps * (double)(float)t2, H + 4 * (size_t)c);
         }
     }
     // closure cells of the workgroup (lane half 0 of each wavefront), one atomic
@@ -811,9 +819,11 @@ __global__ void k_need2d(const uint8_t *__restrict__ cls, const uint8_t *__restr
     }
 }
 
-// Rebuild the listed cells from their (q, S) / eps:
-//   g = M / (2 p T) [S' : w w^T + (q . w)(|w|^2 / (2T) - 2)],  then (I - Pi) g,
-// with S' the traceless part of S.  A fixed grid of wavefronts walks the list,
+// Rebuild the listed cells from their (q, S, t) / eps:
+//   g = M / (2 p T) [S' : w w^T + (q . w)(|w|^2 / (2T) - 2)]
+//       + M / (24 p T^2) [t1 (w1^3 - 3 w1 w2^2) + t2 (3 w1^2 w2 - w2^3)],
+// then (I - Pi) g, with S' the traceless part of S (the cubic harmonics have
+// zero moments below third order and third moments t, as 24 rho T^3 / (24 p T^2) = 1).  A fixed grid of wavefronts walks the list,
 // one cell per wavefront at a time.
 template <typename TS>
 __global__ __launch_bounds__(256) void k_rebuild2d(TS *__restrict__ G, const double *__restrict__ rec,
@@ -834,7 +844,13 @@ __global__ __launch_bounds__(256) void k_rebuild2d(TS *__restrict__ G, const dou
         const double q1 = o[0], q2 = o[1];
         const double tr = 0.5 * ((double)o[2] + o[4]);
         const double a11 = o[2] - tr, a12 = o[3], a22 = o[4] - tr;
-        const double pre = 1.0 / (2.0 * p * T);
+        const double pre = 1.0 / (2.0 * p * T), pre3 = pre / (12.0 * T);
+        const double c1 = pre3 * o[5], c2 = pre3 * o[6];
+        // t1 (w1^3 - 3 w1 w2^2) + t2 (3 w1^2 w2 - w2^3), scaled by pre3
+        auto cubic = [&](double w1, double w2) {
+            const double a = w1 * w1, b = w2 * w2;
+            return c1 * w1 * (a - 3.0 * b) + c2 * w2 * (3.0 * a - b);
+        };
         double s[4] = {0.0, 0.0, 0.0, 0.0};
         if (lk_lanes(P.nv1, P.nv2) == 64) {
             // lane-k layout: lane (k, l0) owns the nodes (k, l0 + L m); the Maxwellian
@@ -848,7 +864,7 @@ __global__ __launch_bounds__(256) void k_rebuild2d(TS *__restrict__ G, const dou
             const double b0 = pre * a11 * w1 * w1, b1 = pre * 2.0 * a12 * w1, b2 = pre * a22, bq = pre * q1 * w1;
             auto gval = [&](double w2, double M) {
                 const double ww = w1 * w1 + w2 * w2;
-                return M * (b0 + (b1 + b2 * w2) * w2 + (bq + pre * q2 * w2) * (ww * i2T - 2.0));
+                return M * (b0 + (b1 + b2 * w2) * w2 + (bq + pre * q2 * w2) * (ww * i2T - 2.0) + cubic(w1, w2));
             };
             double e = e0, r = r0;
             for (int m = 0; m < npt; ++m) {
@@ -884,8 +900,9 @@ __global__ __launch_bounds__(256) void k_rebuild2d(TS *__restrict__ G, const dou
             const double v1 = P.v1_lo + (k + 0.5) * P.dv1, v2 = P.v2_lo + (l + 0.5) * P.dv2;
             const double w1 = v1 - cl.u1d, w2 = v2 - cl.u2d, ww = w1 * w1 + w2 * w2;
             const double M = R[R_MPRE] * exp(-ww * R[R_I2T]);
-            const double g = M * pre * (a11 * w1 * w1 + 2.0 * a12 * w1 * w2 + a22 * w2 * w2 +
-                                        (q1 * w1 + q2 * w2) * (ww / (2.0 * T) - 2.0));
+            const double g = M * (pre * (a11 * w1 * w1 + 2.0 * a12 * w1 * w2 + a22 * w2 * w2 +
+                                         (q1 * w1 + q2 * w2) * (ww / (2.0 * T) - 2.0)) +
+                                  cubic(w1, w2));
             s[0] += g;
             s[1] += v1 * g;
             s[2] += v2 * g;
@@ -903,16 +920,18 @@ __global__ __launch_bounds__(256) void k_rebuild2d(TS *__restrict__ G, const dou
             const double v1 = P.v1_lo + (k + 0.5) * P.dv1, v2 = P.v2_lo + (l + 0.5) * P.dv2;
             const double w1 = v1 - cl.u1d, w2 = v2 - cl.u2d, ww = w1 * w1 + w2 * w2;
             const double M = R[R_MPRE] * exp(-ww * R[R_I2T]);
-            const double g = M * pre * (a11 * w1 * w1 + 2.0 * a12 * w1 * w2 + a22 * w2 * w2 +
-                                        (q1 * w1 + q2 * w2) * (ww / (2.0 * T) - 2.0));
+            const double g = M * (pre * (a11 * w1 * w1 + 2.0 * a12 * w1 * w2 + a22 * w2 * w2 +
+                                         (q1 * w1 + q2 * w2) * (ww / (2.0 * T) - 2.0)) +
+                                  cubic(w1, w2));
             const double pg = (cp[0] + cp[1] * v1 + cp[2] * v2 + cp[3] * (v1 * v1 + v2 * v2)) * M;
             gout[n] = (TS)(g - pg);
         }
     }
 }
 
-// Training targets of every cell from the micro solve: (q1, q2, S11, S12, S22) / eps
-// with q = (H111 + H122, H112 + H222) / 2 and S from the g-moments
+// Training targets of every cell from the micro solve: (q1, q2, S11, S12, S22, t1, t2) / eps
+// with q = (H111 + H122, H112 + H222) / 2, t = (H111 - 3 H122, 3 H112 - H222)
+// and S from the g-moments
 // gm = eps dv sum (w1^2 - w2^2, 2 w1 w2, |w|^2) G / 2 (entries 4..6).
 // With residual = 1 the Navier-Stokes-Fourier values of the cell are
 // subtracted; residual = 2 also divides that difference by eps.
@@ -946,10 +965,10 @@ __global__ __launch_bounds__(1024) void k_snapshot2d(const float *__restrict__ f
             for (int a = 0; a < NF; ++a) Xo[(size_t)pos * NF + a] = feat[(size_t)c * NF + a];
             const double *h = H + 4 * (size_t)c, *m = gm + 7 * (size_t)c;
             double t[NO] = {0.5 * (h[0] + h[2]) / eps, 0.5 * (h[1] + h[3]) / eps, (m[4] + m[6]) / eps, m[5] / eps,
-                            (m[6] - m[4]) / eps};
+                            (m[6] - m[4]) / eps,          (h[0] - 3.0 * h[2]) / eps, (3.0 * h[1] - h[3]) / eps};
             if (residual) {
                 double b[NO];
-                nsf5(feat + (size_t)c * NF, P, b);
+                nsf_out(feat + (size_t)c * NF, P, b);
                 const double f = residual == 2 ? 1.0 / eps : 1.0;
 #pragma unroll
                 for (int k = 0; k < NO; ++k) t[k] = (t[k] - b[k]) * f;

@@ -12,7 +12,7 @@ from gpu_common import log, rel_l1
 
 pytestmark = pytest.mark.gpu
 
-NF, NO = 21, 5
+NF, NO = 21, 7
 
 
 def _torch():
@@ -69,7 +69,7 @@ def _net(seed, scale=0.25):
 def _oracle_params(P):
     """The parameters as the kernels see them: weight matrices rounded to bf16, biases FP32."""
     P64 = P.astype(np.float64)
-    nw1, nb1, nw2, nb2, nw3 = 64 * 21, 64, 64 * 64, 64, 5 * 64
+    nw1, nb1, nw2, nb2, nw3 = 64 * 21, 64, 64 * 64, 64, NO * 64
     o = 0
     out = P64.copy()
     for n, is_w in ((nw1, True), (nb1, False), (nw2, True), (nb2, False), (nw3, True)):
@@ -138,8 +138,8 @@ def test_mlp_grad_vs_oracle():
     go, Lo = oracle.mlp_grad(_oracle_params(P), _norm_dict(N), X.astype(np.float64), Yt.astype(np.float64),
                              bf16=True)
     e = np.linalg.norm(g - go) / np.linalg.norm(go)
-    blocks = {"W1": (0, 1344), "b1": (1344, 1408), "W2": (1408, 5504), "b2": (5504, 5568), "W3": (5568, 5888),
-              "b3": (5888, 5893)}
+    blocks = {"W1": (0, 1344), "b1": (1344, 1408), "W2": (1408, 5504), "b2": (5504, 5568), "W3": (5568, 6016),
+              "b3": (6016, 6023)}
     eb = {k: np.linalg.norm(g[a:b] - go[a:b]) / np.linalg.norm(go[a:b]) for k, (a, b) in blocks.items()}
     log(f"[mlp grad] rel L2 {e:.3e}; per block " + " ".join(f"{k} {v:.2e}" for k, v in eb.items()) +
         f"; loss {L:.6f} vs {Lo:.6f}")
@@ -159,7 +159,7 @@ def test_mlp_train_reduces_loss():
     X = F.astype(np.float64)
     # targets: a smooth function of the features (stand-in for the micro moments)
     Yt = np.stack([X[:, 10] * X[:, 0], X[:, 17] * X[:, 3], X[:, 8] - X[:, 16], np.tanh(X[:, 15] + X[:, 9]),
-                   X[:, 4] - X[:, 6]], 1).astype(np.float32)
+                   X[:, 4] - X[:, 6], X[:, 1] * X[:, 2], np.tanh(X[:, 11] - X[:, 18])], 1).astype(np.float32)
     Xt = torch.from_numpy(F).cuda()
     Yd = torch.from_numpy(Yt).cuda()
     net = B.Mlp(seed=1)
@@ -191,8 +191,8 @@ def test_closure_rebuild_vs_oracle(proj):
         Gg = s.get_g_cells(cells)
         keep = s.get_g_cells(np.nonzero(~mask)[0])
     Qc = Q.reshape(ncell, 6)
-    ref = np.stack([oracle.closure_grec(p, Qc[c], out[c, :2].astype(np.float64), out[c, 2:].astype(np.float64))
-                    for c in cells])
+    o64 = out.astype(np.float64)
+    ref = np.stack([oracle.closure_grec(p, Qc[c], o64[c, :2], o64[c, 2:5], o64[c, 5:7]) for c in cells])
     e = np.abs(Gg - ref).max() / np.abs(ref).max()
     log(f"[rebuild {proj}] {len(cells)} cells, max rel {e:.3e}")
     assert e <= 1e-6
@@ -266,8 +266,8 @@ def _dilate(cls, p):
 @pytest.mark.parametrize("case", ["cavity_walls", "periodic"])
 def test_two_hybrid_steps_vs_oracle_pieces(case):
     """Two closure steps (NSF closure, threshold at the median indicator) against the oracle
-    composed the same way: classes from the oracle indicator, H = isotropic form of eps q in
-    closure cells, the oracle micro step on the cells it solves with the rebuilt micro parts
+    composed the same way: classes from the oracle indicator, H of eps (q, t) in closure
+    cells (t = 0: the isotropic form), the oracle micro step on the cells it solves with the rebuilt micro parts
     of the closure cells they need, and the oracle macro step with the assembled H."""
     B = _B()
     if case == "cavity_walls":
@@ -301,13 +301,14 @@ def test_two_hybrid_steps_vs_oracle_pieces(case):
         Gmod = Gn_valid.reshape(ncell, nv).copy()
         Qc = Qn.reshape(ncell, 6)
         for c in np.nonzero(need & ~valid)[0]:
-            Gmod[c] = oracle.closure_grec(p, Qc[c], out_or[c, :2], out_or[c, 2:])
+            Gmod[c] = oracle.closure_grec(p, Qc[c], out_or[c, :2], out_or[c, 2:5], out_or[c, 5:7])
         Go, Ho = oracle.micro2d(p, Qn, Gmod.reshape(-1))
         Go = Go.reshape(ncell, nv)
         Ho = Ho.reshape(ncell, 4)
         Hg = Hg.reshape(ncell, 4)
-        # closure cells: isotropic H of eps q
-        hc = np.array([oracle.closure_H(p["eps"] * out_or[c, :2]) for c in range(ncell)])
+        # closure cells: H of eps (q, t) (t = 0 for NSF: the isotropic form)
+        hc = np.array([oracle.closure_H(p["eps"] * out_or[c, :2], p["eps"] * out_or[c, 5:7])
+                       for c in range(ncell)])
         ecl = np.abs(Hg[~cls] - hc[~cls]).max() / (np.abs(hc[~cls]).max() + 1e-300) if (~cls).any() else 0.0
         # solved cells: the micro step
         gsc = np.abs(Go[cls]).max()
@@ -340,7 +341,7 @@ def _snapshots(B, torch, cases, steps, first, every, kn_max, cap, residual):
 def trained():
     """The closure network trained on the GPU on snapshots of cavity and quadrant runs at
     eps = 1e-3, 2e-3, 5e-3, 1e-2 (64^2 cells, 16^2 velocity nodes): it learns the
-    correction of the micro solve's (q, S) / eps to the Navier-Stokes-Fourier values,
+    correction of the micro solve's (q, S, t) / eps to the Navier-Stokes-Fourier values,
     divided by eps."""
     from paper_2509_21832_amd import closure as CL
     net, losses, n = CL.trained_closure()
@@ -392,13 +393,15 @@ def test_trained_closure_against_micro_solve(trained):
     Yn = nsf + p["eps"] * net.forward(Xh).cpu().numpy()
     rms = lambda a: float(np.sqrt(np.mean(a ** 2)))  # noqa: E731
     e_q = (rms(Yn[:, :2] - Yh[:, :2]), rms(nsf[:, :2] - Yh[:, :2]))
-    e_s = (rms(Yn[:, 2:] - Yh[:, 2:]), rms(nsf[:, 2:] - Yh[:, 2:]))
+    e_s = (rms(Yn[:, 2:5] - Yh[:, 2:5]), rms(nsf[:, 2:5] - Yh[:, 2:5]))
+    e_t = (rms(Yn[:, 5:] - Yh[:, 5:]), rms(nsf[:, 5:] - Yh[:, 5:]))
     log(f"[gain] held-out RMS error, heat flux: net {e_q[0]:.4e} NSF {e_q[1]:.4e} (target rms "
-        f"{rms(Yh[:, :2]):.3e}); stress: net {e_s[0]:.4e} NSF {e_s[1]:.4e} (target rms {rms(Yh[:, 2:]):.3e})")
+        f"{rms(Yh[:, :2]):.3e}); stress: net {e_s[0]:.4e} NSF {e_s[1]:.4e} (target rms {rms(Yh[:, 2:5]):.3e}); "
+        f"traceless third moments: net {e_t[0]:.4e} NSF {e_t[1]:.4e}")
     Fh = Xh.cpu().numpy().astype(np.float64)
     p_ = Fh[:, 0] * Fh[:, 3]
     Sc = np.stack([Fh[:, 4] - p_, Fh[:, 5], Fh[:, 6] - p_], 1) / p["eps"]
-    log(f"[gain] stress of the macro state (P - p I) / eps: RMS error {rms(Sc - Yh[:, 2:]):.4e}")
+    log(f"[gain] stress of the macro state (P - p I) / eps: RMS error {rms(Sc - Yh[:, 2:5]):.4e}")
     assert e_q[0] < 0.8 * e_q[1]
     assert e_s[0] <= 1.1 * e_s[1]
 

@@ -9,7 +9,7 @@ import pytest
 import mm_workloads as W
 import oracle
 
-NF, NH, NO = 21, 64, 5
+NF, NH, NO = 21, 64, 7
 
 
 def _problem(nx=12, ny=10, nv=16, V=8.0, bc=None, eps=0.01, **kw):
@@ -241,17 +241,35 @@ def test_closure_H_contracts_to_q():
     assert 0.5 * (H[1] + H[3]) == pytest.approx(q[1], rel=1e-15)
     # isotropic (Grad) form: H111 = 3 H122, H222 = 3 H112
     assert H[0] == pytest.approx(3 * H[2]) and H[3] == pytest.approx(3 * H[1])
+    assert np.array_equal(oracle.closure_H(q, np.zeros(2)), H)
 
 
-@pytest.mark.parametrize("proj", ["discrete", "paper"])
-def test_closure_grec_moments(proj):
-    """The rebuilt micro part has the requested stress deviation and heat flux and no
-    conserved moments (fine, wide velocity grid so quadrature errors are negligible)."""
+def test_closure_H_is_inverted_by_contractions_and_traceless_part():
+    """Any symmetric 2D third-order tensor (four free components) is rebuilt from its
+    contraction q and its traceless combinations t: the map is one to one."""
+    rng = np.random.default_rng(5)
+    for _ in range(20):
+        Hin = rng.normal(size=4)                 # (H111, H112, H122, H222)
+        q = 0.5 * np.array([Hin[0] + Hin[2], Hin[1] + Hin[3]])
+        t = np.array([Hin[0] - 3 * Hin[2], 3 * Hin[1] - Hin[3]])
+        assert np.allclose(oracle.closure_H(q, t), Hin, rtol=0, atol=1e-14)
+    # the traceless part alone has zero contraction
+    Ht = oracle.closure_H(np.zeros(2), np.array([0.8, -0.3]))
+    assert abs(Ht[0] + Ht[2]) < 1e-16 and abs(Ht[1] + Ht[3]) < 1e-16
+
+
+@pytest.mark.parametrize("proj,with_t", [("discrete", False), ("paper", False), ("discrete", True),
+                                         ("paper", True)])
+def test_closure_grec_moments(proj, with_t):
+    """The rebuilt micro part has the requested stress deviation, heat flux and traceless
+    third moments and no conserved moments (fine, wide velocity grid so quadrature
+    errors are negligible)."""
     p = _problem(nx=2, ny=2, nv=96, V=11.0, proj_mode=proj)
     q = W.conserved2d(np.array(1.3), np.array(0.2), np.array(-0.15), np.array(0.9)).reshape(-1)
     qt = np.array([0.4, -0.25])
     St = np.array([0.3, -0.12, -0.2])          # not traceless: its traceless part is used
-    g = oracle.closure_grec(p, q, qt, St).reshape(p["nv2"], p["nv1"])
+    tt = np.array([0.35, -0.6]) if with_t else None
+    g = oracle.closure_grec(p, q, qt, St, tt).reshape(p["nv2"], p["nv1"])
     v1 = W.centres(*p["v1"], p["nv1"])
     v2 = W.centres(*p["v2"], p["nv2"])
     V1, V2 = np.meshgrid(v1, v2)
@@ -269,9 +287,13 @@ def test_closure_grec_moments(proj):
     ww = w1 ** 2 + w2 ** 2
     assert 0.5 * m(w1 * ww) == pytest.approx(qt[0], abs=1e-10)
     assert 0.5 * m(w2 * ww) == pytest.approx(qt[1], abs=1e-10)
-    # third central moments in the isotropic form (the H of the closure, divided by eps)
-    H = oracle.closure_H(qt)
-    assert np.allclose([m(w1 ** 3), m(w1 ** 2 * w2), m(w1 * w2 ** 2), m(w2 ** 3)], H, atol=1e-10)
+    # third central moments: the H of the closure, divided by eps
+    H = oracle.closure_H(qt, tt)
+    H3 = [m(w1 ** 3), m(w1 ** 2 * w2), m(w1 * w2 ** 2), m(w2 ** 3)]
+    assert np.allclose(H3, H, atol=1e-10)
+    t_exp = tt if with_t else np.zeros(2)
+    assert H3[0] - 3 * H3[2] == pytest.approx(t_exp[0], abs=1e-10)
+    assert 3 * H3[1] - H3[3] == pytest.approx(t_exp[1], abs=1e-10)
 
 
 def test_nsf_closure_matches_moments_of_first_order_micro_part():
@@ -295,7 +317,7 @@ def test_nsf_closure_matches_moments_of_first_order_micro_part():
     dv = (v1[1] - v1[0]) ** 2
     for cell in (0, 9, 27, 45, 63):
         f = F[cell]
-        qt, St = oracle.nsf_closure(p, f)
+        qt, St, tt = oracle.nsf_closure(p, f)
         w1, w2 = V1 - f[1], V2 - f[2]
         ww = w1 ** 2 + w2 ** 2
         g = Gh[cell]
@@ -304,3 +326,9 @@ def test_nsf_closure_matches_moments_of_first_order_micro_part():
         assert dv * np.sum(w1 * w1 * g) == pytest.approx(St[0], rel=1e-8, abs=1e-9)
         assert dv * np.sum(w1 * w2 * g) == pytest.approx(St[1], rel=1e-8, abs=1e-9)
         assert dv * np.sum(w2 * w2 * g) == pytest.approx(St[2], rel=1e-8, abs=1e-9)
+        # G-hat's third central moments are of the isotropic form: its traceless part is 0
+        h111, h112 = dv * np.sum(w1 ** 3 * g), dv * np.sum(w1 * w1 * w2 * g)
+        h122, h222 = dv * np.sum(w1 * w2 * w2 * g), dv * np.sum(w2 ** 3 * g)
+        scale = 1e-8 * (abs(h111) + abs(h122) + abs(h112) + abs(h222)) + 1e-9
+        assert abs(h111 - 3 * h122 - tt[0]) <= scale
+        assert abs(3 * h112 - h222 - tt[1]) <= scale
