@@ -139,7 +139,9 @@ typedef struct {
  *   g0: host G^0 (layout above) or NULL for g = 0, the paper's initial
  *       condition in every example (with q0 != NULL).
  *   *out receives the context, or NULL on failure (nothing leaks).
- * Errors: MM_EINVAL (bad sizes, eps <= 0, cfl <= 0, nu outside [-1, 1) in 2D,
+ * Errors: MM_EINVAL (bad sizes: more than INT_MAX cells or velocity nodes, or
+ * more than 4e10 phase-space points; non-finite box bounds, eps, cfl or dt;
+ * eps <= 0, cfl <= 0 without dt, nu outside [-1, 1) in 2D,
  * unpaired periodic sides, inflow sides in 1D, T_wall <= 0, dev_buffers partly set, set
  * in 1D or with two equal G buffers), MM_ENONPHYS (Q^0 not physical), MM_ENOMEM,
  * MM_EDEVICE.
@@ -190,7 +192,8 @@ void mm_free(mm_ctx *ctx);
 /* mm_dt -- the time step cfg implies (cfg->dt if > 0, else the CFL rule).
  * With t_final > 0 the reset rule of Sec. 3.2 / (CFL-2D-part1) is applied:
  * N = ceil(t_final / dt), dt = t_final / N, and *nsteps (if not NULL) gets N.
- * Returns a negative value for an invalid configuration. */
+ * Returns a negative value for an invalid configuration, or when N would not
+ * fit an int. */
 double mm_dt(const mm_config *cfg, double t_final, int *nsteps);
 
 /* mm_failed_step -- first step whose macro state was non-physical, or -1. */

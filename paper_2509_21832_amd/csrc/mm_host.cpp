@@ -79,8 +79,15 @@ int check_cfg(const mm_config *c)
     if (c->dim == 2 && (c->ny < 2 || c->nv2 < 2)) return MM_EINVAL;
     if (!(c->x_hi > c->x_lo) || !(c->v1_hi > c->v1_lo)) return MM_EINVAL;
     if (c->dim == 2 && (!(c->y_hi > c->y_lo) || !(c->v2_hi > c->v2_lo))) return MM_EINVAL;
+    const double box[8] = {c->x_lo, c->x_hi, c->y_lo, c->y_hi, c->v1_lo, c->v1_hi, c->v2_lo, c->v2_hi};
+    for (double b : box)
+        if (!std::isfinite(b)) return MM_EINVAL;
     if (!(c->eps > 0.0) || !std::isfinite(c->eps)) return MM_EINVAL;
-    if (!(c->dt > 0.0) && !(c->cfl > 0.0)) return MM_EINVAL;
+    if (c->dt > 0.0) {                          // a given dt replaces the CFL rule
+        if (!std::isfinite(c->dt)) return MM_EINVAL;
+    } else if (!(c->cfl > 0.0) || !std::isfinite(c->cfl)) {
+        return MM_EINVAL;
+    }
     if (c->dim == 2 && (!(c->nu >= -1.0) || !(c->nu < 1.0))) return MM_EINVAL;
     if (c->tau_model < 0 || c->tau_model > 3 || !(c->tau_coef > 0.0)) return MM_EINVAL;
     if (c->proj_mode != MM_PROJ_DISCRETE && c->proj_mode != MM_PROJ_PAPER) return MM_EINVAL;
@@ -96,8 +103,9 @@ int check_cfg(const mm_config *c)
     }
     if ((c->bc[0].kind == MM_BC_PERIODIC) != (c->bc[1].kind == MM_BC_PERIODIC)) return MM_EINVAL;
     if (c->dim == 2 && (c->bc[2].kind == MM_BC_PERIODIC) != (c->bc[3].kind == MM_BC_PERIODIC)) return MM_EINVAL;
-    const double pts = (double)c->nx * (c->dim == 2 ? c->ny : 1) * c->nv1 * (c->dim == 2 ? c->nv2 : 1);
-    if (pts > 4.0e10) return MM_EINVAL;
+    // cell and node counts are ints in the kernels' index arithmetic
+    const double cells = (double)c->nx * (c->dim == 2 ? c->ny : 1), nodes = (double)c->nv1 * (c->dim == 2 ? c->nv2 : 1);
+    if (cells > INT_MAX || nodes > INT_MAX || cells * nodes > 4.0e10) return MM_EINVAL;
     const int nbuf = (c->dev_buffers[0] != nullptr) + (c->dev_buffers[1] != nullptr) + (c->dev_buffers[2] != nullptr);
     if (nbuf != 0 && (nbuf != 3 || c->dim != 2 || c->dev_buffers[0] == c->dev_buffers[1])) return MM_EINVAL;
     return MM_OK;
@@ -476,7 +484,9 @@ double mm_dt(const mm_config *cfg, double t_final, int *nsteps)
     if (check_cfg(cfg) != MM_OK) return -1.0;
     double dt = cfg->dt > 0.0 ? cfg->dt : dt_rule(cfg);
     if (t_final > 0.0) {
-        const int n = (int)std::ceil(t_final / dt);
+        const double steps = std::ceil(t_final / dt);
+        if (!(steps <= (double)INT_MAX)) return -1.0;    // more steps than an int holds (or t_final not finite)
+        const int n = (int)steps;
         dt = t_final / n;
         if (nsteps) *nsteps = n;
     } else if (nsteps) {
