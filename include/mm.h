@@ -262,9 +262,10 @@ int mm_device_ptrs(mm_ctx *ctx, void **q, void **g, void **h, int *g_bytes);
  * of Sec. 6.3 and whose traceless combinations are t = (H111 - 3 H122,
  * 3 H112 - H222); t = 0 is the isotropic (Grad) form.
  *
- * Features of a cell (21, FP32): (rho, u1, u2, T, P11, P12, P22) and their
- * centred x and y differences (one-sided next to a non-periodic side), in that
- * order.  Targets (7, FP32): (q1, q2, S11, S12, S22, t1, t2) / eps with
+ * Features of a cell (30, FP32): (rho, u1, u2, T, P11, P12, P22), their
+ * centred x and y differences (one-sided next to a non-periodic side), the
+ * local mean free path eps sqrt(T) / tau, and the second x and y differences
+ * of (rho, u1, u2, T) (zero next to a non-periodic side), in that order.  Targets (7, FP32): (q1, q2, S11, S12, S22, t1, t2) / eps with
  *   q = (H111 + H122, H112 + H222) / 2,  S = eps dv sum (w w^T) g,
  *   t = (H111 - 3 H122, 3 H112 - H222).
  * Local Knudsen indicator:
@@ -281,11 +282,11 @@ int mm_device_ptrs(mm_ctx *ctx, void **q, void **g, void **h, int *g_bytes);
  * mm_moments are meaningful only in solved cells.
  * ===================================================================== */
 
-/* the network: 21 -> 64 -> 64 -> 7, GELU (erf form), bf16 weights and
+/* the network: 30 -> 64 -> 64 -> 7, GELU (erf form), bf16 weights and
  * activations on the matrix cores with FP32 accumulation, FP32 master weights */
 typedef struct mm_mlp mm_mlp;
-#define MM_MLP_NPARAM 6023   /* W1[64][21], b1[64], W2[64][64], b2[64], W3[7][64], b3[7] */
-#define MM_MLP_NNORM 56      /* in_mean[21], in_std[21], out_mean[7], out_std[7]         */
+#define MM_MLP_NPARAM 6599   /* W1[64][30], b1[64], W2[64][64], b2[64], W3[7][64], b3[7] */
+#define MM_MLP_NNORM 74      /* in_mean[30], in_std[30], out_mean[7], out_std[7]         */
 
 /* mm_mlp_create -- a network on `device` with Glorot-uniform weights drawn
  * from `seed` (SplitMix64), zero biases and identity normalisation; stream as
@@ -294,7 +295,7 @@ int mm_mlp_create(int device, void *stream, unsigned long long seed, mm_mlp **ou
 void mm_mlp_free(mm_mlp *net);
 
 /* mm_mlp_fit_norm -- set the normalisation to the mean and standard deviation
- * of the n rows of x_dev [n][21] and y_dev [n][7] (device FP32). */
+ * of the n rows of x_dev [n][30] and y_dev [n][7] (device FP32). */
 int mm_mlp_fit_norm(mm_mlp *net, const float *x_dev, const float *y_dev, int n);
 
 /* mm_mlp_get / mm_mlp_set -- FP32 parameters [MM_MLP_NPARAM] and normalisation
@@ -303,7 +304,7 @@ int mm_mlp_fit_norm(mm_mlp *net, const float *x_dev, const float *y_dev, int n);
 int mm_mlp_get(mm_mlp *net, float *params, float *norm);
 int mm_mlp_set(mm_mlp *net, const float *params, const float *norm);
 
-/* mm_mlp_forward -- raw outputs y_dev [n][7] of raw features x_dev [n][21]:
+/* mm_mlp_forward -- raw outputs y_dev [n][7] of raw features x_dev [n][30]:
  * y = MLP((x - in_mean) / in_std) * out_std + out_mean (device FP32). */
 int mm_mlp_forward(mm_mlp *net, const float *x_dev, int n, float *y_dev);
 
@@ -332,7 +333,12 @@ int mm_mlp_train(mm_mlp *net, const float *x_dev, const float *y_dev, int n, int
  *     kind, see mm_closure_snapshot).
  * The network is kept by pointer: it must outlive its use and not be trained
  * while the context steps.  Stepping an MM_CLOSURE context without a closure
- * gives MM_EINVAL. */
+ * gives MM_EINVAL.  The closure values stand for a relaxed micro part: from a
+ * g that is not relaxed (g = 0 at mm_init), attach with kn_max = 0 for the
+ * initial layer, a few collision times eps tau (every cell with a nonzero
+ * indicator is then solved; where it is zero the state is uniform and g = 0 is
+ * relaxed), and attach the threshold after it; attaching again replaces the
+ * previous closure. */
 int mm_closure_attach(mm_ctx *ctx, mm_mlp *net, double kn_max, int residual);
 
 /* mm_closure_cells -- number of closure cells summed over the steps since the
@@ -344,13 +350,13 @@ int mm_closure_cells(mm_ctx *ctx, long long *n_closure, unsigned char *cls_host)
  * MM_MIXED context): the features of the current state, one step, the targets
  * of the new micro part (residual = 1: minus the NSF values of the cell).
  * Rows of cells with kn <= kn_max that are not next to a non-periodic side are
- * appended in cell order to x_dev [capacity][21] and y_dev [capacity][7]
+ * appended in cell order to x_dev [capacity][30] and y_dev [capacity][7]
  * (device FP32) from row *count on; *count is updated (at most capacity rows
  * are written). */
 int mm_closure_snapshot(mm_ctx *ctx, double kn_max, int residual, float *x_dev, float *y_dev, int capacity,
                         int *count);
 
-/* mm_closure_features -- features [ny][nx][21], kn [ny][nx] and the
+/* mm_closure_features -- features [ny][nx][30], kn [ny][nx] and the
  * next-to-a-non-periodic-side mask [ny][nx] of the current state (host;
  * kn_host and edge_host may be NULL). */
 int mm_closure_features(mm_ctx *ctx, float *feat_host, float *kn_host, unsigned char *edge_host);
@@ -387,7 +393,9 @@ int mm_closure_rebuild(mm_ctx *ctx, const float *out_host, const unsigned char *
  *   h_dev   device H [ny][nx][4] FP64 of the last step, or NULL (H stays in the
  *           static array).
  *   failed_step  NULL: the work is only enqueued on cfg->stream (NULL: the null
- *           stream) and the call returns; usable under stream capture.
+ *           stream) and the call returns; it enqueues kernel launches only, so
+ *           it can be captured in a HIP graph and replayed (the first call on a
+ *           device looks up the static array's address: make it outside capture).
  *           Otherwise the call waits for the stream and, as mm_step does,
  *           returns MM_ENONPHYS with *failed_step the first non-physical step,
  *           counted from 0 at the start of this call (-1 when none).

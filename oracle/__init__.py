@@ -291,7 +291,7 @@ def wall_R(u, Taa, T_wall, sign):
 
 # ---------------------------------------------------------------- closure form
 
-N_FEAT, N_HID, N_OUT = 21, 64, 7
+N_FEAT, N_HID, N_OUT = 30, 64, 7
 
 
 def mlp_nparam():
@@ -299,7 +299,7 @@ def mlp_nparam():
 
 
 def features2d(p, Q):
-    """Per-cell features [ncell, 21], local Knudsen indicator [ncell] and the
+    """Per-cell features [ncell, 30], local Knudsen indicator [ncell] and the
     always-micro mask of cells next to non-periodic sides [ncell]."""
     n = p["nx"] * p["ny"]
     F = np.zeros(n * N_FEAT)
@@ -316,8 +316,8 @@ def _norm(norm):
 
 
 def mlp_forward(params, norm, X, bf16=False):
-    """Raw outputs [n, 7] of the closure network for raw features X [n, 21]:
-    (q1, q2, S11, S12, S22, t1, t2) / eps; norm: dict of in_mean, in_std (21),
+    """Raw outputs [n, 7] of the closure network for raw features X [n, 30]:
+    (q1, q2, S11, S12, S22, t1, t2) / eps; norm: dict of in_mean, in_std (30),
     out_mean, out_std (7)."""
     X = _f64(X).reshape(-1, N_FEAT)
     Y = np.zeros((X.shape[0], N_OUT))

@@ -3,10 +3,12 @@
  * of the 2D2V micro-macro step (the closure itself is not in the paper; its
  * ingredients are):
  *   - per-cell features: the primitive state (rho, u1, u2, T, P11, P12, P22)
- *     of the macro vector of Sec. 5.1 and its centred x / y differences;
+ *     of the macro vector of Sec. 5.1, its centred x / y differences, the
+ *     local mean free path eps sqrt(T) / tau and the second x / y differences
+ *     of (rho, u1, u2, T);
  *   - the local Knudsen indicator that decides where the closure may replace
  *     the micro solve;
- *   - a 21 -> 64 -> 64 -> 7 perceptron with exact (erf) GELU, its loss and its
+ *   - a 30 -> 64 -> 64 -> 7 perceptron with exact (erf) GELU, its loss and its
  *     gradient by reverse accumulation;
  *   - the heat-flux tensor H of the closed macro system (eq5-41), four third
  *     moments in 2D, rebuilt from its two contractions (the heat-flux vector q,
@@ -53,7 +55,7 @@ typedef struct {
 /* from mm_oracle.c */
 int o_project2d(const void *cfg, const double *q, const double *F, double *PF);
 
-#define NF 21
+#define NF 30
 #define NH 64
 #define NO 7   /* (q1, q2, S11, S12, S22, t1, t2) / eps */
 #define NPARAM (NH * NF + NH + NH * NH + NH + NO * NH + NO)
@@ -94,6 +96,10 @@ static double diff1(const double *wm, const double *w0, const double *wp, int ha
  * Features, indicator and the "always micro" mask of every cell.
  *   feat[c][0..6]   = (rho, u1, u2, T, P11, P12, P22)
  *   feat[c][7..13]  = d/dx of the same, feat[c][14..20] = d/dy
+ *   feat[c][21]     = eps sqrt(T) / tau (the local mean free path)
+ *   feat[c][22..25] = d2/dx2 of (rho, u1, u2, T), feat[c][26..29] = d2/dy2: the
+ *                     central second difference, zero where a neighbour is
+ *                     missing (next to a side that is not periodic)
  *   kn[c]  = (eps sqrt(T) / tau) max(|grad rho| / rho, |grad T| / T, |grad u|_F / sqrt(T))
  *   edge[c] = 1 for cells next to a side that is not periodic (their micro part
  *             is always solved), else 0.
@@ -126,13 +132,18 @@ int o_features2d(const void *cfgp, const double *Q, double *feat, double *kn, in
                 f[14 + a] = diff1(wym, w0, wyp, vm, vp, dy, a);
             }
             const double rho = w0[0], T = w0[3];
+            f[21] = c->eps * sqrt(T) / tau_of(c, rho, T);
+            for (int a = 0; a < 4; ++a) {
+                f[22 + a] = hm && hp ? (wxp[a] - 2.0 * w0[a] + wxm[a]) / (dx * dx) : 0.0;
+                f[26 + a] = vm && vp ? (wyp[a] - 2.0 * w0[a] + wym[a]) / (dy * dy) : 0.0;
+            }
             const double gr = sqrt(f[7] * f[7] + f[14] * f[14]) / rho;
             const double gT = sqrt(f[10] * f[10] + f[17] * f[17]) / T;
             const double gu = sqrt(f[8] * f[8] + f[15] * f[15] + f[9] * f[9] + f[16] * f[16]) / sqrt(T);
             double m = gr;
             if (gT > m) m = gT;
             if (gu > m) m = gu;
-            kn[cidx] = c->eps * sqrt(T) / tau_of(c, rho, T) * m;
+            kn[cidx] = f[21] * m;
             edge[cidx] = (!px && (i == 0 || i == nx - 1)) || (!py && (j == 0 || j == ny - 1));
         }
     free(W);
@@ -160,7 +171,7 @@ double o_bf16(double x)
     return ldexp(r, e - 8);
 }
 
-/* parameter block: W1[64][21], b1[64], W2[64][64], b2[64], W3[7][64], b3[7] */
+/* parameter block: W1[64][30], b1[64], W2[64][64], b2[64], W3[7][64], b3[7] */
 typedef struct {
     const double *W1, *b1, *W2, *b2, *W3, *b3;
 } mlp_view;
@@ -172,7 +183,7 @@ static mlp_view view(const double *p)
     return v;
 }
 
-/* one sample: normalised input xh[21] -> pre-activations z1, z2, activations a1,
+/* one sample: normalised input xh[30] -> pre-activations z1, z2, activations a1,
  * a2 and the normalised output yh[7].  With bf16 != 0 every matrix-product input
  * (xh, a1, a2) is rounded to bfloat16 first, as the GPU kernels feed them to the
  * matrix cores; sums and everything else stay FP64. */
@@ -203,9 +214,9 @@ static void forward1(const mlp_view *v, const double *xh_in, int bf16, double *z
 }
 
 /*
- * Network outputs for n samples of raw features X[n][21]:
+ * Network outputs for n samples of raw features X[n][30]:
  *   xh = (x - in_mean) / in_std, yh = MLP(xh), y = yh * out_std + out_mean.
- * norm = [in_mean(21), in_std(21), out_mean(5), out_std(5)].
+ * norm = [in_mean(30), in_std(30), out_mean(7), out_std(7)].
  */
 int o_mlp_forward(const double *params, const double *norm, const double *X, int n, int bf16, double *Y)
 {

@@ -123,14 +123,14 @@ int main(void)
     /* closure pieces */
     {
         o_cfg c = cfg2d(5, 4, 8, O_BC_WALL, O_BC_PERIODIC);
-        double Q[6 * 20], F[21 * 20], kn[20];
+        double Q[6 * 20], F[30 * 20], kn[20];
         int edge[20];
         state2d(&c, Q);
         CHECK(o_features2d(&c, Q, F, kn, edge) == 0);
         const int np = o_mlp_nparam();
-        double *par = calloc(np, sizeof(double)), *gr = malloc(sizeof(double) * np), norm[56], Y[7 * 20], loss;
+        double *par = calloc(np, sizeof(double)), *gr = malloc(sizeof(double) * np), norm[74], Y[7 * 20], loss;
         for (int k = 0; k < np; ++k) par[k] = 0.01 * sin(0.37 * k);
-        for (int k = 0; k < 56; ++k) norm[k] = (k >= 21 && k < 42) || k >= 49 ? 1.0 : 0.0;
+        for (int k = 0; k < 74; ++k) norm[k] = (k >= 30 && k < 60) || k >= 67 ? 1.0 : 0.0;
         CHECK(o_mlp_forward(par, norm, F, 20, 1, Y) == 0);
         CHECK(o_mlp_grad(par, norm, F, Y, 20, 0, gr, &loss) == 0);
         double qt[2] = {0.1, -0.05}, St[3] = {0.02, 0.01, -0.02}, tt[2] = {0.03, -0.01}, Hc[4], g[64];

@@ -28,9 +28,9 @@ EXPORTS = ("mm_init", "mm_step", "mm_step_async", "mm_sync", "mm_moments", "mm_g
            "mm_closure_snapshot", "mm_closure_features", "mm_closure_rebuild", "mm_step2d_noalloc",
            "mm_set_source")
 
-MLP_NPARAM = 6023
-MLP_NNORM = 56
-N_FEAT, N_OUT = 21, 7
+MLP_NPARAM = 6599
+MLP_NNORM = 74
+N_FEAT, N_OUT = 30, 7
 
 
 class MMError(RuntimeError):
@@ -354,7 +354,7 @@ class Solver:
         return n.value, cls
 
     def closure_snapshot(self, kn_max, X, Y, count, residual=0):
-        """Append training rows to the device tensors X [cap, 21], Y [cap, 7]; returns the new count."""
+        """Append training rows to the device tensors X [cap, 30], Y [cap, 7]; returns the new count."""
         cap = X.shape[0]
         if Y.shape[0] != cap:
             raise ValueError("X and Y capacities differ")

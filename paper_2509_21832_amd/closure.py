@@ -5,8 +5,17 @@ this module only chooses the runs and marshals device buffers.
 
 The network learns residual kind 2: the correction of the micro solve's
 (q, S, t) / eps to the Navier-Stokes-Fourier values, divided by eps (the leading
-correction is first order in eps, so the target is nearly eps-independent and
-the features carry no eps).
+correction is first order in eps, so the target is nearly eps-independent; the
+local mean free path among the features carries what is not).
+
+The training runs use the grid of the closure's use (256^2 cells, 32^2 velocity
+nodes): the second differences among the features scale with the cell size, and
+the targets hold the quadrature of the velocity grid, so a network trained on
+another grid does not carry over.
+
+A closure cell stands for a relaxed micro part.  From g = 0 (the initial
+condition of every example) the micro part relaxes over a few collision times
+eps tau, so a run starts with every cell solved (start()).
 """
 import numpy as np
 
@@ -15,9 +24,10 @@ import mm_workloads as W
 RESIDUAL = 2          # kind of residual the network predicts (see mm_closure_attach)
 KN_TRAIN = 0.1        # snapshot cells up to twice the default threshold of the closure form
 KN_MAX = 0.05         # threshold of the closure form
+INITIAL_LAYER = 40    # steps with every cell solved before the closure takes over
 
 
-def training_runs(eps_list=(1e-3, 2e-3, 5e-3, 1e-2), nx=64, nv=16, seed0=20):
+def training_runs(eps_list=(1e-3, 2e-3, 5e-3, 1e-2), nx=256, nv=32, seed0=20):
     """Cavity-box and quadrant-Riemann states, one of each per eps (seeded)."""
     runs = []
     for k, eps in enumerate(eps_list):
@@ -26,8 +36,9 @@ def training_runs(eps_list=(1e-3, 2e-3, 5e-3, 1e-2), nx=64, nv=16, seed0=20):
     return runs
 
 
-def snapshots(runs, steps=160, first=40, every=6, kn_max=KN_TRAIN, residual=RESIDUAL, cap=4_000_000):
-    """Training rows (device tensors X [n, 21], Y [n, 7]) from full micro solves with g in
+def snapshots(runs, steps=160, first=INITIAL_LAYER, every=12, kn_max=KN_TRAIN, residual=RESIDUAL,
+              cap=12_000_000):
+    """Training rows (device tensors X [n, 30], Y [n, 7]) from full micro solves with g in
     FP32: a snapshot every `every` steps from step `first` on (the first steps relax g from
     its zero initial value)."""
     import torch
@@ -43,6 +54,17 @@ def snapshots(runs, steps=160, first=40, every=6, kn_max=KN_TRAIN, residual=RESI
                 else:
                     s.step(1)
     return X[:count].contiguous(), Y[:count].contiguous()
+
+
+def start(solver, net, kn_max=KN_MAX, residual=RESIDUAL, initial_layer=INITIAL_LAYER):
+    """Run a closure-form solver through the initial layer with every cell solved
+    (kn_max = 0), then attach the closure with its threshold (net None: the
+    Navier-Stokes-Fourier values, residual 0).  Returns the number of steps run."""
+    r = residual if net is not None else 0
+    solver.closure_attach(net, 0.0, residual=r)
+    solver.step(initial_layer)
+    solver.closure_attach(net, kn_max, residual=r)
+    return initial_layer
 
 
 def train(X, Y, epochs=30, batch=512, lr=2e-3, seed=3):

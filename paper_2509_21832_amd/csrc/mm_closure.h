@@ -8,10 +8,12 @@
 namespace mm {
 namespace closure {
 
-constexpr int NF = 21;      // features: (rho, u1, u2, T, P11, P12, P22), d/dx, d/dy
+constexpr int NF = 30;      // features: (rho, u1, u2, T, P11, P12, P22), d/dx, d/dy; eps sqrt(T) / tau;
+                            // d2/dx2, d2/dy2 of (rho, u1, u2, T)
+static_assert(NF <= 32, "the first layer takes at most 32 inputs (two K-blocks of 16)");
 constexpr int NH = 64;      // hidden width (two layers)
 constexpr int NO = 7;       // outputs: (q1, q2, S11, S12, S22, t1, t2) / eps
-constexpr int NPARAM = NH * NF + NH + NH * NH + NH + NO * NH + NO;   // 6023
+constexpr int NPARAM = NH * NF + NH + NH * NH + NH + NO * NH + NO;   // 6599
 static_assert(NO <= 8, "the output layer keeps outputs 4 g + v (g < 2, v < 4) per lane half");
 constexpr int NNORM = 2 * NF + 2 * NO;   // in_mean, in_std, out_mean, out_std
 

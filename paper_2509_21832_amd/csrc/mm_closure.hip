@@ -3,7 +3,8 @@
 // The macro system of Sec. 5.1 is closed by the heat-flux tensor H of the micro
 // part (eq5-41).  In near-continuum cells the closure form replaces the micro
 // solve by a small network that predicts, from the local macro state and its
-// centred differences, the heat-flux vector q, the stress deviation S and the
+// first and second differences and its local mean free path, the heat-flux
+// vector q, the stress deviation S and the
 // traceless third moments t = (H111 - 3 H122, 3 H112 - H222) of eps g (scaled
 // by 1/eps).  H is rebuilt from its contraction q (the heat-flux vector h of
 // Sec. 6.3) and t: the isotropic form H_abc = (q_a d_bc + q_b d_ac + q_c d_ab) / 2
@@ -11,7 +12,7 @@
 // whose local Knudsen indicator exceeds the threshold, keep the full micro
 // solve; their neighbours' micro parts are rebuilt from (q, S, t) when needed.
 //
-// The network: 21 -> 64 -> 64 -> 7, exact (erf) GELU, bf16 weights and
+// The network: 30 -> 64 -> 64 -> 7, exact (erf) GELU, bf16 weights and
 // activations on the matrix cores (v_mfma_f32_32x32x16_bf16) with FP32
 // accumulation, FP32 master weights and Adam moments.  Every matrix product of
 // the forward and backward passes runs on a 32-sample tile per wavefront, with
@@ -86,8 +87,8 @@ __device__ __forceinline__ float gelu_d(float z)
            z * __builtin_amdgcn_exp2f(-0.72134752044448170f * z * z) * 0.39894228040143268f;
 }
 
-// Weights of the network in LDS (bf16): W1 [64][32] (inputs 21..31 zero),
-// W2 [64][64], W3 [32][64] (rows 5..31 zero); biases and normalisation FP32.
+// Weights of the network in LDS (bf16): W1 [64][32] (inputs 30, 31 zero),
+// W2 [64][64], W3 [32][64] (rows 7..31 zero); biases and normalisation FP32.
 struct SmemW {
     __bf16 W1[NH * 32];
     __bf16 W2[NH * NH];
@@ -112,7 +113,7 @@ __device__ void load_weights(SmemW &s, const MlpDev &w)
 
 // Per-wavefront activations of one 32-sample tile (row-major, column = sample)
 struct SmemFwd {
-    __bf16 X[32 * 32];     // normalised inputs [feature][sample], features >= 21 zero
+    __bf16 X[32 * 32];     // normalised inputs [feature][sample], features >= 30 zero
     __bf16 A1[NH * 32];
     __bf16 A2[NH * 32];
 };
@@ -120,7 +121,7 @@ struct SmemFwd {
 struct SmemBwd {
     float G1[NH * 32];     // gelu'(z1), gelu'(z2)
     float G2[NH * 32];
-    __bf16 dY[32 * 32];    // output error [output][sample], outputs >= 5 zero
+    __bf16 dY[32 * 32];    // output error [output][sample], outputs >= 7 zero
     __bf16 dZ2[NH * 32];
     __bf16 dZ1[NH * 32];
 };
@@ -511,7 +512,7 @@ __global__ void k_mlp_pack(const float *__restrict__ master, __bf16 *__restrict_
     if (t < NO) b3[t] = pb3[t];
 }
 
-// Mean and standard deviation of the 21 feature and 5 target columns (FP64
+// Mean and standard deviation of the 30 feature and 7 target columns (FP64
 // sums, one workgroup per column).  A standard deviation below 1e-6 times the
 // column's root mean square (or exactly zero) is raised to that floor.
 __global__ __launch_bounds__(256) void k_mlp_norm(const float *__restrict__ X, const float *__restrict__ Y, int n,
@@ -590,14 +591,25 @@ __device__ __forceinline__ void cell_features(const double *__restrict__ Q, cons
                     : vm        ? (w0[a] - wym[a]) * idy
                                 : 0.0;
     }
+    // the local mean free path eps sqrt(T) / tau, and the second differences of
+    // (rho, u1, u2, T) along x and y (zero next to a side that is not periodic:
+    // those cells are always solved)
+    const double rho = w0[0], T = w0[3];
+    const double lam = P.eps * sqrt(T) / tau_of(P, rho, rho * T, T);
+    f[21] = lam;
+    const double idx2 = idx * idx, idy2 = idy * idy;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        f[22 + a] = (hm && hp) ? (wxp[a] - 2.0 * w0[a] + wxm[a]) * idx2 : 0.0;
+        f[26 + a] = (vm && vp) ? (wyp[a] - 2.0 * w0[a] + wym[a]) * idy2 : 0.0;
+    }
 #pragma unroll
     for (int a = 0; a < NF; ++a) fo[a] = (float)f[a];
-    const double rho = w0[0], T = w0[3];
     const double gr = sqrt(f[7] * f[7] + f[14] * f[14]) / rho;
     const double gT = sqrt(f[10] * f[10] + f[17] * f[17]) / T;
     const double gu = sqrt(f[8] * f[8] + f[15] * f[15] + f[9] * f[9] + f[16] * f[16]) / sqrt(T);
     const double m = fmax(gr, fmax(gT, gu));
-    kn = P.eps * sqrt(T) / tau_of(P, rho, rho * T, T) * m;
+    kn = lam * m;
     edge = (!px && (i == 0 || i == P.nx - 1)) || (!py && (j == 0 || j == P.ny - 1));
 }
 

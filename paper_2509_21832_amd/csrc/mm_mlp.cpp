@@ -16,6 +16,9 @@
 #include "mm_closure.h"
 #include "mm_mlp_impl.h"
 
+static_assert(MM_MLP_NPARAM == mm::closure::NPARAM && MM_MLP_NNORM == mm::closure::NNORM,
+              "parameter and normalisation sizes of the header");
+
 using namespace mm::closure;
 
 namespace {

@@ -32,6 +32,19 @@ def test_library_exports_every_declared_symbol():
     assert set(_declared()) == set(B.EXPORTS)
 
 
+def test_binding_sizes_match_the_header():
+    """The closure network's sizes in the binding are the header's."""
+    import re
+    from paper_2509_21832_amd import binding as B
+    text = open(os.path.join(ROOT, "include", "mm.h")).read()
+    val = {k: int(re.search(rf"#define {k} (\d+)", text).group(1))
+           for k in ("MM_MLP_NPARAM", "MM_MLP_NNORM", "MM_NOALLOC_MAX_CELLS")}
+    assert B.MLP_NPARAM == val["MM_MLP_NPARAM"] and B.MLP_NNORM == val["MM_MLP_NNORM"]
+    assert B.NOALLOC_MAX_CELLS == val["MM_NOALLOC_MAX_CELLS"]
+    assert B.MLP_NPARAM == 64 * B.N_FEAT + 64 + 64 * 64 + 64 + B.N_OUT * 64 + B.N_OUT
+    assert B.MLP_NNORM == 2 * B.N_FEAT + 2 * B.N_OUT
+
+
 def test_dt_rule_matches_oracle():
     import oracle
     from paper_2509_21832_amd import binding as B

@@ -12,7 +12,7 @@ from gpu_common import log, rel_l1
 
 pytestmark = pytest.mark.gpu
 
-NF, NO = 21, 7
+NF, NO = 30, 7
 
 
 def _torch():
@@ -69,7 +69,7 @@ def _net(seed, scale=0.25):
 def _oracle_params(P):
     """The parameters as the kernels see them: weight matrices rounded to bf16, biases FP32."""
     P64 = P.astype(np.float64)
-    nw1, nb1, nw2, nb2, nw3 = 64 * 21, 64, 64 * 64, 64, NO * 64
+    nw1, nb1, nw2, nb2, nw3 = 64 * NF, 64, 64 * 64, 64, NO * 64
     o = 0
     out = P64.copy()
     for n, is_w in ((nw1, True), (nb1, False), (nw2, True), (nb2, False), (nw3, True)):
@@ -138,8 +138,8 @@ def test_mlp_grad_vs_oracle():
     go, Lo = oracle.mlp_grad(_oracle_params(P), _norm_dict(N), X.astype(np.float64), Yt.astype(np.float64),
                              bf16=True)
     e = np.linalg.norm(g - go) / np.linalg.norm(go)
-    blocks = {"W1": (0, 1344), "b1": (1344, 1408), "W2": (1408, 5504), "b2": (5504, 5568), "W3": (5568, 6016),
-              "b3": (6016, 6023)}
+    o = np.cumsum([0, 64 * NF, 64, 64 * 64, 64, NO * 64, NO])
+    blocks = {k: (o[i], o[i + 1]) for i, k in enumerate(("W1", "b1", "W2", "b2", "W3", "b3"))}
     eb = {k: np.linalg.norm(g[a:b] - go[a:b]) / np.linalg.norm(go[a:b]) for k, (a, b) in blocks.items()}
     log(f"[mlp grad] rel L2 {e:.3e}; per block " + " ".join(f"{k} {v:.2e}" for k, v in eb.items()) +
         f"; loss {L:.6f} vs {Lo:.6f}")
@@ -340,89 +340,87 @@ def _snapshots(B, torch, cases, steps, first, every, kn_max, cap, residual):
 @pytest.fixture(scope="module")
 def trained():
     """The closure network trained on the GPU on snapshots of cavity and quadrant runs at
-    eps = 1e-3, 2e-3, 5e-3, 1e-2 (64^2 cells, 16^2 velocity nodes): it learns the
-    correction of the micro solve's (q, S, t) / eps to the Navier-Stokes-Fourier values,
-    divided by eps."""
+    eps = 1e-3, 2e-3, 5e-3, 1e-2 on the grid of its use (256^2 cells, 32^2 velocity
+    nodes): it learns the correction of the micro solve's (q, S, t) / eps to the
+    Navier-Stokes-Fourier values, divided by eps."""
     from paper_2509_21832_amd import closure as CL
     net, losses, n = CL.trained_closure()
     log(f"[train] {n} samples; epoch losses {np.round(losses[[0, 4, 9, 19, 29]], 5)}")
     return net, losses
 
 
-def test_trained_closure_against_micro_solve(trained):
-    """Held-out cavity at eps = 3e-3 (between training values, another seed): macro rel-L1
-    after 100 steps against the FP64 full micro solve (the reference) <= 1e-2 with most cells on
-    the closure and below the error of the Navier-Stokes-Fourier closure; on held-out
-    snapshots, the network's heat flux (the moment that closes the macro system) closer to
-    the micro solve than the NSF closure (the method without the network), its stress no
-    further than the NSF stress (within 10 %)."""
+@pytest.mark.parametrize("eps", [1e-3, 3e-3, 1e-2])
+def test_trained_closure_against_micro_solve(trained, eps):
+    """Held-out cavity (another seed than the training runs) at 256^2 x 32^2: the closure
+    form runs its initial layer with every cell solved (40 steps), then 100 steps with the
+    closure; macro rel-L1 against the FP64 full micro solve over the same 140 steps at
+    least 30 % below that of the Navier-Stokes-Fourier closure (the method without the
+    network) run the same way, with at least 90 % of the cells on the closure.  On
+    held-out snapshots of the same run, the network's heat flux, stress and traceless
+    third moments each at least 20 % closer to the micro solve than the NSF values."""
     torch = _torch()
     B = _B()
+    from paper_2509_21832_amd import closure as CL
     net, losses = trained
     assert losses[-1] < 0.5 * losses[0]
-    p, Q, G = W.cavity2d(seed=40, nx=64, ny=64, nv=16, eps=3e-3, amp=0.2)
+    p, Q, G = W.cavity2d(seed=41, eps=eps)
     steps = 100
     with B.Solver(p, Q, G) as s:                                    # reference: FP64 full solve
-        s.step(steps)
+        s.step(CL.INITIAL_LAYER + steps)
         Qref = s.moments()
     res = {}
     for name, closure in (("net", net), ("nsf", None)):
         with B.Solver(dict(p, precision="closure"), Q, G) as s:
-            s.closure_attach(closure, 0.05, residual=2 if closure is not None else 0)
+            CL.start(s, closure)
+            s.closure_cells()
             s.step(steps)
-            Qc = s.moments()
             ncl, _ = s.closure_cells()
-        res[name] = (rel_l1(Qc, Qref), ncl / (steps * p["nx"] * p["ny"]))
-    with B.Solver(dict(p, precision="mixed"), Q, G) as s:
-        s.step(steps)
-        emix = rel_l1(s.moments(), Qref)
-    log(f"[reference] macro rel-L1 vs FP64 full solve: net {res['net'][0]:.3e} (closure fraction "
-        f"{res['net'][1]:.2f}), NSF {res['nsf'][0]:.3e}, FP32-storage full solve {emix:.3e}")
+            res[name] = (rel_l1(s.moments(), Qref), ncl / (steps * p["nx"] * p["ny"]))
+    gain = 1.0 - res["net"][0] / res["nsf"][0]
+    log(f"[reference eps={eps:g}] macro rel-L1 vs FP64 full solve: net {res['net'][0]:.3e} (closure fraction "
+        f"{res['net'][1]:.2f}), NSF {res['nsf'][0]:.3e}; gain {gain:.2f}")
     assert res["net"][0] <= 1e-2
-    assert res["net"][1] >= 0.5
-    assert res["net"][0] < res["nsf"][0]
+    assert res["net"][1] >= 0.9
+    assert gain >= 0.30
 
-    # offline, on held-out snapshots after the initial relaxation: raw targets of the micro
+    # offline, on held-out snapshots after the initial layer: raw targets of the micro
     # solve vs NSF and vs NSF + network correction
-    Xh, Yh = _snapshots(B, torch, [(p, Q, G)], steps=100, first=40, every=5, kn_max=0.05, cap=500_000,
-                        residual=0)
-    Xr, Yr = _snapshots(B, torch, [(p, Q, G)], steps=100, first=40, every=5, kn_max=0.05, cap=500_000,
-                        residual=1)
+    kw = dict(steps=CL.INITIAL_LAYER + steps, first=CL.INITIAL_LAYER, every=10, kn_max=CL.KN_MAX, cap=2_000_000)
+    Xh, Yh = _snapshots(B, torch, [(p, Q, G)], residual=0, **kw)
+    Xr, Yr = _snapshots(B, torch, [(p, Q, G)], residual=1, **kw)
     Yh = Yh.cpu().numpy().astype(np.float64)
     nsf = Yh - Yr.cpu().numpy()                      # the NSF values the kernels used
     Yn = nsf + p["eps"] * net.forward(Xh).cpu().numpy()
     rms = lambda a: float(np.sqrt(np.mean(a ** 2)))  # noqa: E731
-    e_q = (rms(Yn[:, :2] - Yh[:, :2]), rms(nsf[:, :2] - Yh[:, :2]))
-    e_s = (rms(Yn[:, 2:5] - Yh[:, 2:5]), rms(nsf[:, 2:5] - Yh[:, 2:5]))
-    e_t = (rms(Yn[:, 5:] - Yh[:, 5:]), rms(nsf[:, 5:] - Yh[:, 5:]))
-    log(f"[gain] held-out RMS error, heat flux: net {e_q[0]:.4e} NSF {e_q[1]:.4e} (target rms "
-        f"{rms(Yh[:, :2]):.3e}); stress: net {e_s[0]:.4e} NSF {e_s[1]:.4e} (target rms {rms(Yh[:, 2:5]):.3e}); "
-        f"traceless third moments: net {e_t[0]:.4e} NSF {e_t[1]:.4e}")
-    Fh = Xh.cpu().numpy().astype(np.float64)
-    p_ = Fh[:, 0] * Fh[:, 3]
-    Sc = np.stack([Fh[:, 4] - p_, Fh[:, 5], Fh[:, 6] - p_], 1) / p["eps"]
-    log(f"[gain] stress of the macro state (P - p I) / eps: RMS error {rms(Sc - Yh[:, 2:5]):.4e}")
-    assert e_q[0] < 0.8 * e_q[1]
-    assert e_s[0] <= 1.1 * e_s[1]
+    e = {k: (rms(Yn[:, a:b] - Yh[:, a:b]), rms(nsf[:, a:b] - Yh[:, a:b]), rms(Yh[:, a:b]))
+         for k, (a, b) in (("heat flux", (0, 2)), ("stress", (2, 5)), ("traceless third moments", (5, 7)))}
+    log(f"[gain eps={eps:g}] held-out RMS error, " + "; ".join(
+        f"{k}: net {v[0]:.3e} NSF {v[1]:.3e} (target rms {v[2]:.3e})" for k, v in e.items()))
+    for k, v in e.items():
+        assert v[0] <= 0.8 * v[1], k
 
 
 def test_trained_closure_speedup_at_full_size(trained):
     """256^2 cells x 32^2 velocity nodes, eps = 3e-3: the closure form against the
     FP32-storage full micro solve on the same GPU (wall time of 30 synchronised steps),
-    its macro error against the FP64 full solve after 30 steps."""
+    its macro error against the FP64 full solve after its initial layer and 30 steps."""
     import time
     B = _B()
+    from paper_2509_21832_amd import closure as CL
     net, _ = trained
     p, Q, G = W.cavity2d(seed=41, eps=3e-3)
     steps = 30
     with B.Solver(p, Q, G) as s:
-        s.step(steps)
+        s.step(CL.INITIAL_LAYER + steps)
         Qref = s.moments()
     times, errs = {}, {}
     for form in ("mixed", "closure"):
         with B.Solver(dict(p, precision=form), Q, G) as s:
             if form == "closure":
-                s.closure_attach(net, 0.05, residual=2)
+                CL.start(s, net)
+                s.closure_cells()
+            else:
+                s.step(CL.INITIAL_LAYER)
             s.step(steps)
             errs[form] = rel_l1(s.moments(), Qref)
             s.step(3)

@@ -9,7 +9,7 @@ import pytest
 import mm_workloads as W
 import oracle
 
-NF, NH, NO = 21, 64, 7
+NF, NH, NO = 30, 64, 7
 
 
 def _problem(nx=12, ny=10, nv=16, V=8.0, bc=None, eps=0.01, **kw):
@@ -209,10 +209,39 @@ def test_features_of_linear_fields_are_exact():
     gu = np.sqrt(0.2 ** 2 + 0.05 ** 2 + 0.1 ** 2 + 0.1 ** 2) / np.sqrt(T)
     ref = p["eps"] * np.sqrt(T) / (p["tau_coef"] * rho) * np.maximum(np.maximum(gr, gT), gu)
     assert np.allclose(kn.reshape(p["ny"], p["nx"]), ref, rtol=1e-9)
+    # the local mean free path eps sqrt(T) / tau, tau = tau_coef rho
+    assert np.allclose(F[..., 21], p["eps"] * np.sqrt(T) / (p["tau_coef"] * rho), rtol=1e-13)
+    # second differences of linear fields vanish; next to the walls they are set to zero
+    scale = max(p["nx"] / (p["x"][1] - p["x"][0]), p["ny"] / (p["y"][1] - p["y"][0])) ** 2
+    assert np.abs(F[..., 22:30]).max() <= 1e-12 * scale
+    assert np.all(F[:, 0, 22:26] == 0) and np.all(F[:, -1, 22:26] == 0)
+    assert np.all(F[0, :, 26:30] == 0) and np.all(F[-1, :, 26:30] == 0)
     # walls on all four sides: the outer ring is always micro
     e = edge.reshape(p["ny"], p["nx"])
     assert e[0].all() and e[-1].all() and e[:, 0].all() and e[:, -1].all()
     assert not e[1:-1, 1:-1].any()
+
+
+def test_features_second_differences_of_quadratic_fields_are_exact():
+    """The central second difference is exact for quadratics: d2/dx2 and d2/dy2 of
+    (rho, u1, u2, T) in the interior, zero where a neighbour is missing."""
+    p = _problem(nx=9, ny=8)
+    x = W.centres(*p["x"], p["nx"])
+    y = W.centres(*p["y"], p["ny"])
+    X, Y = np.meshgrid(x, y)
+    c = {"rho": (1.0, 0.3, -0.2), "u1": (0.1, 0.4, 0.25), "u2": (-0.05, -0.3, 0.2), "T": (1.0, 0.15, 0.35)}
+    f = {k: a + b * X * X + d * Y * Y + 0.1 * X * Y for k, (a, b, d) in c.items()}
+    Q = W.conserved2d(f["rho"], f["u1"], f["u2"], f["T"])
+    F, kn, edge = oracle.features2d(p, Q.reshape(-1))
+    F = F.reshape(p["ny"], p["nx"], NF)
+    for a, k in enumerate(("rho", "u1", "u2", "T")):
+        assert np.allclose(F[1:-1, 1:-1, 22 + a], 2 * c[k][1], rtol=1e-8), k
+        assert np.allclose(F[1:-1, 1:-1, 26 + a], 2 * c[k][2], rtol=1e-8), k
+        assert np.all(F[:, 0, 22 + a] == 0) and np.all(F[:, -1, 22 + a] == 0)
+        assert np.all(F[0, :, 26 + a] == 0) and np.all(F[-1, :, 26 + a] == 0)
+    # the mixed term x y adds nothing to either second difference; first differences
+    # stay the centred ones: d rho / dx = 2 b x + 0.1 y exactly for a quadratic
+    assert np.allclose(F[1:-1, 1:-1, 7], (2 * 0.3 * X + 0.1 * Y)[1:-1, 1:-1], rtol=1e-9, atol=1e-12)
 
 
 def test_features_periodic_wrap_second_order():
@@ -226,9 +255,12 @@ def test_features_periodic_wrap_second_order():
         F, kn, edge = oracle.features2d(p, Q.reshape(-1))
         F = F.reshape(n, n, NF)
         exact = 0.2 * 2 * np.pi * np.cos(2 * np.pi * X) * np.cos(2 * np.pi * Y)
-        errs.append(np.abs(F[..., 7] - exact).max())
+        exact2 = -0.2 * (2 * np.pi) ** 2 * np.sin(2 * np.pi * X) * np.cos(2 * np.pi * Y)
+        errs.append((np.abs(F[..., 7] - exact).max(), np.abs(F[..., 22] - exact2).max(),
+                     np.abs(F[..., 26] - exact2).max()))
         assert not edge.any()
-    assert errs[1] < errs[0] / 3.5     # second order including the wrapped cells
+    for k in range(3):                 # second order including the wrapped cells
+        assert errs[1][k] < errs[0][k] / 3.5, (k, errs)
 
 
 # ------------------------------------------------------------------ closure moments
