@@ -62,29 +62,34 @@ __device__ __forceinline__ f32x16 zero16()
     return z;
 }
 
-// erf without branches: erf(t) = 1 - exp(-t P(t)) for t = |x| >= 0 (odd extension), P
-// the degree-9 least-squares Chebyshev fit of -log(erfc(t)) / t on [0, 4] (fit_erf.py;
-// beyond 4 the fit is held at 4 and erf rounds to 1).  Within 4e-7 relative and 8e-8
-// absolute of erf, far below the bf16 rounding of the activations; the library erff
-// takes a divergent branch at |x| = 1 and costs about twice as many instructions.
-__device__ __forceinline__ float erf_fit(float x)
+// GELU without branches.  With a = |z|, erfc(a / sqrt 2) = 2^(-a Q(a)), Q the degree-5
+// least-squares Chebyshev fit of -log2(erfc(a / sqrt 2)) / a on [0, 4 sqrt 2]
+// (fit_erf.py; held at 4 sqrt 2 beyond, where erfc is below 2e-8).  For either sign,
+//   z Phi(z) = max(z, 0) - a 2^(-a Q(a) - 1),
+// within 2e-6 of the exact GELU, far below the bf16 rounding of the activations; the
+// library erff takes a divergent branch at |x| = 1 and costs several times as much.
+__device__ __forceinline__ float half_erfc(float a)     // erfc(a / sqrt 2) / 2, a >= 0
 {
-    constexpr float c[10] = {1.128379464e+00f, 6.366103888e-01f, 1.028422564e-01f, -1.933863945e-02f,
-                             1.000994671e-04f, 1.479538158e-03f, -5.703387433e-04f, 1.147649891e-04f,
-                             -1.261705529e-05f, 5.963064496e-07f};
-    const float t = fabsf(x), tc = fminf(t, 4.0f);
-    float p = c[9];
+    constexpr float c[6] = {1.151109576e+00f, 4.590861499e-01f, 5.302880332e-02f, -7.888867520e-03f,
+                            7.298647542e-04f, -3.054398985e-05f};
+    const float ac = fminf(a, 5.65685424949238f);
+    float q = c[5];
 #pragma unroll
-    for (int k = 8; k >= 0; --k) p = fmaf(p, tc, c[k]);
-    const float e = __builtin_amdgcn_exp2f(-1.44269504088896341f * t * p);
-    return copysignf(1.0f - e, x);
+    for (int k = 4; k >= 0; --k) q = fmaf(q, ac, c[k]);
+    return __builtin_amdgcn_exp2f(-fmaf(a, q, 1.0f));
 }
 
-__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erf_fit(z * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu(float z)
+{
+    const float a = fabsf(z);
+    return fmaf(-a, half_erfc(a), fmaxf(z, 0.0f));
+}
+
 __device__ __forceinline__ float gelu_d(float z)
 {
-    return 0.5f * (1.0f + erf_fit(z * 0.70710678118654752f)) +
-           z * __builtin_amdgcn_exp2f(-0.72134752044448170f * z * z) * 0.39894228040143268f;
+    const float he = half_erfc(fabsf(z));
+    const float Phi = z >= 0.0f ? 1.0f - he : he;
+    return Phi + z * __builtin_amdgcn_exp2f(-0.72134752044448170f * z * z) * 0.39894228040143268f;
 }
 
 // Weights of the network in LDS (bf16): W1 [64][32] (inputs 30, 31 zero),
@@ -577,19 +582,16 @@ __device__ __forceinline__ void cell_features(const double *__restrict__ Q, cons
     prim(Q + 6 * (size_t)(jm * P.nx + i), wym);
     prim(Q + 6 * (size_t)(jp * P.nx + i), wyp);
     double f[NF];
-    // reciprocal spacings: one division each instead of one per feature
+    // A missing neighbour was loaded from the cell itself (wxp = w0 when !hp, ...),
+    // so wxp - wxm is the centred difference times 2 dx, the one-sided one times dx,
+    // or zero: one scale per direction picks the divisor.
     const double idx = 1.0 / P.dx, idy = 1.0 / P.dy;
+    const double sx = (hm && hp) ? 0.5 * idx : idx, sy = (vm && vp) ? 0.5 * idy : idy;
 #pragma unroll
     for (int a = 0; a < 7; ++a) {
         f[a] = w0[a];
-        f[7 + a] = (hm && hp) ? (wxp[a] - wxm[a]) * (0.5 * idx)
-                   : hp        ? (wxp[a] - w0[a]) * idx
-                   : hm        ? (w0[a] - wxm[a]) * idx
-                               : 0.0;
-        f[14 + a] = (vm && vp) ? (wyp[a] - wym[a]) * (0.5 * idy)
-                    : vp        ? (wyp[a] - w0[a]) * idy
-                    : vm        ? (w0[a] - wym[a]) * idy
-                                : 0.0;
+        f[7 + a] = (wxp[a] - wxm[a]) * sx;
+        f[14 + a] = (wyp[a] - wym[a]) * sy;
     }
     // the local mean free path eps sqrt(T) / tau, and the second differences of
     // (rho, u1, u2, T) along x and y (zero next to a side that is not periodic:
@@ -597,11 +599,11 @@ __device__ __forceinline__ void cell_features(const double *__restrict__ Q, cons
     const double rho = w0[0], T = w0[3];
     const double lam = P.eps * sqrt(T) / tau_of(P, rho, rho * T, T);
     f[21] = lam;
-    const double idx2 = idx * idx, idy2 = idy * idy;
+    const double sxx = (hm && hp) ? idx * idx : 0.0, syy = (vm && vp) ? idy * idy : 0.0;
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
-        f[22 + a] = (hm && hp) ? (wxp[a] - 2.0 * w0[a] + wxm[a]) * idx2 : 0.0;
-        f[26 + a] = (vm && vp) ? (wyp[a] - 2.0 * w0[a] + wym[a]) * idy2 : 0.0;
+        f[22 + a] = (wxp[a] - 2.0 * w0[a] + wxm[a]) * sxx;
+        f[26 + a] = (wyp[a] - 2.0 * w0[a] + wym[a]) * syy;
     }
 #pragma unroll
     for (int a = 0; a < NF; ++a) fo[a] = (float)f[a];
@@ -735,11 +737,9 @@ __global__ __launch_bounds__(256) void k_cells2d(const double *__restrict__ Q, P
     if (!NET || residual) {
         double b[NO];
         nsf_out(f, P, b);
+        // outputs 4 g + v: a select per slot, not an index that depends on the lane
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int o = 4 * g + v;
-            o4[v] = o < NO ? b[o < NO ? o : 0] : 0.0;
-        }
+        for (int v = 0; v < 4; ++v) o4[v] = g ? (4 + v < NO ? b[4 + v < NO ? 4 + v : 0] : 0.0) : b[v];
     }
     if constexpr (NET) {
         MlpRegs R;
@@ -790,15 +790,21 @@ __global__ __launch_bounds__(256) void k_cells2d(const double *__restrict__ Q, P
 
 // Cells whose micro part a solved cell needs (its 3 x 3 block) but whose G^n is
 // not current go to a list; the validity of G^{n+1} (= solved) goes to
-// valid_next.  One thread per cell.
-__global__ void k_need2d(const uint8_t *__restrict__ cls, const uint8_t *__restrict__ valid,
+// valid_next.  One thread per cell, NEED_BLOCK cells per workgroup and one list
+// atomic per workgroup: the cells next to the walls all need rebuilding, and an
+// atomic per wavefront on the one counter serialised about 500 of them.
+constexpr int NEED_BLOCK = 1024;
+
+__global__ __launch_bounds__(NEED_BLOCK) void k_need2d(const uint8_t *__restrict__ cls, const uint8_t *__restrict__ valid,
                          uint8_t *__restrict__ valid_next, int *__restrict__ list, int *__restrict__ nrebuild,
                          Params P)
 {
+    __shared__ int wcount[NEED_BLOCK / 64], wbase[NEED_BLOCK / 64];
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= P.nx * P.ny) return;
-    const int lane = threadIdx.x & 63;
-    const int i = c % P.nx, j = c / P.nx;
+    const bool in_grid = c < P.nx * P.ny;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int cc = in_grid ? c : 0;
+    const int i = cc % P.nx, j = cc / P.nx;
     const bool px = P.bc[0].kind == BC_PERIODIC, py = P.bc[2].kind == BC_PERIODIC;
     bool need = false;
 #pragma unroll
@@ -817,18 +823,24 @@ __global__ void k_need2d(const uint8_t *__restrict__ cls, const uint8_t *__restr
             }
             if (in && cls[jj * P.nx + ii]) need = true;
         }
-    valid_next[c] = cls[c];
-    // one atomic per wavefront: the first listed lane reserves the wavefront's
-    // slots, each lane takes its rank among the listed lanes
-    const bool add = need && !valid[c];
+    if (in_grid) valid_next[c] = cls[c];
+    // the workgroup's listed cells: wavefront counts, one atomic reserves the
+    // workgroup's slots, each lane takes its wavefront's offset plus its rank
+    const bool add = in_grid && need && !valid[c];
     const uint64_t m = __ballot(add);
-    if (m) {
-        const int lead = __ffsll((unsigned long long)m) - 1;
-        int base = 0;
-        if (lane == lead) base = atomicAdd(nrebuild, __popcll(m));
-        base = __shfl(base, lead, 64);
-        if (add) list[base + __popcll(m & ((1ull << lane) - 1))] = c;
+    if (lane == 0) wcount[wv] = (int)__popcll(m);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int tot = 0;
+        for (int w = 0; w < NEED_BLOCK / 64; ++w) {
+            wbase[w] = tot;
+            tot += wcount[w];
+        }
+        const int base = tot ? atomicAdd(nrebuild, tot) : 0;
+        for (int w = 0; w < NEED_BLOCK / 64; ++w) wbase[w] += base;
     }
+    __syncthreads();
+    if (add) list[wbase[wv] + __popcll(m & ((1ull << lane) - 1))] = c;
 }
 
 // Rebuild the listed cells from their (q, S, t) / eps:
@@ -1077,7 +1089,8 @@ void launch_rebuild2d(void *G, int g_bytes, const double *rec, const float *out,
                       hipStream_t st)
 {
     const int n = P.nx * P.ny;
-    hipLaunchKernelGGL(k_need2d, dim3((n + 255) / 256), dim3(256), 0, st, cls, valid, valid_next, list, nrebuild, P);
+    hipLaunchKernelGGL(k_need2d, dim3((n + NEED_BLOCK - 1) / NEED_BLOCK), dim3(NEED_BLOCK), 0, st, cls, valid,
+                       valid_next, list, nrebuild, P);
     int blocks = (n + 3) / 4;
     if (blocks > 1024) blocks = 1024;
     if (g_bytes == 8)
