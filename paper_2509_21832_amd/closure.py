@@ -38,16 +38,18 @@ def training_runs(eps_list=(1e-3, 2e-3, 5e-3, 1e-2), nx=256, nv=32, seed0=20):
 
 def snapshots(runs, steps=160, first=INITIAL_LAYER, every=12, kn_max=KN_TRAIN, residual=RESIDUAL,
               cap=12_000_000):
-    """Training rows (device tensors X [n, 30], Y [n, 7]) from full micro solves with g in
-    FP32: a snapshot every `every` steps from step `first` on (the first steps relax g from
-    its zero initial value)."""
+    """Training rows (device tensors X [n, 30], Y [n, 7]) from FP64 full micro solves: a
+    snapshot every `every` steps from step `first` on (the first steps relax g from its zero
+    initial value).  FP64 rather than g in FP32: the residual targets divide the micro
+    solve's moments by eps twice, which lifts FP32 storage noise into the targets (measured:
+    the network trained on FP32-storage runs gains 4 points less at eps = 1e-2)."""
     import torch
     from . import binding as B
     X = torch.zeros((cap, B.N_FEAT), dtype=torch.float32, device="cuda")
     Y = torch.zeros((cap, B.N_OUT), dtype=torch.float32, device="cuda")
     count = 0
     for p, Q, G in runs:
-        with B.Solver(dict(p, precision="mixed"), Q, G) as s:
+        with B.Solver(dict(p, precision="fp64"), Q, G) as s:
             for k in range(steps):
                 if k >= first and (k - first) % every == 0:
                     count = s.closure_snapshot(kn_max, X, Y, count, residual=residual)
