@@ -120,10 +120,8 @@ struct PassLK {
         }
     };
     // start values (e(0), r(0)) of a Gaussian's recurrence: the x-sweep of row j+1
-    // makes the Maxwellian's, and in FP64 the finish of that row one step later
-    // reuses them (timed: FP64 faster by a few percent; the FP32 instance, which
-    // runs two wavefronts per SIMD, slower, so it computes them again)
-    static constexpr bool MQ_RING = sizeof(TC) == 8;
+    // makes the Maxwellian's, and the finish of that row one step later reuses them
+    // (timed: faster by a few percent in FP64 and by 1.8% with g in FP32)
     struct GqS {
         double e, r;
     };
@@ -277,7 +275,7 @@ struct PassLK {
         sum_proj(s, R, o);
         const TC c2 = (TC)o[2], c3 = (TC)o[3], Kz = (TC)(o[0] + (o[1] + o[3] * v1d) * v1d), dt = (TC)P->dt;
         const auto ws = row(Gn, jr);
-        Gq mq = MQ_RING ? Gq{ms.e, ms.r, R[R_KM]} : maxw_q(R);
+        Gq mq{ms.e, ms.r, R[R_KM]};
         TC w = v2b;
 #pragma unroll
         for (int m = 0; m < NPT; ++m, w += h) {
@@ -316,7 +314,7 @@ struct PassLK {
         const double a = v1d - R[R_U1];             // w1 of this lane
         TC C[4];
         ghat_cubic(R, a, C);
-        const Gq mq0 = MQ_RING ? Gq{ms.e, ms.r, R[R_KM]} : maxw_q(R);
+        const Gq mq0{ms.e, ms.r, R[R_KM]};
         Gq gq = es_q(R);
         const double iepsd = R[R_IEPS], rbd = R[R_B];
         const TC u2 = (TC)u2d;
