@@ -201,6 +201,61 @@ def test_closure_rebuild_vs_oracle(proj):
     assert np.abs(keep - Gc).max() <= 1e-6 * np.abs(Gc).max()
 
 
+# ---------------------------------------------------------------- training snapshots
+
+@pytest.mark.parametrize("residual", [0, 1, 2])
+def test_closure_snapshot_vs_oracle(residual):
+    """mm_closure_snapshot on an FP64 context: features of Q^n and one step, then the rows of
+    the cells with kn <= kn_max not next to a wall, in cell order, with targets
+    (q1, q2, S11, S12, S22, t1, t2) / eps of g^{n+1} (w = v - u^n): q and t from the oracle's
+    H, S = dv sum w w^T g; minus the NSF values (residual 1), divided by eps (residual 2)."""
+    torch = _torch()
+    B = _B()
+    p, Q, G = _cavity(seed=21, nx=13, ny=11, nv=16, eps=0.02)
+    Q, G = _developed(p, Q, G, 4)
+    F, kn, edge = oracle.features2d(p, Q)
+    # the NSF baseline from the features as the kernels hold them (FP32)
+    nsf = np.array([np.concatenate(oracle.nsf_closure(p, f)) for f in F.astype(np.float32).astype(np.float64)])
+    ks = np.sort(kn[~edge])
+    kn_max = float(0.5 * (ks[len(ks) // 2] + ks[len(ks) // 2 + 1]))   # between two cells' values
+    sel = (~edge) & (kn <= kn_max)
+    cap = p["nx"] * p["ny"] + 5
+    X = torch.zeros((cap, NF), dtype=torch.float32, device="cuda")
+    Y = torch.zeros((cap, NO), dtype=torch.float32, device="cuda")
+    with B.Solver(p, Q, G) as s:
+        n = s.closure_snapshot(kn_max, X, Y, 2, residual=residual)      # appended after two rows
+    Xg, Yg = X.cpu().numpy(), Y.cpu().numpy()
+    # the oracle: one step, H and the stress of g^{n+1} about u^n
+    Qo, Go, Ho = oracle.run(p, Q.reshape(-1), G.reshape(-1), 1)
+    ncell = p["nx"] * p["ny"]
+    Go = Go.reshape(ncell, p["nv2"], p["nv1"])
+    Ho = Ho.reshape(ncell, 4)
+    v1 = W.centres(*p["v1"], p["nv1"])
+    v2 = W.centres(*p["v2"], p["nv2"])
+    V1, V2 = np.meshgrid(v1, v2)
+    dv = (v1[1] - v1[0]) * (v2[1] - v2[0])
+    Qc = Q.reshape(ncell, 6)
+    eps = p["eps"]
+    T = np.zeros((ncell, NO))
+    for c in range(ncell):
+        w1, w2 = V1 - Qc[c, 1] / Qc[c, 0], V2 - Qc[c, 2] / Qc[c, 0]
+        g, h = Go[c], Ho[c]
+        T[c] = [0.5 * (h[0] + h[2]) / eps, 0.5 * (h[1] + h[3]) / eps, dv * np.sum(w1 * w1 * g),
+                dv * np.sum(w1 * w2 * g), dv * np.sum(w2 * w2 * g), (h[0] - 3 * h[2]) / eps, (3 * h[1] - h[3]) / eps]
+    if residual:
+        T = (T - nsf) / (eps if residual == 2 else 1.0)
+    rows = np.nonzero(sel)[0]
+    log(f"[snapshot r={residual}] {len(rows)} rows of {ncell} cells (kn_max {kn_max:.3e})")
+    assert n == 2 + len(rows)
+    assert np.all(Xg[:2] == 0) and np.all(Yg[:2] == 0) and np.all(Xg[n:] == 0)
+    fs = np.abs(F).mean(0) + 1e-30
+    assert np.max(np.abs(Xg[2:n] - F[rows]) / (np.abs(F[rows]) + fs)) <= 1e-6
+    ys = np.abs(T[rows]).mean(0) + 1e-30
+    ey = np.abs(Yg[2:n] - T[rows]) / (np.abs(T[rows]) + ys)
+    log(f"[snapshot r={residual}] targets max rel {ey.max():.3e}")
+    assert ey.max() <= 1e-5
+
+
 # ---------------------------------------------------------------- hybrid steps
 
 def test_closure_with_all_cells_solved_equals_mixed():
