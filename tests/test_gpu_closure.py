@@ -148,6 +148,28 @@ def test_mlp_grad_vs_oracle():
     assert max(eb.values()) <= 3e-3
 
 
+def test_mlp_fit_norm_mean_and_std():
+    """mm_mlp_fit_norm: population mean and standard deviation of every feature and target
+    column (FP64 sums); a constant column gets the floor 1e-6 x its root mean square."""
+    torch = _torch()
+    B = _B()
+    rng = np.random.default_rng(12)
+    n = 3001
+    X = (rng.standard_normal((n, NF)) * rng.uniform(0.01, 100.0, NF) + rng.standard_normal(NF) * 10).astype(np.float32)
+    Y = (rng.standard_normal((n, NO)) * rng.uniform(0.1, 5.0, NO) + rng.standard_normal(NO)).astype(np.float32)
+    X[:, 3] = 2.5                     # a constant feature
+    net = B.Mlp(seed=0)
+    net.fit_norm(torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda())
+    _, N = net.get()
+    X64, Y64 = X.astype(np.float64), Y.astype(np.float64)
+    sx, sy = X64.std(0), Y64.std(0)
+    sx[3] = 1e-6 * 2.5
+    ref = np.concatenate([X64.mean(0), sx, Y64.mean(0), sy])
+    err = np.abs(N - ref) / np.abs(ref)
+    log(f"[fit_norm] max rel {err.max():.3e}")
+    assert err.max() <= 1e-5
+
+
 def test_mlp_train_reduces_loss():
     """Adam on the GPU fits a smooth map of real features."""
     torch = _torch()
