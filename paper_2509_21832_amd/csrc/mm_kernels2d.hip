@@ -87,18 +87,22 @@ __device__ __forceinline__ void spd_inverse4(const double A[4][4], double scale,
 
 // S[q] = sum_k w_k^q exp(-w_k^2 i2T), q = 0..4, over the nodes w_k = w0 + (k + 1/2) h,
 // k < n.  The Gaussian follows e(k+1) = e(k) r(k), r(k+1) = r(k) kappa (its
-// exponent is quadratic in k), restarted from a direct exponential every 8
-// nodes so the relative error stays within a few tens of ulps.  Within a chunk
-// of 8 nodes the sums run over the centred index t = k - 7/2 (exact constants):
-// T_p = sum t^p e, and S_q gains sum_p C(q, p) wc^(q-p) h^p T_p with wc the
-// chunk's centre.
+// exponent is quadratic in k) from one pair of exponentials at the first node:
+// the range rule keeps every node's exponent within EXP_RANGE, so no value
+// leaves the range of FP64, and the relative error grows like k^2 / 2 ulps
+// (below 2e-13 of each moment's scale for 64 nodes, as small as restarting
+// the recurrence every 8 nodes, which cost two exponentials per chunk).  Within
+// a chunk of 8 nodes the sums run over the centred index t = k - 7/2 (exact
+// constants): T_p = sum t^p e, and S_q gains sum_p C(q, p) wc^(q-p) h^p T_p with
+// wc the chunk's centre.
 __device__ inline void gauss_sums(double w0, double h, int n, double i2T, double S[5])
 {
     const double kap = exp(-2.0 * h * h * i2T);
     const double h2 = h * h, h3 = h2 * h, h4 = h2 * h2;
+    const double wf = w0 + 0.5 * h;
+    double e = exp(-wf * wf * i2T), r = exp(-(2.0 * wf + h) * h * i2T);
     for (int k0 = 0; k0 < n; k0 += 8) {
         const double wb = w0 + (k0 + 0.5) * h;
-        double e = exp(-wb * wb * i2T), r = exp(-(2.0 * wb + h) * h * i2T);
         const int kn = n - k0 < 8 ? n - k0 : 8;
         double T[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
@@ -151,12 +155,14 @@ __global__ __launch_bounds__(4 * PREP_CELLS) void k_prep2d(const double *__restr
     if (c < ncell) {
         const int i = c % P.nx, j = c / P.nx;
         const CellPrim s = prim_of(Q + 6 * (size_t)c);
-        const double i2T = 1.0 / (2.0 * s.T);
+        const double iT = 1.0 / s.T, i2T = 0.5 * iT;   // 0.5 / T exactly as 1 / (2T)
         const double h = lk_step(P.nv1, P.nv2, P.dv2);
         if (role == 0) {
-            const double S11 = (1.0 - P.nu) * s.T + P.nu * s.P11 / s.rho;
-            const double S12 = P.nu * s.P12 / s.rho;
-            const double S22 = (1.0 - P.nu) * s.T + P.nu * s.P22 / s.rho;
+            // one reciprocal each of rho, 2 det and sqrt(det) instead of eight divisions
+            const double nir = P.nu / s.rho;
+            const double S11 = (1.0 - P.nu) * s.T + nir * s.P11;
+            const double S12 = nir * s.P12;
+            const double S22 = (1.0 - P.nu) * s.T + nir * s.P22;
             const double det = S11 * S22 - S12 * S12;
             if (!(s.rho > 0.0) || !(s.T > 0.0) || !(det > 0.0) || !(s.P11 > 0.0) || !(s.P22 > 0.0) ||
                 !isfinite(s.u1) || !isfinite(s.u2) || !isfinite(s.P12))
@@ -165,12 +171,13 @@ __global__ __launch_bounds__(4 * PREP_CELLS) void k_prep2d(const double *__restr
             R[R_U1] = s.u1;
             R[R_U2] = s.u2;
             R[R_T] = s.T;
-            R[R_GPRE] = s.rho / (2.0 * MM_PI * sqrt(det));
-            const double qa = S22 / (2.0 * det), qb = -S12 / (2.0 * det), qc = S11 / (2.0 * det);
+            const double isd = 1.0 / sqrt(det), i2d = 0.5 / det;
+            R[R_GPRE] = s.rho * isd * (0.5 / MM_PI);
+            const double qa = S22 * i2d, qb = -S12 * i2d, qc = S11 * i2d;
             R[R_QA] = qa;
             R[R_QB] = qb;
             R[R_QC] = qc;
-            R[R_LG] = log(s.T / sqrt(det));
+            R[R_LG] = log(s.T * isd);
             R[R_DA] = qa - i2T;
             R[R_DC] = qc - i2T;
             R[R_KG] = exp(-2.0 * qc * h * h);
@@ -179,15 +186,17 @@ __global__ __launch_bounds__(4 * PREP_CELLS) void k_prep2d(const double *__restr
         } else if (role == 1) {
             for (int q = R_PM + 10; q < REC; ++q) R[q] = 0.0;    // unused tail of the record
             const double tau = tau_of(P, s.rho, s.p, s.T);
-            R[R_RST] = 1.0 / sqrt(s.T);
-            R[R_MPRE] = s.rho / (2.0 * MM_PI * s.T);
+            // the reciprocals of T (above), tau, eps and eps + dt tau serve every quotient
+            const double iw = 1.0 / (P.eps + P.dt * tau);
+            R[R_RST] = sqrt(iT);
+            R[R_MPRE] = s.rho * iT * (0.5 / MM_PI);
             R[R_I2T] = i2T;
             R[R_TAU] = tau;
             R[R_ITAU] = 1.0 / tau;
             R[R_IEPS] = 1.0 / P.eps;
-            R[R_A] = P.eps / (P.eps + P.dt * tau);
-            R[R_B] = P.dt * tau / (P.eps + P.dt * tau);
-            R[R_IT] = 1.0 / s.T;
+            R[R_A] = P.eps * iw;
+            R[R_B] = P.dt * tau * iw;
+            R[R_IT] = iT;
             R[R_KM] = exp(-2.0 * h * h * i2T);
             // Gram_ab = dA sum phi_a phi_b M from separable 1D sums: M = c0 e1(k) e2(l)
             if (discrete) {
