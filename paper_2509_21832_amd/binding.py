@@ -341,7 +341,7 @@ class Solver:
     # ---- closure form
     def closure_attach(self, net, kn_max, residual=0):
         """net: an Mlp, or None for the Navier-Stokes-Fourier closure; residual: 0 the network
-        predicts (q, S) / eps, 1 its correction to the NSF values, 2 that correction / eps."""
+        predicts (q, S, t) / eps, 1 its correction to the NSF values, 2 that correction / eps."""
         self._net = net       # the context keeps the network by pointer
         _check(_lib.mm_closure_attach(self._ctx, net._h if net is not None else None, float(kn_max),
                                       int(residual)), "mm_closure_attach")

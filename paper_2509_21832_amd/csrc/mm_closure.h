@@ -33,7 +33,7 @@ struct MlpDevMut {
 
 void launch_features2d(const double *Q, const Params &P, float *feat, float *kn, uint8_t *edge, hipStream_t st);
 // the closure part of a step in one kernel: features, indicator, classes, the
-// closure values out = (q, S) / eps (NSF, network, or NSF plus scale x network
+// closure values out = (q, S, t) / eps (NSF, network, or NSF plus scale x network
 // with residual) and H of the closure cells; empties the rebuild list
 void launch_cells2d(const double *Q, const Params &P, const MlpDev *w, int residual, float kn_max, uint8_t *cls,
                     float *out, double *H, unsigned long long *nclosure, int *nrebuild, hipStream_t st);
