@@ -45,13 +45,15 @@ struct PassLK {
     const double *__restrict__ rec;
     const double *__restrict__ wrec;
     const Params *P;
-    // Large FP64 instances park the local part of G^{n+1} of the row being
-    // finished in this wavefront's LDS slice between the two node loops instead
-    // of in registers
+    // Large instances (FP64 from 16 nodes per lane, FP32 from 48) park the local
+    // part of G^{n+1} of the row being finished in this wavefront's LDS slice
+    // between the two node loops instead of in registers.  For the FP32 instance
+    // with 48 nodes this is what fits two wavefronts per SIMD (256 VGPRs instead of
+    // 326): the pass went from 2.26 to 1.79-1.84 ms at 512^2 x 48^2
 #ifndef MM_LK_STASH
 #define MM_LK_STASH 1
 #endif
-    static constexpr bool STASH = MM_LK_STASH && sizeof(TC) == 8 && NPT >= 16;
+    static constexpr bool STASH = MM_LK_STASH && ((sizeof(TC) == 8 && NPT >= 16) || NPT >= 48);
 #ifndef MM_LK_WPROJ
 #define MM_LK_WPROJ 1
 #endif
@@ -494,15 +496,16 @@ struct PassLK {
 };
 
 // Occupancy: the FP64 instance with 16 nodes per lane (128 B of G per lane)
-// runs one wavefront per SIMD (measured faster than two); every other instance
-// fits two wavefronts per SIMD.
+// runs one wavefront per SIMD (measured faster than two); every other instance,
+// the FP32 one with 48 nodes per lane included (its window half in LDS), runs
+// two wavefronts per SIMD.
 #ifndef MM_LK_OCC64
 #define MM_LK_OCC64 1
 #endif
 template <typename TC, int NPT>
 struct LKTraits {
     static constexpr bool big = sizeof(TC) * NPT >= 128;   // the same rule picks the launch geometry
-    static constexpr int occupancy = big ? MM_LK_OCC64 : 2;
+    static constexpr int occupancy = big && !(sizeof(TC) == 4 && NPT >= 48) ? MM_LK_OCC64 : 2;
 };
 
 template <typename TS, typename TC, int NPT, bool CL, bool SYM, int ACT>
@@ -858,8 +861,10 @@ bool launch_micro_lk2d(const void *G, void *Gn, double *H, const double *rec, co
 {
     const int act = lk_lanes(P.nv1, P.nv2), npt = lk_npt(P, precision);
     if (npt == 0) return false;
-    // the instances with 128 bytes of g per lane and more run one wavefront per SIMD
-    const bool one_wave = (precision == 0 ? 8 : 4) * npt >= 128 && MM_LK_OCC64 == 1;
+    // the instances with 128 bytes of g per lane and more run one wavefront per SIMD,
+    // except the FP32 one with 48 nodes per lane (see LKTraits)
+    const bool one_wave =
+        (precision == 0 ? 8 : 4) * npt >= 128 && MM_LK_OCC64 == 1 && !(precision != 0 && npt >= 48);
     const Geom geo = geometry(P, one_wave ? 1 : 2);
     if (cls) {   // closure form: g in FP32 only, 64 active lanes
         if (act != 64) return false;
