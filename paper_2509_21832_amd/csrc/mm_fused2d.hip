@@ -368,6 +368,7 @@ bool launch_micro_closure2d(const void *G, void *Gn, double *H, const double *re
 
 bool fused_supported(const Params &P, int precision)
 {
+    if (lk_supported(P, precision)) return true;    // the lane-k pass takes the grid
     if (P.nv1 > MAXV || P.nv2 > MAXV) return false;
     return npt_for(P.nv, precision) != 0;
 }

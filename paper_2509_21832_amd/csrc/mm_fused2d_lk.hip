@@ -634,7 +634,7 @@ bool launch_lk_t(int npt, int act, const void *G, void *Gn, double *H, const dou
             MM_LAUNCH(24, 48);
             return true;
         }
-        if constexpr (sizeof(TC) == 4) {
+        {
             if (npt == 48) {
                 MM_LAUNCH(48, 48);
                 return true;
@@ -797,10 +797,11 @@ static int lk_npt(const Params &P, int precision)
     if ((long long)P.nx * P.nv * 8 >= (1LL << 31)) return 0;
     const int npt = P.nv / A;
     if (A == 64) return (npt == 1 || npt == 2 || npt == 4 || npt == 8 || npt == 16) ? npt : 0;
-    return (npt == 12 || npt == 24 || (npt == 48 && precision != 0)) ? npt : 0;
+    return (npt == 12 || npt == 24 || npt == 48) ? npt : 0;
 }
 
 bool lk_supported(const Params &P) { return lk_lanes(P.nv1, P.nv2) == 64 && lk_npt(P, 0) != 0; }
+bool lk_supported(const Params &P, int precision) { return lk_npt(P, precision) != 0; }
 
 bool launch_wall_lk2d(void *Gn, int g_bytes, double *H, const double *rec, const double *wrec, const Params &P,
                       hipStream_t st)
@@ -836,11 +837,11 @@ bool launch_wall_lk2d(void *Gn, int g_bytes, double *H, const double *rec, const
         MM_LAUNCH(24, 48);
         return true;
     }
-    if (g_bytes == 4) {
+    if (g_bytes == 4)
         hipLaunchKernelGGL((k_wall_lk<float, 48, 48>), grid, block, 0, st, (float *)Gn, H, rec, wrec, P, nring);
-        return true;
-    }
-    return false;
+    else
+        hipLaunchKernelGGL((k_wall_lk<double, 48, 48>), grid, block, 0, st, (double *)Gn, H, rec, wrec, P, nring);
+    return true;
 #undef MM_LAUNCH
 }
 

@@ -301,6 +301,8 @@ inline Geom geometry(const Params &P, int occupancy)
 
 // the lane-k specialisation of the fused pass (mm_fused2d_lk.hip)
 bool lk_supported(const Params &P);
+// the lane-k pass takes this grid at this precision (0 FP64, 1 g in FP32)
+bool lk_supported(const Params &P, int precision);
 // cls: nullptr, or (closure form, g in FP32) the per-cell flags of solved cells
 bool launch_micro_lk2d(const void *G, void *Gn, double *H, const double *rec, const double *wrec,
                        const Params &P, const Params *Pd, int precision, const uint8_t *cls, hipStream_t st);
