@@ -61,7 +61,7 @@ def test_host_logic_under_address_and_undefined_sanitizers(tmp_path):
         r = subprocess.run(cmd, capture_output=True, text=True)
         assert r.returncode == 0, r.stdout[-3000:] + r.stderr[-3000:]
         objs.append(o)
-    # the driver and the link: plain host C++ (no HIP source on these lines)
+    # the host-logic program and the link: plain host C++ (no HIP source on these lines)
     main_o = str(tmp_path / "main.o")
     host_flags = ["-O1", "-g", "-std=c++17", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
                   "-fno-sanitize-recover=undefined"]
