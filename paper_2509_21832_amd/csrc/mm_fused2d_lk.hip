@@ -866,7 +866,12 @@ bool launch_micro_lk2d(const void *G, void *Gn, double *H, const double *rec, co
     // except the FP32 one with 48 nodes per lane (see LKTraits)
     const bool one_wave =
         (precision == 0 ? 8 : 4) * npt >= 128 && MM_LK_OCC64 == 1 && !(precision != 0 && npt >= 48);
-    const Geom geo = geometry(P, one_wave ? 1 : 2);
+    // g in FP32 with 16 nodes per lane: one and a half rounds of workgroups (row
+    // segments of 22 rows at 256^2 x 32^2) measured 5% faster than two (163.5 against
+    // 172.4 us, bitwise the same result); the FP64 instances and the 48-node FP32 one
+    // are fastest at two rounds (FP64 at 256^2 x 32^2: 223 us, 233-291 us at segments
+    // of 28-40 rows; FP32 at 512^2 x 48^2: 1.80 against 1.98 ms at one and a half)
+    const Geom geo = geometry(P, one_wave ? 1 : 2, precision != 0 && npt == 16 ? 6 : 8);
     if (cls) {   // closure form: g in FP32 only, 64 active lanes
         if (act != 64) return false;
         // the solved cells cluster along the walls: short row segments spread a

@@ -280,13 +280,13 @@ __device__ __forceinline__ int tile_of(int b, int ntiles)
     return (b % 8) * per + b / 8;   // >= ntiles for padding workgroups
 }
 
-// Workgroups per launch: about two rounds of (CUs x resident workgroups per CU),
-// with row segments of at least 16 rows.
-inline Geom geometry(const Params &P, int occupancy)
+// Workgroups per launch: about `quarters` / 4 rounds of (CUs x resident
+// workgroups per CU) (two rounds by default), with row segments of at least 16 rows.
+inline Geom geometry(const Params &P, int occupancy, int quarters = 8)
 {
     Geom g;
     g.ncg = (P.nx + WPG - 1) / WPG;
-    const int want = 2 * 256 * occupancy;
+    const int want = quarters * 64 * occupancy;
     const int nseg = (want + g.ncg - 1) / g.ncg;
     int seg = (P.ny + nseg - 1) / nseg;
     if (seg < 16) seg = 16;
